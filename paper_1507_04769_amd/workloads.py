@@ -1,0 +1,88 @@
+"""Seeded synthetic workloads (inputs only; none of the method's arithmetic).
+
+This module is shared by the oracle-side tests and the GPU-side tests, bench
+and smoke check.  It holds the problem parameters of the rigid-body attitude
+workloads, the box in which the sparse grid and the query points live, and
+seeded uniform generators (numpy PCG64).  It never computes a grid, a BVP or
+an interpolant.
+
+The rigid-body model is the gyroscopic simplification of the paper's
+momentum-wheel model (Sec. 5, eq. sat_model): Euler angles in (3,2,1) order,
+J w' = -w x (J w) + B u, running cost 0.5 (q_w x^T x + r_w u^T u) and final
+cost 0.5 p_w x^T x.  The paper samples validation points uniformly at random
+in a box (Sec. 4.3 and 5.1); the query sets here follow that recipe.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+D = 6  # state dimension of the rigid body
+ANGLE_HALF_WIDTH = math.pi / 4
+RATE_HALF_WIDTH = 0.5
+BOX_LO = np.array([-ANGLE_HALF_WIDTH] * 3 + [-RATE_HALF_WIDTH] * 3)
+BOX_HI = -BOX_LO
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    level: int          # sparse-grid level (q = level + d)
+    n_intervals: int    # trapezoidal collocation intervals
+    horizon: float
+    n_queries: int
+    query_seed: int
+    m: int = 3          # number of wheel torques
+
+
+# Plain FP64 path, smallest case: level-2 grid (85 nodes), 64 intervals, 1e3 queries.
+SMALL = Workload("rigid-body-6d-L2-N64-q1e3", level=2, n_intervals=64, horizon=20.0,
+                 n_queries=1000, query_seed=0)
+# Plain FP64 path at scale: level-4 grid (1457 nodes), 256 intervals, 1e6 queries.
+FULL = Workload("rigid-body-6d-L4-N256-q1e6", level=4, n_intervals=256, horizon=20.0,
+                n_queries=1_000_000, query_seed=1)
+
+J_DIAG = (2.0, 3.0, 4.0)
+Q_W, R_W, P_W = 1.0, 0.1, 10.0
+TOL = 1e-10
+MAX_ITER = 20
+
+
+def input_matrix(m: int = 3) -> np.ndarray:
+    """3 x m wheel-torque input matrix: identity for three wheels; for two
+    wheels, seeded orthonormal columns (QR of a PCG64(103) normal draw with
+    the signs fixed so that diag(R) > 0)."""
+    if m == 3:
+        return np.eye(3)
+    if m != 2:
+        raise ValueError("m must be 2 or 3")
+    g = np.random.default_rng(103).standard_normal((3, 2))
+    q, r = np.linalg.qr(g)
+    s = np.sign(np.diag(r))
+    s[s == 0] = 1.0
+    return q * s
+
+
+def uniform_in_box(n: int, seed: int, lo=BOX_LO, hi=BOX_HI) -> np.ndarray:
+    """n points uniform in the box [lo, hi] (n x d), PCG64(seed)."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    u = np.random.default_rng(seed).random((n, lo.size))
+    return lo + (hi - lo) * u
+
+
+def query_points(w: Workload) -> np.ndarray:
+    return uniform_in_box(w.n_queries, w.query_seed)
+
+
+def random_values(n: int, m: int, seed: int) -> np.ndarray:
+    """Seeded standard-normal node values for interpolation tests."""
+    return np.random.default_rng(seed).standard_normal((n, m))
+
+
+def sample_indices(total: int, k: int, seed: int) -> np.ndarray:
+    """k distinct indices of range(total), sorted, PCG64(seed)."""
+    k = min(k, total)
+    return np.sort(np.random.default_rng(seed).choice(total, size=k, replace=False))
