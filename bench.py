@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Benchmark of the sparse grid characteristics method's hot path on one GPU.
+
+One step = the whole hot path on one batch of synthetic input: solve the
+characteristic BVP at every node of the level-4 Smolyak CGL grid of the 6-D
+rigid-body attitude problem (1457 nodes, 256 trapezoidal intervals, Newton
+to max|F| <= 1e-10), build the hierarchical-surplus interpolant of u(0), and
+evaluate the feedback at 1e6 seeded uniform states.  Inputs are resident in
+HBM before the timed region; W untimed warm-up steps, then exactly K timed
+steps bracketed by synchronisation.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload full|small]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "converged 6-D BVPs/s at tol 1e-10 + feedback evals/s; p50/p99 latency"
+PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector (and matrix) peak
+
+# Algorithmic FP64 work of the Newton solve (counted in the design notes):
+#   per interval and linear solve: the 12 x 12 factorisation with 7 right-hand
+#   sides (2/3 n^3 + 2 n^2 k = 1152 + 2016), its assembly (S P, A^T P, S c,
+#   A^T c and the block sums: 768), the forward pass (168) and the update (12);
+#   per mesh point and evaluation: Phi, A = df/dx and W (248) and the interval
+#   residual (48).
+FLOPS_PER_INTERVAL_SOLVE = 1152 + 2016 + 768 + 168 + 12
+FLOPS_PER_POINT_EVAL = 248 + 48
+
+
+def newton_flops(N: int, iters: np.ndarray) -> float:
+    """Algorithmic flops of one sgcm_solve_bvps launch: (iters + 1) linear
+    solves (the first is the linearised step) and (iters + 2) evaluations."""
+    it = iters.astype(np.float64)
+    return float(np.sum((it + 1) * N * FLOPS_PER_INTERVAL_SOLVE + (it + 2) * (N + 1) * FLOPS_PER_POINT_EVAL))
+
+
+def eval_flops_per_query(grid_keys: np.ndarray, level: int, m: int) -> float:
+    """Algorithmic flops of one feedback evaluation: one FMA per node and
+    output (2 m M), the partial products of the node trie, and the 1-D basis
+    tables (prefix/suffix products, 3 flops per point of each X^i, plus one
+    scale per new point) in every dimension."""
+    M, d = grid_keys.shape
+    prefixes = 0
+    for k in range(1, d - 1):
+        prefixes += len({tuple(r) for r in grid_keys[:, :k]})
+    inner = len({tuple(r) for r in grid_keys[:, : d - 1]})
+    basis = 0
+    for i in range(2, level + 2):
+        n = 2 ** (i - 1) + 1
+        basis += 3 * n + 2 * (n // 2 if i > 2 else 2)
+    return 2.0 * m * M + prefixes + 2.0 * m * inner + d * basis
+
+
+def cpu_baseline(args, nodes: np.ndarray, xq: np.ndarray) -> dict:
+    """The FP64 CPU oracle as it stands, on the host cores, on a bounded
+    sample of the same workload: all BVPs of the grid, and a slice of the
+    queries."""
+    from oracle import oracle as O
+    from paper_1507_04769_amd import workloads as W
+    wl = W.FULL if args.workload == "full" else W.SMALL
+    threads = O.default_threads()
+    op = O.Problem(N=wl.n_intervals, T=wl.horizon)
+    t0 = time.perf_counter()
+    r = O.solve_bvps(op, nodes, nthreads=threads)
+    t_solve = time.perf_counter() - t0
+    conv = int(np.sum(r.status == O.CONVERGED))
+    nq = min(len(xq), args.cpu_queries)
+    w = O.build_surplus(6, wl.level, r.u0, nthreads=threads)
+    t0 = time.perf_counter()
+    O.eval_hier(6, wl.level, w, xq[:nq], W.BOX_LO, W.BOX_HI, nthreads=threads)
+    t_eval = time.perf_counter() - t0
+    return {"value": conv / t_solve, "unit": "BVPs/s", "cores": threads, "kind": "oracle",
+            "sample": "all %d BVPs of the grid (N=%d) and %d of the %d queries" % (len(nodes), wl.n_intervals,
+                                                                                nq, len(xq)),
+            "feedback_evals_per_s": nq / t_eval, "solve_s": t_solve, "eval_s": t_eval}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["full", "small"], default="full")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-queries", type=int, default=20000)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the per-node BVPs shard with no communication; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1507_04769_amd as S
+    from paper_1507_04769_amd import workloads as W
+
+    wl = W.FULL if args.workload == "full" else W.SMALL
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    prob = S.Problem(m=wl.m, J=W.J_DIAG, B=W.input_matrix(wl.m), q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W,
+                     T=wl.horizon, N=wl.n_intervals, tol=W.TOL, max_iter=W.MAX_ITER)
+    grid = S.Grid(6, wl.level, W.BOX_LO, W.BOX_HI)
+    nodes = grid.nodes()
+    M = len(grid)
+    xq_host = W.query_points(wl)
+    x0 = torch.tensor(nodes, device=dev)
+    xq = torch.tensor(xq_host, device=dev)
+    lam = torch.empty((M, 6), dtype=torch.float64, device=dev)
+    u0 = torch.empty((M, wl.m), dtype=torch.float64, device=dev)
+    V = torch.empty((M,), dtype=torch.float64, device=dev)
+    traj = torch.empty((M, wl.n_intervals + 1, 12), dtype=torch.float64, device=dev)
+    st = torch.empty((M,), dtype=torch.int32, device=dev)
+    it = torch.empty((M,), dtype=torch.int32, device=dev)
+    ws = torch.empty((S.sgcm_solve_bvps_workspace(prob, M) // 8 + 32,), dtype=torch.float64, device=dev)
+    surplus = torch.empty((M, wl.m), dtype=torch.float64, device=dev)
+    uq = torch.empty((len(xq_host), wl.m), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        S.sgcm_solve_bvps(prob, x0, lam, u0, V, traj, st, it, ws, stream)
+        if ev is not None:
+            ev[1].record(stream)
+        S.sgcm_build_interpolant(grid, u0, surplus, stream)
+        if ev is not None:
+            ev[2].record(stream)
+        S.sgcm_eval_feedback(grid, surplus, xq, uq, S.FP64, stream)
+        if ev is not None:
+            ev[3].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([e[0].elapsed_time(e[3]) for e in events])
+    solve_ms = np.array([e[0].elapsed_time(e[1]) for e in events])
+    build_ms = np.array([e[1].elapsed_time(e[2]) for e in events])
+    eval_ms = np.array([e[2].elapsed_time(e[3]) for e in events])
+
+    status = st.cpu().numpy()
+    iters = it.cpu().numpy()
+    converged = int(np.sum(status == S.CONVERGED))
+    total_s = float(np.sum(step_ms)) / 1e3
+    value = converged * args.steps / total_s
+    flops = newton_flops(wl.n_intervals, iters)
+    achieved = flops / (float(np.mean(solve_ms)) / 1e3) / 1e12
+
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "BVPs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": float(np.mean(step_ms)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid_level": wl.level, "grid_nodes": M, "state_dim": 6,
+                   "controls": wl.m, "intervals": wl.n_intervals, "horizon": wl.horizon, "tol": W.TOL,
+                   "queries": len(xq_host), "query_seed": wl.query_seed},
+        "feedback_evals_per_s": len(xq_host) / (float(np.mean(eval_ms)) / 1e3),
+        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
+        "phases_ms": {"solve_bvps": float(np.mean(solve_ms)), "build_interpolant": float(np.mean(build_ms)),
+                      "eval_feedback": float(np.mean(eval_ms))},
+        "converged": converged,
+        "newton_iters_hist": np.bincount(iters).tolist(),
+        "wall_s_timed": wall,
+        "roofline": {"kernel": "k_newton (sgcm_solve_bvps)", "bound": "alu", "achieved": achieved,
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": None, "algorithmic_flops_per_launch": flops},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args, nodes, xq_host)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * sgcm.h -- C ABI of the MI355X (gfx950) sparse grid characteristics method.
+ *
+ * The method (Kang & Wilcox, "Mitigating the Curse of Dimensionality: Sparse
+ * Grid Characteristics Method for Optimal Feedback Control and HJB
+ * Equations") solves, independently at every node of a Smolyak sparse grid,
+ * the two-point boundary value problem of the characteristics (state and
+ * costate equations, Sec. 3.1, eq. hamchar), builds the hierarchical-surplus
+ * polynomial interpolant of the result on the Clenshaw-Curtis ("CGL") sparse
+ * grid (Sec. 3.2 eq. CGL, Sec. 3.3 eq. interpo), and evaluates the feedback
+ * law at arbitrary states (Sec. 3.3, Steps I-III and the on-line step).
+ *
+ * Conventions for every function:
+ *   - All functions are extern "C", never throw, and return an int status
+ *     (sgcm_err) unless stated otherwise.
+ *   - Arguments are validated before any GPU work is queued; a bad argument
+ *     returns SGCM_EINVAL and queues nothing.  A failed launch or runtime call
+ *     returns SGCM_EDEVICE.
+ *   - Pointers documented as "device" must point to device memory of the
+ *     current HIP device (or be NULL where allowed).  The caller owns every
+ *     device buffer and the stream; the library owns only sgcm_grid objects.
+ *   - Calls on a stream are stream-ordered and do not synchronise the host.
+ *     "stream" is a hipStream_t passed as void*; NULL means the null stream.
+ *   - Arrays are row-major and densely packed unless stated otherwise.
+ */
+#ifndef SGCM_H
+#define SGCM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+typedef enum {
+  SGCM_OK = 0,
+  SGCM_EINVAL = -1,       /* invalid argument (nothing was queued)            */
+  SGCM_ENOMEM = -2,       /* host or device allocation failed                 */
+  SGCM_EDEVICE = -3,      /* HIP launch or runtime failure                    */
+  SGCM_EUNSUPPORTED = -4  /* valid request outside what this build supports   */
+} sgcm_err;
+
+/* Per-BVP outcome written to status[] by sgcm_solve_bvps.  A per-BVP failure
+ * is not a call error: the call still returns SGCM_OK. */
+typedef enum {
+  SGCM_BVP_CONVERGED = 0, /* max|F| <= tol                                    */
+  SGCM_BVP_MAXITER = 1,   /* max_iter Newton iterations without convergence   */
+  SGCM_BVP_SINGULAR = 2,  /* an exactly zero pivot in the Newton linear solve */
+  SGCM_BVP_NONFINITE = 3  /* a NaN or Inf in the collocation residual         */
+} sgcm_bvp_status;
+
+/* Dynamics of the optimal-control problem (Sec. 2).  Both use the state
+ * x = (phi, theta, psi, w1, w2, w3): Euler angles in (3,2,1) order and body
+ * rates (Sec. 5, eq. sat_model with the stored-momentum term replaced by the
+ * gyroscopic term).
+ *   RIGID_BODY:  v' = E(v) w,  J w' = -w x (J w) + B u, with
+ *                E(v) = [[1, s_phi t_th, c_phi t_th], [0, c_phi, -s_phi],
+ *                        [0, s_phi/c_th, c_phi/c_th]].
+ *   LINEARISED:  the same system linearised about x = 0: v' = w, J w' = B u
+ *                (used to pin the solver by the Riccati closed form). */
+typedef enum { SGCM_MODEL_RIGID_BODY = 0, SGCM_MODEL_LINEARISED = 1 } sgcm_model;
+
+typedef enum { SGCM_FP64 = 0, SGCM_FP32 = 1 } sgcm_precision;
+
+/* The optimal-control problem of Sec. 2 and its discretisation.
+ * Cost: integral over [0,T] of 0.5 (q_w x^T x + r_w u^T u) dt
+ *       + 0.5 p_w x(T)^T x(T).
+ * Discretisation: trapezoidal collocation (the two-point Lobatto IIIA
+ * formula) on N uniform intervals of [0, T]; Newton's method from the zero
+ * trajectory; its first step, the solve of the problem linearised about the
+ * origin (the LQR initial guess), is not counted; then at iteration
+ * it = 0, 1, ...: NONFINITE if the residual F is not finite, CONVERGED if
+ * max|F| <= tol, MAXITER if it == max_iter, else a full Newton step. */
+typedef struct sgcm_problem {
+  int32_t model;     /* sgcm_model                                            */
+  int32_t n;         /* state dimension: must be 6                            */
+  int32_t m;         /* number of controls: 1, 2 or 3                         */
+  double J[3];       /* diagonal of the inertia matrix, all > 0               */
+  double B[9];       /* 3 x m input matrix, column-major: B[i + 3*j]          */
+  double q_w;        /* running state weight   (>= 0)                         */
+  double r_w;        /* running control weight (> 0)                          */
+  double p_w;        /* final state weight     (>= 0)                         */
+  double T;          /* horizon (> 0)                                         */
+  int32_t N;         /* number of mesh intervals, 1 <= N <= 65536             */
+  double tol;        /* Newton tolerance on max|F| (>= 0)                     */
+  int32_t max_iter;  /* Newton iterations after the first step, 0..1000       */
+  int32_t precision; /* sgcm_precision of the Newton linear solve; FP64 only  */
+} sgcm_problem;
+
+/* ---- library ------------------------------------------------------------- */
+
+/* Static message for a status code; never NULL. */
+const char* sgcm_strerror(int code);
+
+/* ABI version (major * 10000 + minor * 100 + patch). */
+int sgcm_version(void);
+
+/* ---- characteristic BVP (Sec. 3.1, eq. hamchar and eq. optuv) -------------- */
+
+/* Bytes of device workspace sgcm_solve_bvps needs for n_bvps problems
+ * (written to *bytes).  Returns SGCM_EINVAL for an invalid problem. */
+int sgcm_solve_bvps_workspace(const sgcm_problem* p, int64_t n_bvps, size_t* bytes);
+
+/* Solve the characteristic BVP of eq. hamchar from every initial state:
+ *   x' = (dH/dlambda)^T,  lambda' = -(dH/dx)^T  at u* = argmin_u H,
+ *   x(0) = x0,  lambda(T) = (dh/dx)^T(x(T)),
+ * with H = L + lambda^T f and, for the models here,
+ * u* = -(1/r_w) B^T J^{-1} lambda_w.  Outputs follow eq. optuv at t = 0.
+ *   x0       device, n_bvps x 6 initial states (read only)
+ *   lambda0  device, n_bvps x 6: the costate lambda(0)
+ *   u0       device, n_bvps x m: the feedback u*(0, x0) = u*(x0, lambda(0))
+ *   V        device, n_bvps, or NULL: the cost z(T) + h(x(T)), z integrated
+ *            by the trapezoidal rule on the mesh
+ *   traj     device, n_bvps x (N+1) x 12, or NULL: (x_k, lambda_k), t_k = kT/N
+ *   status   device, n_bvps (sgcm_bvp_status)
+ *   iters    device, n_bvps: Newton iterations after the first step
+ *   workspace, ws_bytes: device scratch of at least
+ *            sgcm_solve_bvps_workspace() bytes, 256-byte aligned; its
+ *            contents on entry are ignored.
+ * n_bvps == 0 is a valid no-op.  Outputs of a non-converged BVP are those of
+ * the last iterate.  The call is stream-ordered on `stream`. */
+int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const double* x0,
+                    double* lambda0, double* u0, double* V, double* traj,
+                    int32_t* status, int32_t* iters, void* workspace,
+                    size_t ws_bytes, void* stream);
+
+/* The right-hand side of eq. hamchar at n_points states y = (x, lambda) and
+ * its Jacobian (the per-mesh-point blocks the Newton solve is built from):
+ *   y     device, n_points x 12
+ *   phi   device, n_points x 12:  [ f(x, u*) ; -(dH/dx)^T(x, lambda, u*) ]
+ *   dphi  device, n_points x 12 x 12 (row-major d phi_i / d y_j), or NULL. */
+int sgcm_characteristic_rhs(const sgcm_problem* p, int64_t n_points, const double* y,
+                            double* phi, double* dphi, void* stream);
+
+/* ---- sparse grid (Sec. 3.2) --------------------------------------------- */
+
+/* Opaque grid: the Smolyak sparse grid G^q = U_{|i| <= q} dX^{i_1} x .. x
+ * dX^{i_d} on the nested CGL (Clenshaw-Curtis) sets of eq. CGL,
+ * X^1 = {1/2}, X^i = {(1 - cos((k-1) pi / 2^{i-1})) / 2 : k = 1..2^{i-1}+1},
+ * with q = level + d, mapped affinely from [0,1]^d to the box [lo, hi].
+ *
+ * Canonical node order (used by every array indexed by node): every 1-D
+ * point has an integer id, numbered by the level at which it first appears
+ * and, within a level, by increasing coordinate (level 1: id 0 = 1/2;
+ * level 2: id 1 = 0, id 2 = 1; level i >= 3: ids 2^{i-2}+1 .. 2^{i-1}).  A
+ * node's key is its tuple of d ids; nodes are sorted lexicographically by key. */
+typedef struct sgcm_grid sgcm_grid;
+
+/* Create the grid (host-side tables only; device copies are made on first
+ * use on each device).  1 <= d <= 8, 0 <= level <= 5, lo[j] < hi[j]. */
+int sgcm_grid_create(int32_t d, int32_t level, const double* lo, const double* hi,
+                     sgcm_grid** out);
+
+/* Number of nodes M, or -1 for a NULL grid. */
+int64_t sgcm_grid_size(const sgcm_grid* g);
+
+/* Host copies of the node coordinates (M x d, box coordinates) and keys
+ * (M x d point ids), canonical order. */
+int sgcm_grid_nodes(const sgcm_grid* g, double* nodes_host);
+int sgcm_grid_keys(const sgcm_grid* g, int32_t* keys_host);
+
+/* Free the grid and its device tables (device tables are freed on the
+ * device they were made on).  NULL is a no-op. */
+void sgcm_grid_destroy(sgcm_grid* g);
+
+/* ---- interpolant (Sec. 3.3, eq. interpo) ----------------------------------- */
+
+/* Hierarchical surpluses of eq. interpo: for levels |i| = d..q in order,
+ * w = f(node) - I^{|i|-1}(f)(node), with the tensor-product Lagrange basis on
+ * X^{i_1} x .. x X^{i_d}.
+ *   values   device, M x m node values f (canonical order), read only
+ *   surplus  device, M x m (canonical order); may not alias values
+ * 1 <= m <= 64. */
+int sgcm_build_interpolant(const sgcm_grid* g, int32_t m, const double* values,
+                           double* surplus, void* stream);
+
+/* The on-line step: evaluate the interpolant I^q(f)(x) = sum over nodes of
+ * w * prod_j a^{i_j}(xi_j) at n_q query states (Sec. 3.3, Step III and the
+ * text after it), xi = (x - lo) / (hi - lo).  Queries outside the box are
+ * evaluated by the same polynomial (no clamping).
+ *   surplus  device, M x m from sgcm_build_interpolant
+ *   xq       device, n_q x d query states
+ *   uq       device, n_q x m results
+ *   precision  SGCM_FP64 (SGCM_FP32 returns SGCM_EUNSUPPORTED in this build)
+ * n_q == 0 is a valid no-op. */
+int sgcm_eval_feedback(const sgcm_grid* g, int32_t m, const double* surplus, int64_t n_q,
+                       const double* xq, double* uq, int32_t precision, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGCM_H */

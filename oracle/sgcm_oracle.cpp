@@ -524,14 +524,28 @@ int newton_solve(const oracle_problem& p, const double* xbar, double* Y, int* it
 // Sparse grid (Sec. 3.2) on the CGL family (eq. CGL).
 // ---------------------------------------------------------------------------
 
-// point k (1-based) of X^i
-double cgl_point(int i, int k) {
+int cgl_size(int i) { return i == 1 ? 1 : (1 << (i - 1)) + 1; }
+
+// point k (1-based) of X^i, eq. CGL: (1 - cos((k-1) pi / 2^{i-1})) / 2
+double cgl_point_formula(int i, int k) {
   if (i == 1) return 0.5;
   const double PI = 3.14159265358979323846;
   double n = std::ldexp(1.0, i - 1);
   return 0.5 * (1.0 - std::cos((k - 1) * PI / n));
 }
-int cgl_size(int i) { return i == 1 ? 1 : (1 << (i - 1)) + 1; }
+
+// the same values, computed once per level (a lookup table of the formula)
+constexpr int kMaxTableLevel = 12;
+double cgl_point(int i, int k) {
+  static const std::vector<std::vector<double>> table = [] {
+    std::vector<std::vector<double>> t(kMaxTableLevel + 1);
+    for (int lev = 1; lev <= kMaxTableLevel; ++lev)
+      for (int kk = 1; kk <= cgl_size(lev); ++kk) t[lev].push_back(cgl_point_formula(lev, kk));
+    return t;
+  }();
+  if (i > kMaxTableLevel) return cgl_point_formula(i, k);
+  return table[i][k - 1];
+}
 
 // The 1-based indices k of the new points dX^i = X^i - X^{i-1} inside X^i.
 // X^{i-1} sits in X^i at the even offsets k-1 (the angle (k-1) pi / 2^{i-1}

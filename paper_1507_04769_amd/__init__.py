@@ -1,0 +1,321 @@
+"""Python binding of libsgcm, the MI355X (gfx950) sparse grid characteristics
+method (Kang & Wilcox): per-node characteristic BVPs (Sec. 3.1), the
+hierarchical sparse-grid interpolant (Sec. 3.2-3.3) and on-line feedback
+evaluation.
+
+This module only marshals arguments: every step runs in the HIP kernels of
+``libsgcm.so`` behind the C ABI of ``include/sgcm.h``.  The functions named
+``sgcm_*`` mirror the C entry points one to one; the few helpers below them
+allocate the outputs with PyTorch (device memory and streams only) and call
+those entry points.  Importing works without the library; the first call
+raises if ``libsgcm.so`` has not been built (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgcm.so")
+
+SGCM_OK, SGCM_EINVAL, SGCM_ENOMEM, SGCM_EDEVICE, SGCM_EUNSUPPORTED = 0, -1, -2, -3, -4
+CONVERGED, MAXITER, SINGULAR, NONFINITE = 0, 1, 2, 3
+MODEL_RIGID_BODY, MODEL_LINEARISED = 0, 1
+FP64, FP32 = 0, 1
+
+# every extern "C" symbol declared in include/sgcm.h
+EXPORTS = ("sgcm_strerror", "sgcm_version", "sgcm_solve_bvps_workspace", "sgcm_solve_bvps",
+           "sgcm_characteristic_rhs", "sgcm_grid_create", "sgcm_grid_size", "sgcm_grid_nodes",
+           "sgcm_grid_keys", "sgcm_grid_destroy", "sgcm_build_interpolant", "sgcm_eval_feedback")
+
+
+class SgcmError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what or "sgcm", strerror(code), code))
+
+
+class _CProblem(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("J", ctypes.c_double * 3), ("B", ctypes.c_double * 9),
+                ("q_w", ctypes.c_double), ("r_w", ctypes.c_double), ("p_w", ctypes.c_double),
+                ("T", ctypes.c_double), ("N", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+@dataclass
+class Problem:
+    """sgcm_problem: the optimal-control problem of Sec. 2 and its mesh."""
+    model: int = MODEL_RIGID_BODY
+    m: int = 3
+    J: tuple = (2.0, 3.0, 4.0)
+    B: np.ndarray = field(default_factory=lambda: np.eye(3))  # 3 x m
+    q_w: float = 1.0
+    r_w: float = 0.1
+    p_w: float = 10.0
+    T: float = 20.0
+    N: int = 64
+    tol: float = 1e-10
+    max_iter: int = 20
+    precision: int = FP64
+    n: int = 6
+
+    def c(self) -> _CProblem:
+        p = _CProblem()
+        p.model, p.n, p.m = int(self.model), int(self.n), int(self.m)
+        for i in range(3):
+            p.J[i] = float(self.J[i])
+        Bm = np.asarray(self.B, dtype=np.float64).reshape(3, -1)
+        flat = np.zeros(9)
+        flat[: Bm.size] = Bm.T.reshape(-1)  # column-major B[i + 3 j]
+        for i in range(9):
+            p.B[i] = float(flat[i])
+        p.q_w, p.r_w, p.p_w, p.T = float(self.q_w), float(self.r_w), float(self.p_w), float(self.T)
+        p.N, p.tol, p.max_iter = int(self.N), float(self.tol), int(self.max_iter)
+        p.precision = int(self.precision)
+        return p
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libsgcm.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libsgcm.so is not built (expected at %s); run "
+                           "`python -m paper_1507_04769_amd.build`" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    P = ctypes.POINTER(_CProblem)
+    sig = {
+        "sgcm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "sgcm_version": (ctypes.c_int, []),
+        "sgcm_solve_bvps_workspace": (ctypes.c_int, [P, i64, ctypes.POINTER(ctypes.c_size_t)]),
+        "sgcm_solve_bvps": (ctypes.c_int, [P, i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
+        "sgcm_characteristic_rhs": (ctypes.c_int, [P, i64, vp, vp, vp, vp]),
+        "sgcm_grid_create": (ctypes.c_int, [i32, i32, vp, vp, ctypes.POINTER(vp)]),
+        "sgcm_grid_size": (i64, [vp]),
+        "sgcm_grid_nodes": (ctypes.c_int, [vp, vp]),
+        "sgcm_grid_keys": (ctypes.c_int, [vp, vp]),
+        "sgcm_grid_destroy": (None, [vp]),
+        "sgcm_build_interpolant": (ctypes.c_int, [vp, i32, vp, vp, vp]),
+        "sgcm_eval_feedback": (ctypes.c_int, [vp, i32, vp, i64, vp, vp, i32, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype, f.argtypes = res, args
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().sgcm_strerror(code).decode()
+    except RuntimeError:
+        return "status %d" % code
+
+
+def _check(rc: int, what: str):
+    if rc != SGCM_OK:
+        raise SgcmError(rc, what)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _ptr(t, dtype=None, name="tensor", numel=None):
+    """Device pointer of a contiguous CUDA tensor (or None); with numel, the
+    tensor must hold at least that many elements (checked on the host so an
+    undersized buffer never reaches a kernel)."""
+    if t is None:
+        return None
+    import torch
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s holds %d elements, needs %d" % (name, t.numel(), numel))
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s must be %s" % (name, dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# C entry points
+# ---------------------------------------------------------------------------
+
+def sgcm_version() -> int:
+    return lib().sgcm_version()
+
+
+def sgcm_solve_bvps_workspace(problem: Problem, n_bvps: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().sgcm_solve_bvps_workspace(ctypes.byref(problem.c()), int(n_bvps), ctypes.byref(out)),
+           "sgcm_solve_bvps_workspace")
+    return int(out.value)
+
+
+def sgcm_solve_bvps(problem: Problem, x0, lambda0, u0, V, traj, status, iters, workspace, stream=None):
+    import torch
+    f64, i32 = torch.float64, torch.int32
+    n = x0.shape[0] if x0 is not None else 0
+    if x0 is not None and (x0.dim() != 2 or x0.shape[1] != 6):
+        raise ValueError("x0 must be n x 6")
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    m, NP = int(problem.m), int(problem.N) + 1
+    rc = lib().sgcm_solve_bvps(ctypes.byref(problem.c()), int(n), _ptr(x0, f64, "x0"),
+                               _ptr(lambda0, f64, "lambda0", 6 * n), _ptr(u0, f64, "u0", m * n),
+                               _ptr(V, f64, "V", n), _ptr(traj, f64, "traj", 12 * NP * n),
+                               _ptr(status, i32, "status", n), _ptr(iters, i32, "iters", n),
+                               _ptr(workspace, None, "workspace"), ctypes.c_size_t(ws_bytes),
+                               _stream(stream))
+    _check(rc, "sgcm_solve_bvps")
+
+
+def sgcm_characteristic_rhs(problem: Problem, y, phi, dphi=None, stream=None):
+    import torch
+    if y.dim() != 2 or y.shape[1] != 12:
+        raise ValueError("y must be n x 12")
+    n = y.shape[0]
+    rc = lib().sgcm_characteristic_rhs(ctypes.byref(problem.c()), int(n), _ptr(y, torch.float64, "y"),
+                                       _ptr(phi, torch.float64, "phi", 12 * n),
+                                       _ptr(dphi, torch.float64, "dphi", 144 * n), _stream(stream))
+    _check(rc, "sgcm_characteristic_rhs")
+
+
+class Grid:
+    """sgcm_grid: the Smolyak CGL sparse grid (Sec. 3.2) owned by libsgcm."""
+
+    def __init__(self, d: int, level: int, lo, hi):
+        lo = np.ascontiguousarray(lo, dtype=np.float64)
+        hi = np.ascontiguousarray(hi, dtype=np.float64)
+        if lo.size != d or hi.size != d:
+            raise ValueError("lo and hi need d entries")
+        h = ctypes.c_void_p()
+        _check(lib().sgcm_grid_create(int(d), int(level), lo.ctypes.data_as(ctypes.c_void_p),
+                                      hi.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)),
+               "sgcm_grid_create")
+        self._h = h
+        self.d, self.level = int(d), int(level)
+        self.lo, self.hi = lo.copy(), hi.copy()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __len__(self):
+        return int(lib().sgcm_grid_size(self._h))
+
+    @property
+    def size(self) -> int:
+        return len(self)
+
+    def nodes(self) -> np.ndarray:
+        out = np.zeros((len(self), self.d))
+        _check(lib().sgcm_grid_nodes(self._h, out.ctypes.data_as(ctypes.c_void_p)), "sgcm_grid_nodes")
+        return out
+
+    def keys(self) -> np.ndarray:
+        out = np.zeros((len(self), self.d), dtype=np.int32)
+        _check(lib().sgcm_grid_keys(self._h, out.ctypes.data_as(ctypes.c_void_p)), "sgcm_grid_keys")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sgcm_grid_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sgcm_build_interpolant(grid: Grid, values, surplus, stream=None):
+    import torch
+    if values.dim() != 2 or values.shape[0] != len(grid):
+        raise ValueError("values must be M x m with M = %d" % len(grid))
+    m = values.shape[1]
+    rc = lib().sgcm_build_interpolant(grid.handle, int(m), _ptr(values, torch.float64, "values"),
+                                      _ptr(surplus, torch.float64, "surplus", len(grid) * m),
+                                      _stream(stream))
+    _check(rc, "sgcm_build_interpolant")
+
+
+def sgcm_eval_feedback(grid: Grid, surplus, xq, uq, precision: int = FP64, stream=None):
+    import torch
+    if surplus.dim() != 2 or surplus.shape[0] != len(grid):
+        raise ValueError("surplus must be M x m with M = %d" % len(grid))
+    if xq.dim() != 2 or xq.shape[1] != grid.d:
+        raise ValueError("xq must be n_q x %d" % grid.d)
+    m, nq = surplus.shape[1], xq.shape[0]
+    rc = lib().sgcm_eval_feedback(grid.handle, int(m), _ptr(surplus, torch.float64, "surplus"),
+                                  int(nq), _ptr(xq, torch.float64, "xq"),
+                                  _ptr(uq, torch.float64, "uq", nq * m), int(precision), _stream(stream))
+    _check(rc, "sgcm_eval_feedback")
+
+
+# ---------------------------------------------------------------------------
+# allocation helpers (outputs allocated with torch; compute in libsgcm)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class BVPSolution:
+    lambda0: "object"
+    u0: "object"
+    V: "object"
+    traj: "object"
+    status: "object"
+    iters: "object"
+
+
+def solve_bvps(problem: Problem, x0, want_traj: bool = False, want_V: bool = True, workspace=None,
+               stream=None) -> BVPSolution:
+    import torch
+    dev = x0.device
+    n = x0.shape[0]
+    lam = torch.empty((n, 6), dtype=torch.float64, device=dev)
+    u0 = torch.empty((n, problem.m), dtype=torch.float64, device=dev)
+    V = torch.empty((n,), dtype=torch.float64, device=dev) if want_V else None
+    traj = torch.empty((n, problem.N + 1, 12), dtype=torch.float64, device=dev) if want_traj else None
+    st = torch.empty((n,), dtype=torch.int32, device=dev)
+    it = torch.empty((n,), dtype=torch.int32, device=dev)
+    if workspace is None:
+        nbytes = sgcm_solve_bvps_workspace(problem, n)
+        workspace = torch.empty((max(nbytes, 256) + 255) // 256 * 32, dtype=torch.float64, device=dev)
+    sgcm_solve_bvps(problem, x0, lam, u0, V, traj, st, it, workspace, stream)
+    return BVPSolution(lam, u0, V, traj, st, it)
+
+
+def characteristic_rhs(problem: Problem, y, jacobian: bool = True, stream=None):
+    import torch
+    phi = torch.empty_like(y)
+    dphi = torch.empty((y.shape[0], 12, 12), dtype=torch.float64, device=y.device) if jacobian else None
+    sgcm_characteristic_rhs(problem, y, phi, dphi, stream)
+    return phi, dphi
+
+
+def build_interpolant(grid: Grid, values, stream=None):
+    import torch
+    surplus = torch.empty_like(values)
+    sgcm_build_interpolant(grid, values, surplus, stream)
+    return surplus
+
+
+def eval_feedback(grid: Grid, surplus, xq, precision: int = FP64, stream=None):
+    import torch
+    uq = torch.empty((xq.shape[0], surplus.shape[1]), dtype=torch.float64, device=xq.device)
+    sgcm_eval_feedback(grid, surplus, xq, uq, precision, stream)
+    return uq

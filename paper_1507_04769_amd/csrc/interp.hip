@@ -1,0 +1,385 @@
+// Sparse-grid interpolant on gfx950: hierarchical surpluses (Sec. 3.3,
+// eq. interpo) and the on-line evaluation of the feedback interpolant.
+//
+// Both kernels share one device routine: the sum over sparse-grid nodes of
+// w(node) * prod_k a^{i_k}(xi_k).  The nodes are stored in lexicographic order
+// of their point-id keys, with 1-D point ids ordered by level, so the node set
+// is a trie whose children at every depth form a contiguous id range
+// [0, points_upto(budget)).  One lane owns one evaluation point; every lane
+// walks the same trie with the same (uniform) control flow, so the surplus
+// table is read through scalar loads and multiplied into per-lane partial
+// products:
+//     acc += p_{d-2} * sum_{e} b_{d-1}[e] * w[base + e],
+//     p_k = p_{k-1} * b_k[e_k]  at every trie node.
+// The 1-D basis values b_k[e] (Lagrange polynomials on X^i for the new points
+// of level i, Sec. 3.3) are built once per lane by prefix/suffix products over
+// X^i: the innermost dimension lives in registers, the outer ones in LDS laid
+// out [dim][point][lane] so that every LDS access is lane-private and
+// conflict free.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+
+#include "sgcm_internal.h"
+
+namespace sgcm {
+namespace {
+
+struct GridArgs {
+  int d, L, P;
+  const int32_t* excess;  // P
+  const int32_t* off;     // child offsets [(r-1)*(L+1) + b][P]
+  const double* X;        // finest 1-D set X^{L+1} (P points)
+  const double* scale;    // P Lagrange scale factors
+  double lo[kMaxDim], inv_width[kMaxDim];
+};
+
+__host__ __device__ constexpr int upto(int b) { return b <= 0 ? 1 : (1 << b) + 1; }
+
+// Lagrange basis values of the new points of level I (2 <= I <= L+1) at xi,
+// from prefix and suffix products of (xi - x_s) over X^I.
+template <int L, int I>
+__device__ __forceinline__ void level_basis(const GridArgs& g, double xi, double (&out)[kMaxPoints]) {
+  if constexpr (I <= L + 1) {
+    constexpr int n = (1 << (I - 1)) + 1;
+    constexpr int stride = 1 << (L + 1 - I);
+    // suffix products suf[s] = prod_{s' > s} (xi - x_s'), then one forward
+    // sweep with a running prefix product
+    double suf[n];
+    suf[n - 1] = 1.0;
+#pragma unroll
+    for (int s = n - 2; s >= 0; --s) suf[s] = suf[s + 1] * (xi - g.X[(s + 1) * stride]);
+    double pre = 1.0;
+#pragma unroll
+    for (int s = 0; s < n; ++s) {
+      if constexpr (I == 2) {
+        if (s != 1) out[1 + s / 2] = pre * suf[s] * g.scale[1 + s / 2];
+      } else {
+        if (s & 1) {
+          constexpr int base = (1 << (I - 2)) + 1;
+          out[base + s / 2] = pre * suf[s] * g.scale[base + s / 2];
+        }
+      }
+      pre *= xi - g.X[s * stride];
+    }
+    level_basis<L, I + 1>(g, xi, out);
+  }
+}
+
+template <int L>
+__device__ __forceinline__ void basis_row_l(const GridArgs& g, double xi, double (&out)[kMaxPoints]) {
+  out[0] = 1.0;
+  level_basis<L, 2>(g, xi, out);
+}
+
+__device__ __forceinline__ void basis_row(const GridArgs& g, double xi, double (&out)[kMaxPoints]) {
+  switch (g.L) {
+    case 0: basis_row_l<0>(g, xi, out); break;
+    case 1: basis_row_l<1>(g, xi, out); break;
+    case 2: basis_row_l<2>(g, xi, out); break;
+    case 3: basis_row_l<3>(g, xi, out); break;
+    case 4: basis_row_l<4>(g, xi, out); break;
+    default: basis_row_l<5>(g, xi, out); break;
+  }
+}
+
+// Walk the trie below depth K.  bL: excess budget of the storage layout (the
+// full grid), bE: excess budget of the nodes summed (bE <= bL; a smaller bE
+// evaluates a coarser interpolant I^{q'} with the same surplus table).
+template <int K, int D, int MC>
+__device__ __forceinline__ void walk(const GridArgs& g, const double* __restrict__ w, int m,
+                                     int col0, int bL, int bE, int64_t base, double p,
+                                     double (&acc)[MC], const double (&bin)[kMaxPoints],
+                                     const double* lds_lane) {
+  if constexpr (K == D - 1) {
+    const int cE = upto(bE);
+    const double* wb = w + base * m + col0;
+    double t[MC];
+#pragma unroll
+    for (int c = 0; c < MC; ++c) t[c] = 0.0;
+#pragma unroll
+    for (int e = 0; e < kMaxPoints; ++e) {
+      if (e < cE) {
+#pragma unroll
+        for (int c = 0; c < MC; ++c) t[c] = fma(bin[e], wb[(int64_t)e * m + c], t[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < MC; ++c) acc[c] = fma(p, t[c], acc[c]);
+  } else {
+    const int cE = upto(bE);
+    const int32_t* offrow = g.off + ((D - K - 1) * (g.L + 1) + bL) * g.P;
+    for (int e = 0; e < cE; ++e) {
+      const int ex = g.excess[e];
+      const double pk = (K == 0) ? lds_lane[(K * g.P + e) * 64] : p * lds_lane[(K * g.P + e) * 64];
+      walk<K + 1, D, MC>(g, w, m, col0, bL - ex, bE - ex, base + offrow[e], pk, acc, bin, lds_lane);
+    }
+  }
+}
+
+// Basis tables of one lane at xi[0..D-1]: dims 0..D-2 to LDS, dim D-1 to bin.
+template <int D>
+__device__ __forceinline__ void lane_tables(const GridArgs& g, const double (&xi)[D], double* lds_lane,
+                                            double (&bin)[kMaxPoints]) {
+  double row[kMaxPoints];
+#pragma unroll
+  for (int k = 0; k < D - 1; ++k) {
+    basis_row(g, xi[k], row);
+#pragma unroll
+    for (int e = 0; e < kMaxPoints; ++e)
+      if (e < g.P) lds_lane[(k * g.P + e) * 64] = row[e];
+  }
+  basis_row(g, xi[D - 1], bin);
+}
+
+template <int D, int MC>
+__global__ __launch_bounds__(64) void k_eval(GridArgs g, const double* __restrict__ w, int m, int col0,
+                                             int64_t nq, const double* __restrict__ xq,
+                                             double* __restrict__ uq) {
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x;
+  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+  const bool active = q < nq;
+  double xi[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) xi[k] = active ? (xq[q * D + k] - g.lo[k]) * g.inv_width[k] : 0.5;
+  double bin[kMaxPoints];
+  double* lds_lane = lds + lane;
+  lane_tables<D>(g, xi, lds_lane, bin);
+  double acc[MC];
+#pragma unroll
+  for (int c = 0; c < MC; ++c) acc[c] = 0.0;
+  walk<0, D, MC>(g, w, m, col0, g.L, g.L, 0, 1.0, acc, bin, lds_lane);
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < MC; ++c) uq[q * m + col0 + c] = acc[c];
+  }
+}
+
+template <int D, int MC>
+__global__ __launch_bounds__(64) void k_surplus_level(GridArgs g, const double* __restrict__ f,
+                                                      double* w, int m, int col0, int lv,
+                                                      const int32_t* __restrict__ nodes, int64_t count,
+                                                      const double* __restrict__ node_xi) {
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const bool active = i < count;
+  const int64_t node = active ? nodes[i] : 0;
+  double xi[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) xi[k] = node_xi[node * D + k];
+  double bin[kMaxPoints];
+  double* lds_lane = lds + lane;
+  lane_tables<D>(g, xi, lds_lane, bin);
+  double acc[MC];
+#pragma unroll
+  for (int c = 0; c < MC; ++c) acc[c] = 0.0;
+  if (lv > 0) walk<0, D, MC>(g, w, m, col0, g.L, lv - 1, 0, 1.0, acc, bin, lds_lane);
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < MC; ++c) w[node * m + col0 + c] = f[node * m + col0 + c] - acc[c];
+  }
+}
+
+// ---- host side -------------------------------------------------------------
+
+int ensure_device_tables(Grid& G, int dev) {
+  std::lock_guard<std::mutex> lock(G.mu);
+  GridDevice& gd = G.dev[dev];
+  if (gd.ready) return SGCM_OK;
+  auto up = [](void** dst, const void* src, size_t bytes) -> bool {
+    if (bytes == 0) bytes = 8;
+    if (hipMalloc(dst, bytes) != hipSuccess) return false;
+    return src == nullptr || hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  bool ok = up((void**)&gd.node_xi, G.xi.data(), G.xi.size() * sizeof(double)) &&
+            up((void**)&gd.by_level, G.by_level.data(), G.by_level.size() * sizeof(int32_t)) &&
+            up((void**)&gd.tables, G.itab.data(), G.itab.size() * sizeof(int32_t)) &&
+            up((void**)&gd.dtab, G.dtab.data(), G.dtab.size() * sizeof(double));
+  if (!ok) {
+    hipFree(gd.node_xi);
+    hipFree(gd.by_level);
+    hipFree(gd.tables);
+    hipFree(gd.dtab);
+    gd = GridDevice();
+    return SGCM_ENOMEM;
+  }
+  gd.ready = true;
+  return SGCM_OK;
+}
+
+GridArgs make_args(const Grid& G, const GridDevice& gd) {
+  GridArgs a;
+  a.d = G.d;
+  a.L = G.level;
+  a.P = G.P;
+  a.excess = gd.tables;
+  a.off = gd.tables + G.itab_off;
+  a.X = gd.dtab;
+  a.scale = gd.dtab + G.P;
+  for (int k = 0; k < kMaxDim; ++k) {
+    a.lo[k] = k < G.d ? G.lo[k] : 0.0;
+    a.inv_width[k] = k < G.d ? G.inv_width[k] : 0.0;
+  }
+  return a;
+}
+
+size_t lds_bytes(const Grid& G) { return (size_t)(G.d - 1) * G.P * 64 * sizeof(double); }
+
+template <int D, int MC>
+hipError_t launch_eval(const GridArgs& a, size_t lds, const double* w, int m, int col0, int64_t nq,
+                       const double* xq, double* uq, hipStream_t s) {
+  auto kern = k_eval<D, MC>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t blocks = (nq + 63) / 64;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64), lds, s, a, w, m, col0, nq, xq, uq);
+  return hipGetLastError();
+}
+
+template <int D, int MC>
+hipError_t launch_level(const GridArgs& a, size_t lds, const double* f, double* w, int m, int col0,
+                        int lv, const int32_t* nodes, int64_t count, const double* node_xi,
+                        hipStream_t s) {
+  auto kern = k_surplus_level<D, MC>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t blocks = (count + 63) / 64;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64), lds, s, a, f, w, m, col0, lv, nodes,
+                     count, node_xi);
+  return hipGetLastError();
+}
+
+template <int D>
+hipError_t dispatch_mc_eval(int mc, const GridArgs& a, size_t lds, const double* w, int m, int col0,
+                            int64_t nq, const double* xq, double* uq, hipStream_t s) {
+  switch (mc) {
+    case 1: return launch_eval<D, 1>(a, lds, w, m, col0, nq, xq, uq, s);
+    case 2: return launch_eval<D, 2>(a, lds, w, m, col0, nq, xq, uq, s);
+    default: return launch_eval<D, 3>(a, lds, w, m, col0, nq, xq, uq, s);
+  }
+}
+
+template <int D>
+hipError_t dispatch_mc_level(int mc, const GridArgs& a, size_t lds, const double* f, double* w, int m,
+                             int col0, int lv, const int32_t* nodes, int64_t count,
+                             const double* node_xi, hipStream_t s) {
+  switch (mc) {
+    case 1: return launch_level<D, 1>(a, lds, f, w, m, col0, lv, nodes, count, node_xi, s);
+    case 2: return launch_level<D, 2>(a, lds, f, w, m, col0, lv, nodes, count, node_xi, s);
+    default: return launch_level<D, 3>(a, lds, f, w, m, col0, lv, nodes, count, node_xi, s);
+  }
+}
+
+#define SGCM_DIM_SWITCH(d, CALL) \
+  switch (d) {                   \
+    case 1: return CALL(1);      \
+    case 2: return CALL(2);      \
+    case 3: return CALL(3);      \
+    case 4: return CALL(4);      \
+    case 5: return CALL(5);      \
+    case 6: return CALL(6);      \
+    case 7: return CALL(7);      \
+    default: return CALL(8);     \
+  }
+
+hipError_t eval_chunk(int d, int mc, const GridArgs& a, size_t lds, const double* w, int m, int col0,
+                      int64_t nq, const double* xq, double* uq, hipStream_t s) {
+#define CALL_EVAL(D) dispatch_mc_eval<D>(mc, a, lds, w, m, col0, nq, xq, uq, s)
+  SGCM_DIM_SWITCH(d, CALL_EVAL)
+#undef CALL_EVAL
+}
+
+hipError_t level_chunk(int d, int mc, const GridArgs& a, size_t lds, const double* f, double* w, int m,
+                       int col0, int lv, const int32_t* nodes, int64_t count, const double* node_xi,
+                       hipStream_t s) {
+#define CALL_LEVEL(D) dispatch_mc_level<D>(mc, a, lds, f, w, m, col0, lv, nodes, count, node_xi, s)
+  SGCM_DIM_SWITCH(d, CALL_LEVEL)
+#undef CALL_LEVEL
+}
+
+int current_device(int* dev) {
+  if (hipGetDevice(dev) != hipSuccess) return SGCM_EDEVICE;
+  if (*dev < 0 || *dev >= kMaxDevices) return SGCM_EUNSUPPORTED;
+  return SGCM_OK;
+}
+
+}  // namespace
+
+void free_device_tables(Grid& G) {
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) cur = -1;
+  for (int dv = 0; dv < kMaxDevices; ++dv) {
+    GridDevice& gd = G.dev[dv];
+    if (!gd.ready) continue;
+    if (hipSetDevice(dv) == hipSuccess) {
+      hipFree(gd.node_xi);
+      hipFree(gd.by_level);
+      hipFree(gd.tables);
+      hipFree(gd.dtab);
+    }
+    gd = GridDevice();
+  }
+  if (cur >= 0) hipSetDevice(cur);
+}
+
+}  // namespace sgcm
+
+using namespace sgcm;
+
+extern "C" int sgcm_build_interpolant(const sgcm_grid* gh, int32_t m, const double* values,
+                                      double* surplus, void* stream) {
+  if (!gh || m < 1 || m > 64 || !values || !surplus || values == surplus) return SGCM_EINVAL;
+  Grid& G = const_cast<Grid&>(gh->g);
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc != SGCM_OK) return rc;
+  rc = ensure_device_tables(G, dev);
+  if (rc != SGCM_OK) return rc;
+  const GridDevice& gd = G.dev[dev];
+  GridArgs a = make_args(G, gd);
+  const size_t lds = lds_bytes(G);
+  hipStream_t s = (hipStream_t)stream;
+  for (int lv = 0; lv <= G.level; ++lv) {
+    const int64_t start = G.level_start[lv], count = G.level_start[lv + 1] - start;
+    if (count == 0) continue;
+    for (int col0 = 0; col0 < m; col0 += 3) {
+      const int mc = (m - col0) < 3 ? (m - col0) : 3;
+      hipError_t e = level_chunk(G.d, mc, a, lds, values, surplus, m, col0, lv, gd.by_level + start,
+                                 count, gd.node_xi, s);
+      if (e != hipSuccess) return SGCM_EDEVICE;
+    }
+  }
+  return SGCM_OK;
+}
+
+extern "C" int sgcm_eval_feedback(const sgcm_grid* gh, int32_t m, const double* surplus, int64_t n_q,
+                                  const double* xq, double* uq, int32_t precision, void* stream) {
+  if (!gh || m < 1 || m > 64 || n_q < 0) return SGCM_EINVAL;
+  if (precision != SGCM_FP64 && precision != SGCM_FP32) return SGCM_EINVAL;
+  if (precision != SGCM_FP64) return SGCM_EUNSUPPORTED;
+  if (n_q == 0) return SGCM_OK;
+  if (!surplus || !xq || !uq) return SGCM_EINVAL;
+  if ((n_q + 63) / 64 > 0x7fffffffLL) return SGCM_EUNSUPPORTED;
+  Grid& G = const_cast<Grid&>(gh->g);
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc != SGCM_OK) return rc;
+  rc = ensure_device_tables(G, dev);
+  if (rc != SGCM_OK) return rc;
+  GridArgs a = make_args(G, G.dev[dev]);
+  const size_t lds = lds_bytes(G);
+  hipStream_t s = (hipStream_t)stream;
+  for (int col0 = 0; col0 < m; col0 += 3) {
+    const int mc = (m - col0) < 3 ? (m - col0) : 3;
+    if (eval_chunk(G.d, mc, a, lds, surplus, m, col0, n_q, xq, uq, s) != hipSuccess) return SGCM_EDEVICE;
+  }
+  return SGCM_OK;
+}

@@ -1,0 +1,130 @@
+"""GPU parity of the sparse-grid interpolant (Sec. 3.3) against the oracle.
+
+Surpluses (eq. interpo) and evaluated values within 1e-8 relative of the
+oracle (in practice ~1e-13); inputs are seeded node values and seeded
+uniform query points in (and around) the box.
+"""
+import numpy as np
+import pytest
+
+import paper_1507_04769_amd as S
+from oracle import oracle as O
+from paper_1507_04769_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+REL = 1e-8
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def box(d):
+    lo = -0.4 - 0.1 * np.arange(d)
+    hi = 0.6 + 0.2 * np.arange(d)
+    return lo, hi
+
+
+def dev(a):
+    torch = _torch()
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+CASES = [(1, 0), (1, 5), (2, 3), (3, 4), (4, 1), (6, 2), (6, 4), (6, 5), (8, 2)]
+
+
+@pytest.mark.parametrize("d,level", CASES)
+@pytest.mark.parametrize("m", [1, 3, 4])
+def test_surplus_and_eval_parity(d, level, m):
+    torch = _torch()
+    lo, hi = box(d)
+    g = S.Grid(d, level, lo, hi)
+    M = len(g)
+    vals = W.random_values(M, m, seed=200 + 10 * d + level)
+    w_gpu = S.build_interpolant(g, dev(vals))
+    w_ref = O.build_surplus(d, level, vals)
+    torch.cuda.synchronize()
+    w_gpu = w_gpu.cpu().numpy()
+    assert np.max(np.abs(w_gpu - w_ref)) <= REL * np.abs(w_ref).max()
+    # queries: inside the box, plus a few outside (same polynomial, no clamping)
+    rng = np.random.default_rng(300 + d)
+    xq = lo + (hi - lo) * rng.uniform(-0.1, 1.1, (777, d))
+    u_gpu = S.eval_feedback(g, dev(w_gpu), dev(xq)).cpu().numpy()
+    u_ref = O.eval_hier(d, level, w_ref, xq, lo, hi)
+    assert np.max(np.abs(u_gpu - u_ref)) <= REL * max(1.0, np.abs(u_ref).max())
+
+
+@pytest.mark.parametrize("d,level", [(2, 5), (6, 3)])
+def test_eval_reproduces_node_values(d, level):
+    lo, hi = box(d)
+    g = S.Grid(d, level, lo, hi)
+    vals = W.random_values(len(g), 3, seed=7)
+    w = S.build_interpolant(g, dev(vals))
+    u = S.eval_feedback(g, w, dev(g.nodes())).cpu().numpy()
+    assert np.max(np.abs(u - vals)) <= 1e-12 * np.abs(vals).max() * 10
+
+
+@pytest.mark.parametrize("nq", [0, 1, 63, 64, 65, 1000])
+def test_ragged_query_counts(nq):
+    torch = _torch()
+    g = S.Grid(6, 2, W.BOX_LO, W.BOX_HI)
+    vals = W.random_values(len(g), 3, seed=8)
+    w_ref = O.build_surplus(6, 2, vals)
+    xq = W.uniform_in_box(nq, seed=9)
+    u = S.eval_feedback(g, dev(w_ref), dev(xq.reshape(nq, 6)))
+    torch.cuda.synchronize()
+    if nq:
+        ref = O.eval_hier(6, 2, w_ref, xq, W.BOX_LO, W.BOX_HI)
+        assert np.max(np.abs(u.cpu().numpy() - ref)) <= REL * max(1.0, np.abs(ref).max())
+
+
+def test_full_size_feedback_eval():
+    # level-4 grid, 1e6 seeded queries: all on the GPU, a seeded sample on
+    # the oracle
+    torch = _torch()
+    w = W.FULL
+    g = S.Grid(6, w.level, W.BOX_LO, W.BOX_HI)
+    vals = W.random_values(len(g), 3, seed=10)
+    w_ref = O.build_surplus(6, w.level, vals)
+    xq = W.query_points(w)
+    u = S.eval_feedback(g, dev(w_ref), dev(xq))
+    torch.cuda.synchronize()
+    u = u.cpu().numpy()
+    assert np.all(np.isfinite(u))
+    idx = W.sample_indices(len(xq), 400, seed=11)
+    idx = np.unique(np.concatenate([idx, [0, len(xq) - 1]]))
+    ref = O.eval_hier(6, w.level, w_ref, xq[idx], W.BOX_LO, W.BOX_HI)
+    assert np.max(np.abs(u[idx] - ref)) <= REL * max(1.0, np.abs(ref).max())
+
+
+def test_pipeline_small_workload():
+    # grid -> BVPs -> surpluses of u(0) -> feedback at 1e3 queries, each side
+    # running its own pipeline
+    torch = _torch()
+    wl = W.SMALL
+    gp = S.Problem(N=wl.n_intervals, T=wl.horizon)
+    op = O.Problem(N=wl.n_intervals, T=wl.horizon)
+    g = S.Grid(6, wl.level, W.BOX_LO, W.BOX_HI)
+    sol = S.solve_bvps(g_prob := gp, dev(g.nodes()))
+    assert int((sol.status != 0).sum()) == 0
+    w_gpu = S.build_interpolant(g, sol.u0)
+    xq = W.query_points(wl)
+    u_gpu = S.eval_feedback(g, w_gpu, dev(xq)).cpu().numpy()
+    og = O.grid(6, wl.level, W.BOX_LO, W.BOX_HI)
+    o = O.solve_bvps(op, og.nodes)
+    w_ref = O.build_surplus(6, wl.level, o.u0)
+    u_ref = O.eval_hier(6, wl.level, w_ref, xq, W.BOX_LO, W.BOX_HI)
+    del g_prob
+    assert np.max(np.abs(u_gpu - u_ref)) <= REL * np.abs(u_ref).max()
+
+
+def test_eval_deterministic():
+    torch = _torch()
+    g = S.Grid(6, 4, W.BOX_LO, W.BOX_HI)
+    w = dev(W.random_values(len(g), 3, seed=12))
+    xq = dev(W.uniform_in_box(5000, seed=13))
+    a = S.eval_feedback(g, w, xq)
+    b = S.eval_feedback(g, w, xq)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
