@@ -27,14 +27,16 @@ sys.path.insert(0, ROOT)
 METRIC = "converged 6-D BVPs/s at tol 1e-10 + feedback evals/s; p50/p99 latency"
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector (and matrix) peak
 
-# Algorithmic FP64 work of the Newton solve (counted in the design notes):
-#   per interval and linear solve: the 12 x 12 factorisation with 7 right-hand
-#   sides (2/3 n^3 + 2 n^2 k = 1152 + 2016), its assembly (S P, A^T P, S c,
-#   A^T c and the block sums: 768), the forward pass (168) and the update (12);
-#   per mesh point and evaluation: Phi, A = df/dx and W (248) and the interval
-#   residual (48).
-FLOPS_PER_INTERVAL_SOLVE = 1152 + 2016 + 768 + 168 + 12
-FLOPS_PER_POINT_EVAL = 248 + 48
+# Algorithmic FP64 work of the Newton solve (the counts are derived in the
+# design notes):
+#   per interval and linear solve: assembly of the 12 x 12 system and its
+#   7 right-hand sides (S P_k, A_k^T P_k, S c_k, A_k^T c_k and the block sums:
+#   1098), the solve itself counted as LU plus substitution (2/3 n^3 + 2 n^2 k
+#   = 1152 + 2016 for n = 12, k = 7) and the forward pass with the update (156);
+#   per mesh point and evaluation: Phi, A = df/dx and W (172) and the interval
+#   residual (48).  Transcendentals (two sincos per point) are not counted.
+FLOPS_PER_INTERVAL_SOLVE = 1098 + 1152 + 2016 + 156
+FLOPS_PER_POINT_EVAL = 172 + 48
 
 
 def newton_flops(N: int, iters: np.ndarray) -> float:

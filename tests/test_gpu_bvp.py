@@ -95,11 +95,15 @@ def test_linear_model_parity_and_riccati():
 
 
 def test_underactuated_short_horizon_parity():
-    gp, op = problems(m=2, N=48, T=3.0)
-    x0 = 0.5 * W.uniform_in_box(32, seed=111)
+    # Two wheels (seeded orthonormal B): the linearisation is not stabilisable
+    # and undamped Newton from the linearised step diverges for large states
+    # or long horizons (the iterates then are chaotic and not comparable), so
+    # parity is checked where the oracle converges everywhere: 0.3 x box, T = 2.
+    gp, op = problems(m=2, N=40, T=2.0)
+    x0 = 0.3 * W.uniform_in_box(64, seed=111)
     o = O.solve_bvps(op, x0, want_traj=True)
     g = gpu_solve(gp, x0)
-    assert np.mean(o.status == O.CONVERGED) > 0.9
+    assert np.all(o.status == O.CONVERGED)
     assert_parity(g, o)
 
 
