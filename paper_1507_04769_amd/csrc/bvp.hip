@@ -3,20 +3,40 @@
 // One 64-lane workgroup (one wavefront) owns one BVP.  The discretisation is
 // trapezoidal collocation on N uniform intervals; the unknowns are
 // y_k = (x_k, lambda_k), k = 0..N, and the residual is
-//   F = [ x_0 - xbar ; r_k = y_k - y_{k-1} - (h/2)(Phi_{k-1} + Phi_k), k=1..N ;
-//         lambda_N - p_w x_N ],
+//   F = [ x_0 - xbar ; r_k = y_k - y_{k-1} - a (Phi_{k-1} + Phi_k), k=1..N ;
+//         lambda_N - p_w x_N ],   a = h/2,
 // with Phi = [ f(x, u*) ; -q_w x - A^T lambda ], A = df/dx, u* = argmin_u H.
 // Newton's linear system is block bidiagonal:
-//   (I - (h/2) Phi'_k) dy_k = (I + (h/2) Phi'_{k-1}) dy_{k-1} - r_k,
+//   (I - a Phi'_k) dy_k = (I + a Phi'_{k-1}) dy_{k-1} - r_k,
 //   Phi' = [[A, -S], [W, -A^T]],  S = (1/r_w) Bt Bt^T,  W = -q_w I - sum_i lambda_i f_i''.
-// It is solved by a backward Riccati sweep: with dlambda_k = P_k dx_k + c_k
-// (P_N = p_w I, c_N = -F_N) each interval gives a 12 x 12 system for
-// (dx_k, dlambda_{k-1}) in terms of dx_{k-1}, solved by Gauss-Jordan with row
-// partial pivoting cooperatively by the 64 lanes in LDS; its solution rows
-// are dx_k = G_k dx_{k-1} + g_k and dlambda_{k-1} = P_{k-1} dx_{k-1} + c_{k-1}.
-// A forward pass from dx_0 = -F_0 recovers the step.  Mesh-point work
-// (Phi, A, W) and the residual are lane-parallel over k.
+//
+// Linear solve: a backward Riccati sweep dlambda_k = P_k dx_k + c_k from
+// P_N = p_w I, c_N = -F_N.  The controls act on the body rates only, so S has
+// rank <= 3 and lives in the rate block; eliminating dlambda_{k-1} with
+// D^{-1} = (I - a A_{k-1}^T)^{-1} and dx_k with L_k = (I - a A_k)^{-1} leaves,
+// on the serial path, one 3 x 3 system per interval (a Woodbury-type step):
+//   EM1 = F P_k - H,  Psi = P_k + EM1,
+//   Z3  = I + S_w Psi_w B_k,   [M | m] = Z3^{-1} S_w [Psi_w R_k - Gam_w | Psi_w rho + phi_w],
+//   P_{k-1} = (EM1 R_k - Gam) - (EM1 B_k) M,   c_{k-1} = EM1 rho - (EM1 B_k) m + F c_k + D^{-1} r^l,
+//   G_k = R_k - B_k M,  g_k = rho - B_k m   (dx_k = G_k dx_{k-1} + g_k),
+// with F = D^{-1}(I + a A_k^T), H = a D^{-1} W_k, Gam = a D^{-1} W_{k-1},
+// R_k = L_k (I + a A_{k-1}), B_k = a L_k[:, rates], rho = -L_k r^x,
+// phi = (I + F) c_k + D^{-1} r^l.  D and I - a A_k are block triangular (the
+// rates do not depend on the angles), so L_k comes from two 3 x 3 inverses and
+// D^{-1} = L_{k-1}^T.
+//
+// Per-point blocks (A, W, L) are derived in batches of 8 points into an LDS
+// ring ahead of the sweep (the trigonometric factors come from the residual
+// pass); each interval is four LDS-synchronised stages (interval products,
+// then three chain stages), each of which issues all of its LDS reads before
+// its first product.  The interval solutions [G_k g_k ; P_{k-1} c_{k-1}] go
+// to global memory and come back, staged through LDS 8 intervals at a time
+// with a register prefetch, for the forward pass dx_0 = -F_0,
+// dx_k = G_k dx_{k-1} + g_k, dlambda_{k-1} = P_{k-1} dx_{k-1} + c_{k-1}.
+// Mesh-point work and the residual are lane-parallel over k.
 #include <hip/hip_runtime.h>
+
+#include <cstddef>
 
 #include "sgcm_internal.h"
 
@@ -33,11 +53,10 @@ struct BvpArgs {
   int64_t per_bvp;  // doubles of workspace per BVP
 };
 
-constexpr int kRows = 12, kCols = 19, kLd = 20;
-
 // Phi, A = df/dx and W = -q I - Hessian_x(lambda^T f) at one mesh point.
 __device__ __forceinline__ void point_eval(const BvpArgs& P, const double* __restrict__ y,
-                                           double (&phi)[12], double (&A)[36], double (&W)[36]) {
+                                           double (&phi)[12], double (&A)[36], double (&W)[36],
+                                           double* trig = nullptr) {
   const double w1 = y[3], w2 = y[4], w3 = y[5];
   const double l1 = y[6], l2 = y[7], l3 = y[8], l4 = y[9], l5 = y[10], l6 = y[11];
 #pragma unroll
@@ -55,6 +74,12 @@ __device__ __forceinline__ void point_eval(const BvpArgs& P, const double* __res
     sincos(y[0], &s, &c);
     sincos(y[1], &st, &ct);
     const double k = 1.0 / ct, t = st * k;
+    if (trig) {
+      trig[0] = s;
+      trig[1] = c;
+      trig[2] = t;
+      trig[3] = k;
+    }
     const double al = s * w2 + c * w3;  // phi-rotated rates
     const double be = c * w2 - s * w3;  // d al / d phi
     f[0] = w1 + t * al;
@@ -138,209 +163,556 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(64) void k_newton(BvpArgs P, const double* __restrict__ x0,
+// Inverse of a 3 x 3 matrix (row-major) by the adjugate; returns the
+// determinant (0 means singular; out is then not finite).
+__device__ __forceinline__ double inv3(const double (&m)[9], double (&out)[9]) {
+  const double c00 = m[4] * m[8] - m[5] * m[7];
+  const double c01 = m[5] * m[6] - m[3] * m[8];
+  const double c02 = m[3] * m[7] - m[4] * m[6];
+  const double det = m[0] * c00 + m[1] * c01 + m[2] * c02;
+  const double r = 1.0 / det;
+  out[0] = c00 * r;
+  out[1] = (m[2] * m[7] - m[1] * m[8]) * r;
+  out[2] = (m[1] * m[5] - m[2] * m[4]) * r;
+  out[3] = c01 * r;
+  out[4] = (m[0] * m[8] - m[2] * m[6]) * r;
+  out[5] = (m[2] * m[3] - m[0] * m[5]) * r;
+  out[6] = c02 * r;
+  out[7] = (m[1] * m[6] - m[0] * m[7]) * r;
+  out[8] = (m[0] * m[4] - m[1] * m[3]) * r;
+  return det;
+}
+
+// The Newton kernel runs one wavefront per workgroup.  LDS operations of a
+// wavefront are executed in program order, so lanes exchange data through LDS
+// with only a wait on the LDS counter and a compiler barrier (no s_barrier and,
+// unlike a workgroup barrier with its release fence, no wait for outstanding
+// global loads and stores: prefetches stay in flight).  Global-memory hand-offs
+// between lanes (a few per Newton iteration) wait for the vector memory counter.
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void wave_mem_sync() { asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory"); }
+// The lane id as a value the compiler cannot prove loop invariant: index
+// arithmetic derived from it is then recomputed where it is used instead of
+// being hoisted out of the Newton and sweep loops, where it would hold
+// registers for the whole kernel.
+__device__ __forceinline__ int opaque_lane(int lane) {
+  asm volatile("" : "+v"(lane));
+  return lane;
+}
+
+constexpr int kRing = 16;    // point slots in the LDS ring (power of two)
+constexpr int kBatch = 8;    // points derived per refill
+constexpr int kSlot = 120;   // per point: A (36), W (36), L (36), r_k (12)
+constexpr int kChunk = 8;    // intervals staged per forward-pass chunk
+constexpr int kZRow = 8;     // padded row of a staged interval solution
+constexpr int kZInt = 12 * kZRow;
+constexpr int kZPer = (kChunk * 84 + 63) / 64;  // prefetch registers per lane
+
+struct SweepShared {
+  union {
+    double ring[kRing * kSlot];
+    double zst[kChunk * kZInt];
+    double pa[2 * 64 * 12];  // phase A: Phi and y of one 64-point chunk
+  } u;
+  double carry_phi[12], carry_y[12];
+  double F[36], H[36], Gam[36], Rk[36], rho[6], Dr[6];
+  double Pt[36], c[6];  // P_k column-major (Pt[j*6+m] = P[m][j]), c_k
+  double EM1[36], Psi[18], phi[6], phic[6];
+  double T1[9], T2[18], t3[3];
+  double X1[36], X2[18], X3[6];
+  double dx[2][8];
+  double zsw[kBatch * 84];               // interval solutions of the last kBatch steps
+  double dxs[kChunk * 6], dls[kChunk * 6]; // forward pass: dx and dlambda of one chunk
+  double F0[6], FN[6], xb[6];
+  double zero[2];  // a zero operand for uniform (branch-free) stage code
+  int flag;
+};
+
+// Flat double offsets into SweepShared: the sweep stages address LDS as one
+// array so that every lane runs the same instructions with per-lane offsets.
+#define SGCM_OFF(field) ((int)(offsetof(SweepShared, field) / sizeof(double)))
+
+// A = df/dx, W and L = (I - a A)^{-1} of one mesh point into an LDS slot
+// (row-major 6 x 6 each).  Entries are stored as soon as they are formed so
+// that few values stay live; the structural zeros of A and W are written too.
+__device__ __forceinline__ void point_blocks(const BvpArgs& P, const double (&y)[12], const double (&tr)[4],
+                                             double* slot, int* flag) {
+  const double w1 = y[3], w2 = y[4], w3 = y[5];
+  const double l1 = y[6], l2 = y[7], l3 = y[8], l4 = y[9], l5 = y[10], l6 = y[11];
+  double* A = slot;
+  double* W = slot + 36;
+  double* L = slot + 72;
+#pragma unroll
+  for (int e = 0; e < 36; ++e) {
+    A[e] = 0.0;
+    W[e] = 0.0;
+  }
+  // the entries of A that the inverse needs: angle block (A00 A01 A10 A20 A21),
+  // kinematic coupling E = A[0:3, 3:6], rate block Omega = A[3:6, 3:6]
+  double a00 = 0.0, a01 = 0.0, a10 = 0.0, a20 = 0.0, a21 = 0.0;
+  double E[9], Om[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    E[e] = 0.0;
+    Om[e] = 0.0;
+  }
+  if (P.model == SGCM_MODEL_RIGID_BODY) {
+    const double s = tr[0], c = tr[1], t = tr[2], k = tr[3];
+    const double al = s * w2 + c * w3;
+    const double be = c * w2 - s * w3;
+    a00 = t * be;
+    a01 = k * k * al;
+    a10 = -al;
+    a20 = k * be;
+    a21 = k * t * al;
+    E[0] = 1.0; E[1] = t * s; E[2] = t * c;
+    E[3] = 0.0; E[4] = c;     E[5] = -s;
+    E[6] = 0.0; E[7] = k * s; E[8] = k * c;
+    Om[1] = P.a[0] * w3; Om[2] = P.a[0] * w2;
+    Om[3] = P.a[1] * w3; Om[5] = P.a[1] * w1;
+    Om[6] = P.a[2] * w2; Om[7] = P.a[2] * w1;
+    const double Pc = l1 * t + l3 * k;
+    const double Pt = l1 * k * k + l3 * k * t;
+    const double Ptt = 2.0 * l1 * k * k * t + l3 * k * (t * t + k * k);
+    W[0 * 6 + 0] = Pc * al + l2 * be - P.q;
+    W[0 * 6 + 1] = W[1 * 6 + 0] = -Pt * be;
+    W[0 * 6 + 4] = W[4 * 6 + 0] = l2 * s - Pc * c;
+    W[0 * 6 + 5] = W[5 * 6 + 0] = Pc * s + l2 * c;
+    W[1 * 6 + 1] = -Ptt * al - P.q;
+    W[1 * 6 + 4] = W[4 * 6 + 1] = -Pt * s;
+    W[1 * 6 + 5] = W[5 * 6 + 1] = -Pt * c;
+    W[3 * 6 + 4] = W[4 * 6 + 3] = -l6 * P.a[2];
+    W[3 * 6 + 5] = W[5 * 6 + 3] = -l5 * P.a[1];
+    W[4 * 6 + 5] = W[5 * 6 + 4] = -l4 * P.a[0];
+    W[2 * 6 + 2] = W[3 * 6 + 3] = W[4 * 6 + 4] = W[5 * 6 + 5] = -P.q;
+  } else {
+    E[0] = E[4] = E[8] = 1.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) W[i * 6 + i] = -P.q;
+  }
+  A[0 * 6 + 0] = a00;
+  A[0 * 6 + 1] = a01;
+  A[1 * 6 + 0] = a10;
+  A[2 * 6 + 0] = a20;
+  A[2 * 6 + 1] = a21;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      A[i * 6 + 3 + j] = E[i * 3 + j];
+      A[(3 + i) * 6 + 3 + j] = Om[i * 3 + j];
+    }
+  const double a = P.alpha;
+  double M1[9] = {1.0 - a * a00, -a * a01, 0.0, -a * a10, 1.0, 0.0, -a * a20, -a * a21, 1.0};
+  double M2[9], Xb[9], Yb[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) M2[e] = ((e % 4) == 0 ? 1.0 : 0.0) - a * Om[e];
+  const double d1 = inv3(M1, Xb);
+  const double d2 = inv3(M2, Yb);
+  if (d1 == 0.0 || d2 == 0.0) *flag = 1;
+  // L = [[Xb, Xb (a E) Yb], [0, Yb]]
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double xe[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      xe[j] = a * (Xb[i * 3 + 0] * E[0 * 3 + j] + Xb[i * 3 + 1] * E[1 * 3 + j] + Xb[i * 3 + 2] * E[2 * 3 + j]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      L[i * 6 + j] = Xb[i * 3 + j];
+      L[i * 6 + 3 + j] = xe[0] * Yb[0 * 3 + j] + xe[1] * Yb[1 * 3 + j] + xe[2] * Yb[2 * 3 + j];
+      L[(3 + i) * 6 + j] = 0.0;
+      L[(3 + i) * 6 + 3 + j] = Yb[i * 3 + j];
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_newton(BvpArgs P, const double* __restrict__ x0,
                                                double* __restrict__ lam0, double* __restrict__ u0,
                                                double* __restrict__ Vout, double* __restrict__ traj,
                                                int32_t* __restrict__ status, int32_t* __restrict__ iters,
                                                double* __restrict__ ws) {
-  const int lane = threadIdx.x;
+  const int lane0 = threadIdx.x;
+  const int lane = lane0;
   const int64_t b = blockIdx.x;
   const int N = P.N, NP = N + 1;
   const double alpha = P.alpha;
-  double* Y = ws + b * P.per_bvp;        // NP x 12
-  double* PD = Y + 12 * (int64_t)NP;     // 84 x NP: Phi (12), A (36), W (36), by component
-  double* R = PD + 84 * (int64_t)NP;     // NP x 12: row 0 = [F_0, F_N], row k = r_k
-  double* Z = R + 12 * (int64_t)NP;      // N x 84: solution rows of interval k at (k-1)*84
+  double* Y = ws + b * P.per_bvp;      // NP x 12: the iterate
+  double* R = Y + 12 * (int64_t)NP;    // NP x 12: residuals (row 0 = [F_0, F_N]), then the step
+  double* TR = R + 12 * (int64_t)NP;   // NP x 4: sin phi, cos phi, tan theta, sec theta
+  double* Zg = TR + 4 * (int64_t)NP;   // N x 84: interval solutions, row-major 12 x 7
 
-  __shared__ double Ka[kRows][kLd];
-  __shared__ double AW[2][72];  // [0] = A_k, W_k   [1] = A_{k-1}, W_{k-1}
-  __shared__ double Pc[6][7];   // P_k | c_k
-  __shared__ double rk[12];
-  __shared__ double dx[6];
-  __shared__ double xb[6];
-  __shared__ int prow[12];
-
-  if (lane < 6) xb[lane] = x0[b * 6 + lane];
+  __shared__ SweepShared sh;
+  if (lane < 6) sh.xb[lane] = x0[b * 6 + lane];
+  if (lane < 2) sh.zero[lane] = 0.0;
   for (int i = lane; i < 12 * NP; i += 64) Y[i] = 0.0;
-  __syncthreads();
+  wave_mem_sync();
 
   int it = -1, st = SGCM_BVP_MAXITER;
   while (true) {
-    // ---- mesh points: Phi, A, W ----
-    for (int k = lane; k < NP; k += 64) {
-      double phi[12], A[36], W[36];
-      point_eval(P, Y + 12 * (int64_t)k, phi, A, W);
-#pragma unroll
-      for (int c = 0; c < 12; ++c) PD[c * (int64_t)NP + k] = phi[c];
-#pragma unroll
-      for (int c = 0; c < 36; ++c) {
-        PD[(12 + c) * (int64_t)NP + k] = A[c];
-        PD[(48 + c) * (int64_t)NP + k] = W[c];
-      }
-    }
-    __syncthreads();
-    // ---- residual and its max norm ----
+    // ---- residual F(Y) and its max norm (lane-parallel over mesh points) ----
     double lmax = 0.0;
     int bad = 0;
-    for (int k = lane; k < NP; k += 64) {
-      double v[12];
-      if (k == 0) {
+    for (int base = 0; base < NP; base += 64) {
+      const int lane = opaque_lane(lane0);
+      const int k = base + lane;
+      const bool valid = k < NP;
+      double yk[12], ph[12];
+      if (valid) {
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
-          v[i] = Y[i] - xb[i];
-          v[6 + i] = Y[12 * (int64_t)N + 6 + i] - P.pw * Y[12 * (int64_t)N + i];
+        for (int i = 0; i < 12; ++i) yk[i] = Y[12 * (int64_t)k + i];
+        double A[36], W[36], tr[4] = {0.0, 0.0, 0.0, 0.0};
+        point_eval(P, yk, ph, A, W, tr);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) TR[4 * (int64_t)k + i] = tr[i];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+          sh.u.pa[lane * 12 + i] = ph[i];
+          sh.u.pa[768 + lane * 12 + i] = yk[i];
         }
-      } else {
-#pragma unroll
-        for (int i = 0; i < 12; ++i)
-          v[i] = Y[12 * (int64_t)k + i] - Y[12 * (int64_t)(k - 1) + i] -
-                 alpha * (PD[i * (int64_t)NP + k - 1] + PD[i * (int64_t)NP + k]);
       }
+      wave_lds_sync();
+      if (valid) {
+        if (k == 0) {
 #pragma unroll
-      for (int i = 0; i < 12; ++i) {
-        R[12 * (int64_t)k + i] = v[i];
-        bad |= !isfinite(v[i]);
-        lmax = fmax(lmax, fabs(v[i]));
+          for (int i = 0; i < 6; ++i) {
+            const double v = yk[i] - sh.xb[i];
+            R[i] = v;
+            bad |= !isfinite(v);
+            lmax = fmax(lmax, fabs(v));
+          }
+        } else {
+          const double* pp = lane > 0 ? &sh.u.pa[(lane - 1) * 12] : sh.carry_phi;
+          const double* yp = lane > 0 ? &sh.u.pa[768 + (lane - 1) * 12] : sh.carry_y;
+#pragma unroll
+          for (int i = 0; i < 12; ++i) {
+            const double v = yk[i] - yp[i] - alpha * (pp[i] + ph[i]);
+            R[12 * (int64_t)k + i] = v;
+            bad |= !isfinite(v);
+            lmax = fmax(lmax, fabs(v));
+          }
+        }
+        if (k == N) {
+#pragma unroll
+          for (int i = 0; i < 6; ++i) {
+            const double v = yk[6 + i] - P.pw * yk[i];
+            R[6 + i] = v;
+            bad |= !isfinite(v);
+            lmax = fmax(lmax, fabs(v));
+          }
+        }
       }
+      wave_lds_sync();
+      if (lane == 63 && valid) {
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+          sh.carry_phi[i] = ph[i];
+          sh.carry_y[i] = yk[i];
+        }
+      }
+      wave_lds_sync();
     }
+    wave_mem_sync();  // residuals R visible to every lane
     const bool nonfinite = __any(bad);
     lmax = wave_max(lmax);
-    __syncthreads();
     if (it >= 0) {
       if (nonfinite) { st = SGCM_BVP_NONFINITE; break; }
       if (lmax <= P.tol) { st = SGCM_BVP_CONVERGED; break; }
       if (it == P.max_iter) { st = SGCM_BVP_MAXITER; break; }
     }
+
     // ---- backward Riccati sweep ----
-    if (lane < 42) {
-      const int i = lane / 7, c = lane % 7;
-      Pc[i][c] = (c < 6) ? ((i == c) ? P.pw : 0.0) : -R[6 + i];
+    if (lane < 6) {
+      sh.F0[lane] = R[lane];
+      sh.FN[lane] = R[6 + lane];
+      sh.c[lane] = -R[6 + lane];
     }
+    if (lane < 36) {
+      const int j = lane / 6, m = lane % 6;
+      sh.Pt[lane] = (j == m) ? P.pw : 0.0;
+    }
+    if (lane == 0) sh.flag = 0;
+    int pf_lo = N + 1;  // lowest point already in the ring
+    int zhi = N;        // highest interval staged in zsw and not yet written out
+    // write the staged interval solutions of intervals [klo, zhi] to global memory
+    auto flush_z = [&](int klo) {
+      const int lane = opaque_lane(lane0);
+      const int cnt = (zhi - klo + 1) * 84;
+      for (int e = lane; e < cnt; e += 64) {
+        const int kk = klo + e / 84, r = e % 84;
+        Zg[(int64_t)(kk - 1) * 84 + r] = sh.zsw[(kk & (kBatch - 1)) * 84 + r];
+      }
+      zhi = klo - 1;
+    };
+    wave_lds_sync();
     bool singular = false;
     for (int k = N; k >= 1; --k) {
-      for (int e = lane; e < 144; e += 64) {
-        const int slot = e / 72, c = e % 72;
-        AW[slot][c] = PD[(12 + c) * (int64_t)NP + (k - slot)];
-      }
-      if (lane < 12) rk[lane] = R[12 * (int64_t)k + lane];
-      __syncthreads();
-      const double* A0 = AW[0];
-      const double* W0 = AW[0] + 36;
-      const double* A1 = AW[1];
-      const double* W1 = AW[1] + 36;
-      for (int e = lane; e < kRows * kCols; e += 64) {
-        const int r = e / kCols, c = e % kCols;
-        double v;
-        if (r < 6) {
-          if (c < 6) {
-            v = (r == c ? 1.0 : 0.0) - alpha * A0[r * 6 + c];
-            for (int mm = 3; mm < 6; ++mm) v += alpha * S_at(P, r, mm) * Pc[mm][c];
-          } else if (c < 12) {
-            v = alpha * S_at(P, r, c - 6);
-          } else if (c < 18) {
-            v = (r == c - 12 ? 1.0 : 0.0) + alpha * A1[r * 6 + (c - 12)];
-          } else {
-            v = -rk[r];
-            for (int mm = 3; mm < 6; ++mm) v -= alpha * S_at(P, r, mm) * Pc[mm][6];
+      if (k - 1 < pf_lo) {
+        // refill the ring with points [lo, hi]: issue the loads first, then
+        // write out the staged solutions, so that the wait for the loads does
+        // not include the stores
+        const int lane = opaque_lane(lane0);
+        const int hi = pf_lo - 1;
+        const int lo = hi - (kBatch - 1) < 0 ? 0 : hi - (kBatch - 1);
+        const int p = lo + lane;
+        double py[12], pr[12], pt[4];
+        if (lane < kBatch && p <= hi) {
+          const int64_t pp = p >= 1 ? p : 1;  // r_0 does not exist; row 0 holds F_0, F_N
+#pragma unroll
+          for (int i = 0; i < 12; ++i) {
+            py[i] = Y[12 * (int64_t)p + i];
+            pr[i] = R[12 * pp + i];
           }
-        } else {
-          const int i = r - 6;
-          if (c < 6) {
-            v = Pc[i][c] - alpha * W0[i * 6 + c];
-            for (int mm = 0; mm < 6; ++mm) v += alpha * A0[mm * 6 + i] * Pc[mm][c];
-          } else if (c < 12) {
-            const int j = c - 6;
-            v = -((i == j ? 1.0 : 0.0) - alpha * A1[j * 6 + i]);
-          } else if (c < 18) {
-            v = alpha * W1[i * 6 + (c - 12)];
-          } else {
-            v = -rk[6 + i] - Pc[i][6];
-            for (int mm = 0; mm < 6; ++mm) v -= alpha * A0[mm * 6 + i] * Pc[mm][6];
-          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) pt[i] = TR[4 * (int64_t)p + i];
         }
-        Ka[r][c] = v;
-      }
-      __syncthreads();
-      // Gauss-Jordan with row partial pivoting (first index of the largest |a|)
-      unsigned used = 0;
-      for (int j = 0; j < 12; ++j) {
-        int p = -1;
-        double best = 0.0;
-        for (int r = 0; r < 12; ++r) {
-          if ((used >> r) & 1u) continue;
-          const double a = fabs(Ka[r][j]);
-          if (a > best) {
-            best = a;
-            p = r;
-          }
+        if (zhi > k) flush_z(k + 1);
+        if (lane < kBatch && p <= hi) {
+          double* slot = sh.u.ring + (p & (kRing - 1)) * kSlot;
+#pragma unroll
+          for (int i = 0; i < 12; ++i) slot[108 + i] = pr[i];
+          point_blocks(P, py, pt, slot, &sh.flag);
         }
-        if (p < 0) {
+        pf_lo = lo;
+        wave_lds_sync();
+        if (sh.flag) {
           singular = true;
           break;
         }
-        used |= 1u << p;
-        if (lane == 0) prow[j] = p;
-        const double inv = 1.0 / Ka[p][j];
-        double av[4], mv[4], pv[4];
+      }
+      double* const Bs = reinterpret_cast<double*>(&sh);
+      const int ra = ((k - 1) & (kRing - 1)) * kSlot;  // point k-1 in the ring
+      const int rb = (k & (kRing - 1)) * kSlot;        // point k
+      // stage 0: interval products (independent of P_k).  Lane (i, j):
+      //   F = L_a^T (I + a A_b^T), H = a L_a^T W_b, Gam = a L_a^T W_a share
+      //   column i of L_a; R_k = L_b (I + a A_a); lanes j = 0, 1 also form
+      //   rho = -L_b r^x and D^{-1} r^l = L_a^T r^l.
+      if (opaque_lane(lane0) < 36) {
+        const int lane = opaque_lane(lane0);
+        const int i = lane / 6, j = lane % 6;
+        const int r5 = rb + 108 + (j == 0 ? 0 : 6);
+        // every LDS read of the stage is issued before the first product, so
+        // the stage waits for LDS once
+        double la[6], lb[6], ab[6], wb[6], wa[6], aa[6], rv[6];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int e = lane + 64 * t;
-          const int r = e / kCols, c = e % kCols;
-          if (e < kRows * kCols && c > j) {
-            av[t] = Ka[r][c];
-            mv[t] = Ka[r][j];
-            pv[t] = Ka[p][c];
+        for (int m = 0; m < 6; ++m) {
+          la[m] = Bs[ra + 72 + m * 6 + i];
+          lb[m] = Bs[rb + 72 + i * 6 + m];
+          ab[m] = Bs[rb + j * 6 + m];
+          wb[m] = Bs[rb + 36 + m * 6 + j];
+          wa[m] = Bs[ra + 36 + m * 6 + j];
+          aa[m] = Bs[ra + m * 6 + j];
+          rv[m] = Bs[r5 + m];
+        }
+        const double cF = Bs[ra + 72 + j * 6 + i], cR = Bs[rb + 72 + i * 6 + j];
+        __builtin_amdgcn_sched_barrier(0);
+        double sF = 0.0, sH = 0.0, sG = 0.0, sR = 0.0, s5 = 0.0;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+          sF = fma(la[m], ab[m], sF);
+          sH = fma(la[m], wb[m], sH);
+          sG = fma(la[m], wa[m], sG);
+          sR = fma(lb[m], aa[m], sR);
+          s5 = fma(j == 0 ? lb[m] : la[m], rv[m], s5);
+        }
+        sh.F[lane] = fma(alpha, sF, cF);
+        sh.H[lane] = alpha * sH;
+        sh.Gam[lane] = alpha * sG;
+        sh.Rk[lane] = fma(alpha, sR, cR);
+        if (j == 0) sh.rho[i] = -s5;
+        if (j == 1) sh.Dr[i] = s5;
+      }
+      wave_lds_sync();
+      // stage 1: EM1 = F P_k - H; Psi_w = (P_k + EM1) rate rows; lanes j = 0:
+      // phic = F c_k + D^{-1} r^l and phi = c_k + phic
+      if (opaque_lane(lane0) < 36) {
+        const int lane = opaque_lane(lane0);
+        const int i = lane / 6, j = lane % 6;
+        double f[6], pt[6], cc[6];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+          f[m] = sh.F[i * 6 + m];
+          pt[m] = sh.Pt[j * 6 + m];
+          cc[m] = sh.c[m];
+        }
+        const double h = sh.H[lane], dr = sh.Dr[i], pji = sh.Pt[j * 6 + i], ci = sh.c[i];
+        __builtin_amdgcn_sched_barrier(0);
+        double e = -h, q = dr;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+          e = fma(f[m], pt[m], e);
+          q = fma(f[m], cc[m], q);
+        }
+        sh.EM1[lane] = e;
+        if (i >= 3) sh.Psi[(i - 3) * 6 + j] = pji + e;
+        if (j == 0) {
+          sh.phic[i] = q;
+          sh.phi[i] = q + ci;
+        }
+      }
+      wave_lds_sync();
+      // stage 2: rows r = 0..2 are Psi_w rows -> T2 = Psi_w R_k - Gam_w,
+      // T1 = Psi_w B_k, t3 = Psi_w rho + phi_w; rows r = 3..8 are EM1 rows ->
+      // X1 = EM1 R_k - Gam, X2 = EM1 B_k, X3 = EM1 rho.  Column o = 0..5: R_k
+      // column, 6..8: B_k column (a L_b rate columns), 9: rho.  Each lane forms
+      // two outputs of one row.
+      if (opaque_lane(lane0) < 45) {
+        const int lane = opaque_lane(lane0);
+        const int r = lane / 5, o0 = 2 * (lane % 5);
+        const int lrow = (r < 3) ? SGCM_OFF(Psi) + r * 6 : SGCM_OFF(EM1) + (r - 3) * 6;
+        const int grow = (r < 3) ? 3 + r : r - 3;
+        double lv[6], rc[2][6], cv[2], coef[2], csgn[2];
+        int dst[2];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) lv[m] = Bs[lrow + m];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int o = o0 + h;
+          const int rbase = (o < 6) ? SGCM_OFF(Rk) + o : (o < 9) ? rb + 72 + 3 + (o - 6) : SGCM_OFF(rho);
+          const int rs = (o < 9) ? 6 : 1;
+          const int cidx = (o < 6) ? SGCM_OFF(Gam) + grow * 6 + o
+                                   : (o == 9 && r < 3) ? SGCM_OFF(phi) + 3 + r : SGCM_OFF(zero);
+          csgn[h] = (o < 6) ? -1.0 : 1.0;
+          coef[h] = (o >= 6 && o < 9) ? alpha : 1.0;
+          dst[h] = (r < 3) ? ((o < 6) ? SGCM_OFF(T2) + r * 6 + o
+                                      : (o < 9) ? SGCM_OFF(T1) + r * 3 + (o - 6) : SGCM_OFF(t3) + r)
+                           : ((o < 6) ? SGCM_OFF(X1) + (r - 3) * 6 + o
+                                      : (o < 9) ? SGCM_OFF(X2) + (r - 3) * 3 + (o - 6)
+                                                : SGCM_OFF(X3) + (r - 3));
+#pragma unroll
+          for (int m = 0; m < 6; ++m) rc[h][m] = Bs[rbase + m * rs];
+          cv[h] = Bs[cidx];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          double acc = 0.0;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) acc = fma(lv[m], rc[h][m], acc);
+          Bs[dst[h]] = fma(coef[h], acc, csgn[h] * cv[h]);
+        }
+      }
+      wave_lds_sync();
+      // stage 3: Z3 = I + S_w T1 and its inverse (every lane), then lane (i, j):
+      // M = Z3^{-1} S_w [T2 | t3], P_{k-1} = X1 - X2 M, c_{k-1} = X3 + phic - X2 m,
+      // G_k = R_k - B_k M, g_k = rho - B_k m
+      {
+        const int lane = opaque_lane(lane0);
+        const int ll = lane < 42 ? lane : 41;
+        const int i = ll / 7, j = ll % 7;
+        const bool col = j < 6;
+        double t1[9], v[3], x2[3], lb[3];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) t1[e] = sh.T1[e];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          v[m] = Bs[col ? SGCM_OFF(T2) + m * 6 + j : SGCM_OFF(t3) + m];
+          x2[m] = sh.X2[i * 3 + m];
+          lb[m] = Bs[rb + 72 + i * 6 + 3 + m];
+        }
+        const double p0 = Bs[col ? SGCM_OFF(X1) + i * 6 + j : SGCM_OFF(X3) + i];
+        const double p1 = Bs[col ? SGCM_OFF(zero) : SGCM_OFF(phic) + i];
+        const double g0 = Bs[col ? SGCM_OFF(Rk) + i * 6 + j : SGCM_OFF(rho) + i];
+        __builtin_amdgcn_sched_barrier(0);
+        double Z3[9], Zi[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            double t = (a == c) ? 1.0 : 0.0;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) t = fma(P.Sw[a * 3 + m], t1[m * 3 + c], t);
+            Z3[a * 3 + c] = t;
           }
-        }
-        __syncthreads();
+        const double det = inv3(Z3, Zi);
+        if (det == 0.0) singular = true;
+        if (lane < 42 && !singular) {
+          double w[3], mu[3];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int e = lane + 64 * t;
-          const int r = e / kCols, c = e % kCols;
-          if (e < kRows * kCols && c > j) Ka[r][c] = (r == p) ? av[t] * inv : av[t] - mv[t] * inv * pv[t];
+          for (int a = 0; a < 3; ++a) w[a] = P.Sw[a * 3 + 0] * v[0] + P.Sw[a * 3 + 1] * v[1] + P.Sw[a * 3 + 2] * v[2];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) mu[a] = Zi[a * 3 + 0] * w[0] + Zi[a * 3 + 1] * w[1] + Zi[a * 3 + 2] * w[2];
+          double pn = p0 + p1;
+          double gn = g0;
+#pragma unroll
+          for (int m = 0; m < 3; ++m) {
+            pn = fma(-x2[m], mu[m], pn);
+            gn = fma(-alpha * lb[m], mu[m], gn);
+          }
+          Bs[col ? SGCM_OFF(Pt) + j * 6 + i : SGCM_OFF(c) + i] = pn;
+          double* zk = sh.zsw + (k & (kBatch - 1)) * 84;
+          zk[i * 7 + j] = gn;
+          zk[(6 + i) * 7 + j] = pn;
         }
-        __syncthreads();
       }
+      wave_lds_sync();
       if (singular) break;
-      for (int e = lane; e < 84; e += 64) {
-        const int j = e / 7, c = e % 7;
-        const double v = Ka[prow[j]][12 + c];
-        Z[(int64_t)(k - 1) * 84 + e] = v;
-        if (j >= 6) Pc[j - 6][c] = v;
-      }
-      __syncthreads();
     }
     if (singular) {
       st = SGCM_BVP_SINGULAR;
       if (it < 0) it = 0;
       break;
     }
-    // ---- forward pass and update ----
+    if (zhi >= 1) flush_z(1);
+
+    // ---- forward pass; the step goes into R ----
+    wave_mem_sync();  // interval solutions Z visible to every lane
     if (lane < 6) {
-      const double d = -R[lane];
-      dx[lane] = d;
-      Y[lane] += d;
+      const double d = -sh.F0[lane];
+      sh.dx[0][lane] = d;
+      R[lane] = d;
     }
-    __syncthreads();
-    for (int k = 1; k <= N; ++k) {
-      double v = 0.0;
-      if (lane < 12) {
-        const double* zr = Z + (int64_t)(k - 1) * 84 + lane * 7;
-        v = zr[6];
+    double zr[kZPer];
+    auto zload = [&](int c0) {
+      const int lane = opaque_lane(lane0);
 #pragma unroll
-        for (int j = 0; j < 6; ++j) v += zr[j] * dx[j];
+      for (int t = 0; t < kZPer; ++t) {
+        const int e = lane + 64 * t;
+        if (e < kChunk * 84 && c0 + e / 84 <= N) zr[t] = Zg[(int64_t)(c0 - 1) * 84 + e];
       }
-      __syncthreads();
-      if (lane < 6) {
-        dx[lane] = v;
-        Y[12 * (int64_t)k + lane] += v;
-      } else if (lane < 12) {
-        Y[12 * (int64_t)(k - 1) + lane] += v;  // dlambda_{k-1}
+    };
+    zload(1);
+    int cur = 0;
+    for (int c0 = 1; c0 <= N; c0 += kChunk) {
+      const int lane = opaque_lane(lane0);
+#pragma unroll
+      for (int t = 0; t < kZPer; ++t) {
+        const int e = lane + 64 * t;
+        if (e < kChunk * 84 && c0 + e / 84 <= N) {
+          const int kl = e / 84, rem = e % 84;
+          sh.u.zst[kl * kZInt + (rem / 7) * kZRow + rem % 7] = zr[t];
+        }
       }
-      __syncthreads();
+      wave_lds_sync();
+      if (c0 + kChunk <= N) zload(c0 + kChunk);
+      const int nk = (N - c0 + 1) < kChunk ? (N - c0 + 1) : kChunk;
+      for (int kl = 0; kl < nk; ++kl) {
+        if (lane < 12) {
+          const double* zrow = sh.u.zst + kl * kZInt + lane * kZRow;
+          double v = zrow[6];
+#pragma unroll
+          for (int j = 0; j < 6; ++j) v = fma(zrow[j], sh.dx[cur][j], v);
+          if (lane < 6) {
+            sh.dx[cur ^ 1][lane] = v;
+            sh.dxs[kl * 6 + lane] = v;        // dx_k
+          } else {
+            sh.dls[kl * 6 + lane - 6] = v;    // dlambda_{k-1}
+          }
+        }
+        wave_lds_sync();
+        cur ^= 1;
+      }
+      // write out the chunk: dx of points c0..c0+nk-1, dlambda of points c0-1..c0+nk-2
+      for (int e = lane; e < 12 * nk; e += 64) {
+        const int half = e / (6 * nk), q = e % (6 * nk), kl = q / 6, i = q % 6;
+        if (half == 0) R[12 * (int64_t)(c0 + kl) + i] = sh.dxs[kl * 6 + i];
+        else R[12 * (int64_t)(c0 - 1 + kl) + 6 + i] = sh.dls[kl * 6 + i];
+      }
     }
-    if (lane < 6) Y[12 * (int64_t)N + 6 + lane] += P.pw * dx[lane] - R[6 + lane];
-    __syncthreads();
+    if (lane < 6) R[12 * (int64_t)N + 6 + lane] = P.pw * sh.dx[cur][lane] - sh.FN[lane];
+    wave_mem_sync();
+    for (int i = lane; i < 12 * NP; i += 64) Y[i] += R[i];
+    wave_mem_sync();
     ++it;
   }
   // ---- outputs (eq. optuv at t = 0) ----
@@ -442,7 +814,7 @@ int make_bvp_args(const sgcm_problem* p, BvpArgs* a) {
   a->alpha = 0.5 * a->h;
   a->tol = p->tol;
   const int64_t NP = (int64_t)p->N + 1;
-  const int64_t doubles = (12 + 84 + 12) * NP + 84 * (int64_t)p->N;
+  const int64_t doubles = (12 + 12 + 4) * NP + 84 * (int64_t)p->N;
   a->per_bvp = (doubles + 31) / 32 * 32;  // 256-byte multiples
   return SGCM_OK;
 }

@@ -182,6 +182,132 @@ __global__ __launch_bounds__(64) void k_surplus_level(GridArgs g, const double* 
   }
 }
 
+// ---- evaluation with the inner trie unrolled at compile time -----------------
+//
+// For a fixed (d, level, m) the trie below any prefix of the outer dimensions
+// depends only on the remaining excess budget, so the sum over the four
+// innermost dimensions is generated at compile time: their basis values sit in
+// registers with static indices, the surplus is read at immediate offsets from
+// a uniform base (scalar loads), and no loop or LDS access remains in the hot
+// part.  The outer dimensions are walked at run time with their basis values
+// in LDS, as in the generic kernel.
+
+__host__ __device__ constexpr int excess_of(int e) {
+  if (e == 0) return 0;
+  if (e <= 2) return 1;
+  int l = 0;
+  while ((1 << (l + 1)) <= e - 1) ++l;
+  return l + 1;
+}
+
+__host__ __device__ constexpr int subgrid(int r, int b) {
+  if (r == 0) return 1;
+  int s = 0;
+  for (int e = 0; e < upto(b); ++e) s += subgrid(r - 1, b - excess_of(e));
+  return s;
+}
+
+__host__ __device__ constexpr int child_off(int r, int b, int e) {
+  int s = 0;
+  for (int q = 0; q < e; ++q) s += subgrid(r - 1, b - excess_of(q));
+  return s;
+}
+
+// Sum over the subtree of R remaining (unrolled) dimensions with budget B whose
+// nodes start at offset OFF; E is the child being visited.  bv[j] holds the
+// basis values of unrolled dimension j.
+template <int KU, int P, int M, int R, int B, int OFF, int E>
+__device__ __forceinline__ void uwalk(const double (&bv)[KU][P], const double* __restrict__ w, double p,
+                                      double (&acc)[M]) {
+  if constexpr (E < upto(B)) {
+    constexpr int ex = excess_of(E);
+    constexpr int off = OFF + child_off(R, B, E);
+    if constexpr (R == 1) {
+      const double pe = p * bv[KU - 1][E];
+#pragma unroll
+      for (int c = 0; c < M; ++c) acc[c] = fma(pe, w[off * M + c], acc[c]);
+    } else if constexpr (R == 2) {
+      constexpr int n = upto(B - ex);
+      double t[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) t[c] = 0.0;
+#pragma unroll
+      for (int q = 0; q < n; ++q)
+#pragma unroll
+        for (int c = 0; c < M; ++c) t[c] = fma(bv[KU - 1][q], w[(off + q) * M + c], t[c]);
+      const double pe = p * bv[KU - 2][E];
+#pragma unroll
+      for (int c = 0; c < M; ++c) acc[c] = fma(pe, t[c], acc[c]);
+    } else {
+      uwalk<KU, P, M, R - 1, B - ex, off, 0>(bv, w, p * bv[KU - R][E], acc);
+    }
+    uwalk<KU, P, M, R, B, OFF, E + 1>(bv, w, p, acc);
+  }
+}
+
+template <int KU, int P, int M, int BB>
+__device__ __forceinline__ void uwalk_budget(int b, const double (&bv)[KU][P], const double* __restrict__ w,
+                                             double p, double (&acc)[M]) {
+  if (b == BB) {
+    uwalk<KU, P, M, KU, BB, 0, 0>(bv, w, p, acc);
+  } else if constexpr (BB > 0) {
+    uwalk_budget<KU, P, M, BB - 1>(b, bv, w, p, acc);
+  }
+}
+
+template <int D, int L, int M, int KO, int KU, int K>
+__device__ __forceinline__ void owalk(const GridArgs& g, const double* __restrict__ w, int bL, int64_t base,
+                                      double p, double (&acc)[M], const double (&bv)[KU][upto(L)],
+                                      const double* lds_lane) {
+  constexpr int P = upto(L);
+  if constexpr (K == KO) {
+    uwalk_budget<KU, P, M, L>(bL, bv, w + base * M, p, acc);
+  } else {
+    const int cE = upto(bL);
+    const int32_t* offrow = g.off + ((D - K - 1) * (L + 1) + bL) * P;
+    for (int e = 0; e < cE; ++e) {
+      const int ex = g.excess[e];
+      const double pk = (K == 0) ? lds_lane[(K * P + e) * 64] : p * lds_lane[(K * P + e) * 64];
+      owalk<D, L, M, KO, KU, K + 1>(g, w, bL - ex, base + offrow[e], pk, acc, bv, lds_lane);
+    }
+  }
+}
+
+template <int D, int L, int M>
+__global__ __launch_bounds__(64) void k_eval_fast(GridArgs g, const double* __restrict__ w, int64_t nq,
+                                                  const double* __restrict__ xq, double* __restrict__ uq) {
+  constexpr int P = upto(L);
+  constexpr int KU = D < 4 ? D : 4;
+  constexpr int KO = D - KU;
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x;
+  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+  const bool active = q < nq;
+  double* lds_lane = lds + lane;
+  double bv[KU][P];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double xi = active ? (xq[q * D + k] - g.lo[k]) * g.inv_width[k] : 0.5;
+    double row[kMaxPoints];
+    basis_row_l<L>(g, xi, row);
+    if (k < KO) {
+#pragma unroll
+      for (int e = 0; e < P; ++e) lds_lane[(k * P + e) * 64] = row[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < P; ++e) bv[k - KO][e] = row[e];
+    }
+  }
+  double acc[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) acc[c] = 0.0;
+  owalk<D, L, M, KO, KU, 0>(g, w, L, 0, 1.0, acc, bv, lds_lane);
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < M; ++c) uq[q * M + c] = acc[c];
+  }
+}
+
 // ---- host side -------------------------------------------------------------
 
 int ensure_device_tables(Grid& G, int dev) {
@@ -198,10 +324,10 @@ int ensure_device_tables(Grid& G, int dev) {
             up((void**)&gd.tables, G.itab.data(), G.itab.size() * sizeof(int32_t)) &&
             up((void**)&gd.dtab, G.dtab.data(), G.dtab.size() * sizeof(double));
   if (!ok) {
-    hipFree(gd.node_xi);
-    hipFree(gd.by_level);
-    hipFree(gd.tables);
-    hipFree(gd.dtab);
+    (void)hipFree(gd.node_xi);
+    (void)hipFree(gd.by_level);
+    (void)hipFree(gd.tables);
+    (void)hipFree(gd.dtab);
     gd = GridDevice();
     return SGCM_ENOMEM;
   }
@@ -305,6 +431,39 @@ hipError_t level_chunk(int d, int mc, const GridArgs& a, size_t lds, const doubl
 #undef CALL_LEVEL
 }
 
+template <int L, int M>
+hipError_t launch_fast(const GridArgs& a, int64_t nq, const double* w, const double* xq, double* uq,
+                       hipStream_t s) {
+  constexpr int D = 6;
+  const size_t lds = (size_t)(D - 4) * upto(L) * 64 * sizeof(double);
+  const int64_t blocks = (nq + 63) / 64;
+  hipLaunchKernelGGL((k_eval_fast<D, L, M>), dim3((unsigned)blocks), dim3(64), lds, s, a, w, nq, xq, uq);
+  return hipGetLastError();
+}
+
+template <int L>
+hipError_t fast_m(int m, const GridArgs& a, int64_t nq, const double* w, const double* xq, double* uq,
+                  hipStream_t s) {
+  switch (m) {
+    case 1: return launch_fast<L, 1>(a, nq, w, xq, uq, s);
+    case 2: return launch_fast<L, 2>(a, nq, w, xq, uq, s);
+    default: return launch_fast<L, 3>(a, nq, w, xq, uq, s);
+  }
+}
+
+// The unrolled kernel covers d = 6, levels 1..4, m <= 3 (the rigid-body feedback).
+bool fast_eval_applies(const Grid& G, int m) { return G.d == 6 && G.level >= 1 && G.level <= 4 && m <= 3; }
+
+hipError_t eval_fast(const Grid& G, int m, const GridArgs& a, int64_t nq, const double* w, const double* xq,
+                     double* uq, hipStream_t s) {
+  switch (G.level) {
+    case 1: return fast_m<1>(m, a, nq, w, xq, uq, s);
+    case 2: return fast_m<2>(m, a, nq, w, xq, uq, s);
+    case 3: return fast_m<3>(m, a, nq, w, xq, uq, s);
+    default: return fast_m<4>(m, a, nq, w, xq, uq, s);
+  }
+}
+
 int current_device(int* dev) {
   if (hipGetDevice(dev) != hipSuccess) return SGCM_EDEVICE;
   if (*dev < 0 || *dev >= kMaxDevices) return SGCM_EUNSUPPORTED;
@@ -320,14 +479,14 @@ void free_device_tables(Grid& G) {
     GridDevice& gd = G.dev[dv];
     if (!gd.ready) continue;
     if (hipSetDevice(dv) == hipSuccess) {
-      hipFree(gd.node_xi);
-      hipFree(gd.by_level);
-      hipFree(gd.tables);
-      hipFree(gd.dtab);
+      (void)hipFree(gd.node_xi);
+      (void)hipFree(gd.by_level);
+      (void)hipFree(gd.tables);
+      (void)hipFree(gd.dtab);
     }
     gd = GridDevice();
   }
-  if (cur >= 0) hipSetDevice(cur);
+  if (cur >= 0) (void)hipSetDevice(cur);
 }
 
 }  // namespace sgcm
@@ -377,6 +536,7 @@ extern "C" int sgcm_eval_feedback(const sgcm_grid* gh, int32_t m, const double* 
   GridArgs a = make_args(G, G.dev[dev]);
   const size_t lds = lds_bytes(G);
   hipStream_t s = (hipStream_t)stream;
+  if (fast_eval_applies(G, m)) return eval_fast(G, m, a, n_q, surplus, xq, uq, s) == hipSuccess ? SGCM_OK : SGCM_EDEVICE;
   for (int col0 = 0; col0 < m; col0 += 3) {
     const int mc = (m - col0) < 3 ? (m - col0) : 3;
     if (eval_chunk(G.d, mc, a, lds, surplus, m, col0, n_q, xq, uq, s) != hipSuccess) return SGCM_EDEVICE;
