@@ -200,36 +200,65 @@ __device__ __forceinline__ int opaque_lane(int lane) {
   return lane;
 }
 
-constexpr int kRing = 16;    // point slots in the LDS ring (power of two)
-constexpr int kBatch = 8;    // points derived per refill
-constexpr int kSlot = 120;   // per point: A (36), W (36), L (36), r_k (12)
-constexpr int kChunk = 8;    // intervals staged per forward-pass chunk
-constexpr int kZRow = 8;     // padded row of a staged interval solution
-constexpr int kZInt = 12 * kZRow;
-constexpr int kZPer = (kChunk * 84 + 63) / 64;  // prefetch registers per lane
+// LDS hand-off inside the wavefront: a compiler-only barrier.  LDS accesses of
+// one wavefront are performed in program order, so a value one lane writes is
+// seen by a later read of another lane without waiting for the write.
+__device__ __forceinline__ void lds_handoff() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-struct SweepShared {
+// Value of v in lane src (a wave-uniform constant), broadcast through SGPRs.
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, src);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+// 16 bytes from src (per lane) into LDS at dst + 16 * lane, without passing
+// through registers (gfx950 global_load_lds_dwordx4); dst is wave-uniform.
+// Completion is tracked by the vector memory counter.
+__device__ __forceinline__ void g2lds16(const double* src, double* dst) {
+  __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+}
+
+constexpr int kNB = 8;             // intervals per sweep batch
+constexpr int kPt = 120;           // per point: A (36), W (36), L (36), r (12)
+constexpr int kKc = 80;            // K = [R | B | rho], column-major, columns padded to 8
+constexpr int kFHr = 20;           // row of F (6), H (6), Gam' (7), pad
+constexpr int kCst = kKc + 6 * kFHr;
+constexpr int kFwd = 12;           // intervals per forward-pass chunk (two chunk buffers)
+constexpr int kZI = 96;            // interval solution: 12 rows padded to 8
+constexpr int kFwdY = 12 * (kFwd + 1);     // rows of Y a chunk updates
+constexpr int kFwdBuf = kFwd * kZI + kFwdY;
+constexpr int kStage = 256;        // point inputs of one batch: y [9][12], r [9][12], trig [9][4]
+
+struct __align__(16) SweepShared {
   union {
-    double ring[kRing * kSlot];
-    double zst[kChunk * kZInt];
-    double pa[2 * 64 * 12];  // phase A: Phi and y of one 64-point chunk
+    struct {
+      double pts[(kNB + 1) * kPt];  // point blocks of one batch (slot l: point klo - 1 + l)
+      double cst[kNB * kCst];       // interval constants of one batch
+    } b;
+    double fwd[2 * kFwdBuf];        // forward pass: two chunks of [Z | Y rows]
+    double pa[2 * 64 * 12];         // residual pass: Phi and y of one 64-point chunk
   } u;
+  double stage[kStage];  // point inputs of the next batch (filled by direct global-to-LDS loads)
+  double PR[48];   // [P | c] rows (c in column 6), 8 per row
+  double QC[80];   // columns of Q, 8 per column
+  double TT[40];   // columns of T = (Q + E) rate rows, 4 per column
+  double ER[24];   // rows of E[:, 6..8], 4 per row
   double carry_phi[12], carry_y[12];
-  double F[36], H[36], Gam[36], Rk[36], rho[6], Dr[6];
-  double Pt[36], c[6];  // P_k column-major (Pt[j*6+m] = P[m][j]), c_k
-  double EM1[36], Psi[18], phi[6], phic[6];
-  double T1[9], T2[18], t3[3];
-  double X1[36], X2[18], X3[6];
-  double dx[2][8];
-  double zsw[kBatch * 84];               // interval solutions of the last kBatch steps
-  double dxs[kChunk * 6], dls[kChunk * 6]; // forward pass: dx and dlambda of one chunk
-  double F0[6], FN[6], xb[6];
-  double zero[2];  // a zero operand for uniform (branch-free) stage code
+  double xb[6], F0[6], FN[6];
+  double zero[8];
   int flag;
 };
 
-// Flat double offsets into SweepShared: the sweep stages address LDS as one
-// array so that every lane runs the same instructions with per-lane offsets.
+// Flat double offsets into SweepShared: lanes address LDS as one array so that
+// every lane runs the same instructions with per-lane offsets.
 #define SGCM_OFF(field) ((int)(offsetof(SweepShared, field) / sizeof(double)))
 
 // A = df/dx, W and L = (I - a A)^{-1} of one mesh point into an LDS slot
@@ -327,24 +356,71 @@ __device__ __forceinline__ void point_blocks(const BvpArgs& P, const double (&y)
   }
 }
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_newton(BvpArgs P, const double* __restrict__ x0,
-                                               double* __restrict__ lam0, double* __restrict__ u0,
-                                               double* __restrict__ Vout, double* __restrict__ traj,
-                                               int32_t* __restrict__ status, int32_t* __restrict__ iters,
-                                               double* __restrict__ ws) {
+// One column task of the interval constants: out = u1 x1 + M (u2 x2), with M
+// = L_k (tasks 0..11) or L_{k-1}^T (tasks 12..31), x1 and x2 6-vectors read
+// from LDS with a stride, out written with a stride.  Tasks: 0..9 columns of
+// K = L_k [I + a A_{k-1} | a e_rates | -r^x]; 12..17 columns of
+// F = L_{k-1}^T (I + a A_k^T); 18: -D^{-1} r^l; 19..24 columns of
+// H = a L_{k-1}^T W_k; 25..30 columns of Gam = a L_{k-1}^T W_{k-1};
+// 10, 11, 31 are empty (dst < 0).
+struct ColTask {
+  int x1, s1, x2, s2, dst, ds;
+  double u1, u2;
+};
+
+__device__ __forceinline__ ColTask col_task(int tau, int pa, int pb, int cst, int zero, double alpha) {
+  ColTask c;
+  c.x1 = zero; c.s1 = 0; c.u1 = 0.0;
+  c.x2 = zero; c.s2 = 0; c.u2 = 0.0;
+  c.dst = -1; c.ds = 1;
+  if (tau < 6) {
+    c.x1 = pb + 72 + tau; c.s1 = 6; c.u1 = 1.0;
+    c.x2 = pa + tau; c.s2 = 6; c.u2 = alpha;
+    c.dst = cst + tau * 8;
+  } else if (tau < 9) {
+    c.x1 = pb + 72 + tau - 3; c.s1 = 6; c.u1 = alpha;
+    c.dst = cst + tau * 8;
+  } else if (tau == 9) {
+    c.x2 = pb + 108; c.s2 = 1; c.u2 = -1.0;
+    c.dst = cst + 72;
+  } else if (tau >= 12 && tau < 18) {
+    const int j = tau - 12;
+    c.x1 = pa + 72 + 6 * j; c.s1 = 1; c.u1 = 1.0;
+    c.x2 = pb + 6 * j; c.s2 = 1; c.u2 = alpha;
+    c.dst = cst + kKc + j; c.ds = kFHr;
+  } else if (tau == 18) {
+    c.x2 = pb + 114; c.s2 = 1; c.u2 = -1.0;
+    c.dst = cst + kKc + 18; c.ds = kFHr;
+  } else if (tau >= 19 && tau < 25) {
+    const int j = tau - 19;
+    c.x2 = pb + 36 + j; c.s2 = 6; c.u2 = alpha;
+    c.dst = cst + kKc + 6 + j; c.ds = kFHr;
+  } else if (tau >= 25 && tau < 31) {
+    const int j = tau - 25;
+    c.x2 = pa + 36 + j; c.s2 = 6; c.u2 = alpha;
+    c.dst = cst + kKc + 12 + j; c.ds = kFHr;
+  }
+  return c;
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_newton(
+    BvpArgs P, const double* __restrict__ x0, double* __restrict__ lam0, double* __restrict__ u0,
+    double* __restrict__ Vout, double* __restrict__ traj, int32_t* __restrict__ status,
+    int32_t* __restrict__ iters, double* __restrict__ ws) {
   const int lane0 = threadIdx.x;
   const int lane = lane0;
   const int64_t b = blockIdx.x;
   const int N = P.N, NP = N + 1;
   const double alpha = P.alpha;
   double* Y = ws + b * P.per_bvp;      // NP x 12: the iterate
-  double* R = Y + 12 * (int64_t)NP;    // NP x 12: residuals (row 0 = [F_0, F_N]), then the step
+  double* R = Y + 12 * (int64_t)NP;    // NP x 12: residuals r_k (row 0 = [F_0, F_N])
   double* TR = R + 12 * (int64_t)NP;   // NP x 4: sin phi, cos phi, tan theta, sec theta
-  double* Zg = TR + 4 * (int64_t)NP;   // N x 84: interval solutions, row-major 12 x 7
+  double* Zg = TR + 4 * (int64_t)NP;   // N x 96: interval solutions, 12 rows of 8
 
   __shared__ SweepShared sh;
+  double* const Bs = reinterpret_cast<double*>(&sh);
   if (lane < 6) sh.xb[lane] = x0[b * 6 + lane];
-  if (lane < 2) sh.zero[lane] = 0.0;
+  if (lane < 8) sh.zero[lane] = 0.0;
   for (int i = lane; i < 12 * NP; i += 64) Y[i] = 0.0;
   wave_mem_sync();
 
@@ -371,7 +447,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
           sh.u.pa[768 + lane * 12 + i] = yk[i];
         }
       }
-      wave_lds_sync();
+      lds_handoff();
       if (valid) {
         if (k == 0) {
 #pragma unroll
@@ -402,7 +478,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
           }
         }
       }
-      wave_lds_sync();
+      lds_handoff();
       if (lane == 63 && valid) {
 #pragma unroll
         for (int i = 0; i < 12; ++i) {
@@ -410,7 +486,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
           sh.carry_y[i] = yk[i];
         }
       }
-      wave_lds_sync();
+      lds_handoff();
     }
     wave_mem_sync();  // residuals R visible to every lane
     const bool nonfinite = __any(bad);
@@ -421,297 +497,292 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       if (it == P.max_iter) { st = SGCM_BVP_MAXITER; break; }
     }
 
-    // ---- backward Riccati sweep ----
+    // ---- backward Riccati sweep, batches of kNB intervals from k = N down ----
     if (lane < 6) {
       sh.F0[lane] = R[lane];
       sh.FN[lane] = R[6 + lane];
-      sh.c[lane] = -R[6 + lane];
-    }
-    if (lane < 36) {
-      const int j = lane / 6, m = lane % 6;
-      sh.Pt[lane] = (j == m) ? P.pw : 0.0;
     }
     if (lane == 0) sh.flag = 0;
-    int pf_lo = N + 1;  // lowest point already in the ring
-    int zhi = N;        // highest interval staged in zsw and not yet written out
-    // write the staged interval solutions of intervals [klo, zhi] to global memory
-    auto flush_z = [&](int klo) {
-      const int lane = opaque_lane(lane0);
-      const int cnt = (zhi - klo + 1) * 84;
-      for (int e = lane; e < cnt; e += 64) {
-        const int kk = klo + e / 84, r = e % 84;
-        Zg[(int64_t)(kk - 1) * 84 + r] = sh.zsw[(kk & (kBatch - 1)) * 84 + r];
+    lds_handoff();
+    // chain state: lane (i, o), o in 0..5 and 9, holds [P_k | c_k][i][o]
+    double pv;
+    {
+      const int l = opaque_lane(lane0);
+      const int ci = l < 60 ? l / 10 : 5, co = l < 60 ? l % 10 : 0;
+      pv = (co < 6) ? (ci == co ? P.pw : 0.0) : -sh.FN[ci];
+    }
+    // point inputs (y, r, trig) of points [lo - 1, hi] into the LDS stage;
+    // rows are contiguous in global memory, 16 bytes per lane
+    auto load_points = [&](int lo, int hi) {
+      const int l = opaque_lane(lane0);
+      const int cnt = hi - lo + 2;
+      const int64_t p0 = lo - 1;
+      if (l < 6 * cnt) {
+        g2lds16(Y + 12 * p0 + 2 * l, sh.stage);
+        g2lds16(R + 12 * p0 + 2 * l, sh.stage + 108);
       }
-      zhi = klo - 1;
+      if (l < 2 * cnt) g2lds16(TR + 4 * p0 + 2 * l, sh.stage + 216);
     };
-    wave_lds_sync();
+    int khi = N;
+    int klo = khi - (kNB - 1) < 1 ? 1 : khi - (kNB - 1);
+    load_points(klo, khi);
     bool singular = false;
-    for (int k = N; k >= 1; --k) {
-      if (k - 1 < pf_lo) {
-        // refill the ring with points [lo, hi]: issue the loads first, then
-        // write out the staged solutions, so that the wait for the loads does
-        // not include the stores
-        const int lane = opaque_lane(lane0);
-        const int hi = pf_lo - 1;
-        const int lo = hi - (kBatch - 1) < 0 ? 0 : hi - (kBatch - 1);
-        const int p = lo + lane;
-        double py[12], pr[12], pt[4];
-        if (lane < kBatch && p <= hi) {
-          const int64_t pp = p >= 1 ? p : 1;  // r_0 does not exist; row 0 holds F_0, F_N
+    while (true) {
+      const int nb = khi - klo + 1;
+      // point blocks of points klo - 1 .. khi into slots 0 .. nb (the
+      // residual of point p is r_p, the residual of interval p; row 0 of R
+      // holds F_0, F_N and is never used as an interval residual)
+      wave_mem_sync();  // the stage has landed
+      {
+        const int l = opaque_lane(lane0);
+        if (l <= nb) {
+          double py[12], pt[4];
+          double* slot = sh.u.b.pts + l * kPt;
 #pragma unroll
           for (int i = 0; i < 12; ++i) {
-            py[i] = Y[12 * (int64_t)p + i];
-            pr[i] = R[12 * pp + i];
+            py[i] = sh.stage[l * 12 + i];
+            slot[108 + i] = sh.stage[108 + l * 12 + i];
           }
 #pragma unroll
-          for (int i = 0; i < 4; ++i) pt[i] = TR[4 * (int64_t)p + i];
-        }
-        if (zhi > k) flush_z(k + 1);
-        if (lane < kBatch && p <= hi) {
-          double* slot = sh.u.ring + (p & (kRing - 1)) * kSlot;
-#pragma unroll
-          for (int i = 0; i < 12; ++i) slot[108 + i] = pr[i];
+          for (int i = 0; i < 4; ++i) pt[i] = sh.stage[216 + l * 4 + i];
           point_blocks(P, py, pt, slot, &sh.flag);
         }
-        pf_lo = lo;
-        wave_lds_sync();
-        if (sh.flag) {
-          singular = true;
-          break;
-        }
       }
-      double* const Bs = reinterpret_cast<double*>(&sh);
-      const int ra = ((k - 1) & (kRing - 1)) * kSlot;  // point k-1 in the ring
-      const int rb = (k & (kRing - 1)) * kSlot;        // point k
-      // stage 0: interval products (independent of P_k).  Lane (i, j):
-      //   F = L_a^T (I + a A_b^T), H = a L_a^T W_b, Gam = a L_a^T W_a share
-      //   column i of L_a; R_k = L_b (I + a A_a); lanes j = 0, 1 also form
-      //   rho = -L_b r^x and D^{-1} r^l = L_a^T r^l.
-      if (opaque_lane(lane0) < 36) {
-        const int lane = opaque_lane(lane0);
-        const int i = lane / 6, j = lane % 6;
-        const int r5 = rb + 108 + (j == 0 ? 0 : 6);
-        // every LDS read of the stage is issued before the first product, so
-        // the stage waits for LDS once
-        double la[6], lb[6], ab[6], wb[6], wa[6], aa[6], rv[6];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) {
-          la[m] = Bs[ra + 72 + m * 6 + i];
-          lb[m] = Bs[rb + 72 + i * 6 + m];
-          ab[m] = Bs[rb + j * 6 + m];
-          wb[m] = Bs[rb + 36 + m * 6 + j];
-          wa[m] = Bs[ra + 36 + m * 6 + j];
-          aa[m] = Bs[ra + m * 6 + j];
-          rv[m] = Bs[r5 + m];
-        }
-        const double cF = Bs[ra + 72 + j * 6 + i], cR = Bs[rb + 72 + i * 6 + j];
-        __builtin_amdgcn_sched_barrier(0);
-        double sF = 0.0, sH = 0.0, sG = 0.0, sR = 0.0, s5 = 0.0;
-#pragma unroll
-        for (int m = 0; m < 6; ++m) {
-          sF = fma(la[m], ab[m], sF);
-          sH = fma(la[m], wb[m], sH);
-          sG = fma(la[m], wa[m], sG);
-          sR = fma(lb[m], aa[m], sR);
-          s5 = fma(j == 0 ? lb[m] : la[m], rv[m], s5);
-        }
-        sh.F[lane] = fma(alpha, sF, cF);
-        sh.H[lane] = alpha * sH;
-        sh.Gam[lane] = alpha * sG;
-        sh.Rk[lane] = fma(alpha, sR, cR);
-        if (j == 0) sh.rho[i] = -s5;
-        if (j == 1) sh.Dr[i] = s5;
+      lds_handoff();
+      if (sh.flag) {
+        singular = true;
+        break;
       }
-      wave_lds_sync();
-      // stage 1: EM1 = F P_k - H; Psi_w = (P_k + EM1) rate rows; lanes j = 0:
-      // phic = F c_k + D^{-1} r^l and phi = c_k + phic
-      if (opaque_lane(lane0) < 36) {
-        const int lane = opaque_lane(lane0);
-        const int i = lane / 6, j = lane % 6;
-        double f[6], pt[6], cc[6];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) {
-          f[m] = sh.F[i * 6 + m];
-          pt[m] = sh.Pt[j * 6 + m];
-          cc[m] = sh.c[m];
-        }
-        const double h = sh.H[lane], dr = sh.Dr[i], pji = sh.Pt[j * 6 + i], ci = sh.c[i];
-        __builtin_amdgcn_sched_barrier(0);
-        double e = -h, q = dr;
-#pragma unroll
-        for (int m = 0; m < 6; ++m) {
-          e = fma(f[m], pt[m], e);
-          q = fma(f[m], cc[m], q);
-        }
-        sh.EM1[lane] = e;
-        if (i >= 3) sh.Psi[(i - 3) * 6 + j] = pji + e;
-        if (j == 0) {
-          sh.phic[i] = q;
-          sh.phi[i] = q + ci;
-        }
-      }
-      wave_lds_sync();
-      // stage 2: rows r = 0..2 are Psi_w rows -> T2 = Psi_w R_k - Gam_w,
-      // T1 = Psi_w B_k, t3 = Psi_w rho + phi_w; rows r = 3..8 are EM1 rows ->
-      // X1 = EM1 R_k - Gam, X2 = EM1 B_k, X3 = EM1 rho.  Column o = 0..5: R_k
-      // column, 6..8: B_k column (a L_b rate columns), 9: rho.  Each lane forms
-      // two outputs of one row.
-      if (opaque_lane(lane0) < 45) {
-        const int lane = opaque_lane(lane0);
-        const int r = lane / 5, o0 = 2 * (lane % 5);
-        const int lrow = (r < 3) ? SGCM_OFF(Psi) + r * 6 : SGCM_OFF(EM1) + (r - 3) * 6;
-        const int grow = (r < 3) ? 3 + r : r - 3;
-        double lv[6], rc[2][6], cv[2], coef[2], csgn[2];
-        int dst[2];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) lv[m] = Bs[lrow + m];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int o = o0 + h;
-          const int rbase = (o < 6) ? SGCM_OFF(Rk) + o : (o < 9) ? rb + 72 + 3 + (o - 6) : SGCM_OFF(rho);
-          const int rs = (o < 9) ? 6 : 1;
-          const int cidx = (o < 6) ? SGCM_OFF(Gam) + grow * 6 + o
-                                   : (o == 9 && r < 3) ? SGCM_OFF(phi) + 3 + r : SGCM_OFF(zero);
-          csgn[h] = (o < 6) ? -1.0 : 1.0;
-          coef[h] = (o >= 6 && o < 9) ? alpha : 1.0;
-          dst[h] = (r < 3) ? ((o < 6) ? SGCM_OFF(T2) + r * 6 + o
-                                      : (o < 9) ? SGCM_OFF(T1) + r * 3 + (o - 6) : SGCM_OFF(t3) + r)
-                           : ((o < 6) ? SGCM_OFF(X1) + (r - 3) * 6 + o
-                                      : (o < 9) ? SGCM_OFF(X2) + (r - 3) * 3 + (o - 6)
-                                                : SGCM_OFF(X3) + (r - 3));
-#pragma unroll
-          for (int m = 0; m < 6; ++m) rc[h][m] = Bs[rbase + m * rs];
-          cv[h] = Bs[cidx];
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          double acc = 0.0;
-#pragma unroll
-          for (int m = 0; m < 6; ++m) acc = fma(lv[m], rc[h][m], acc);
-          Bs[dst[h]] = fma(coef[h], acc, csgn[h] * cv[h]);
-        }
-      }
-      wave_lds_sync();
-      // stage 3: Z3 = I + S_w T1 and its inverse (every lane), then lane (i, j):
-      // M = Z3^{-1} S_w [T2 | t3], P_{k-1} = X1 - X2 M, c_{k-1} = X3 + phic - X2 m,
-      // G_k = R_k - B_k M, g_k = rho - B_k m
+      // interval constants: lane (interval tl, part), four column tasks each
       {
-        const int lane = opaque_lane(lane0);
-        const int ll = lane < 42 ? lane : 41;
-        const int i = ll / 7, j = ll % 7;
-        const bool col = j < 6;
-        double t1[9], v[3], x2[3], lb[3];
+        const int l = opaque_lane(lane0);
+        const int tl = l >> 3, part = l & 7;
+        if (tl < nb) {
+          const int k = khi - tl;
+          const int pa = SGCM_OFF(u.b.pts) + (k - klo) * kPt;  // point k - 1
+          const int pb = pa + kPt;                              // point k
+          const int cst = SGCM_OFF(u.b.cst) + tl * kCst;
+          const bool lk = part < 3;
+          const int mb = (lk ? pb : pa) + 72, msi = lk ? 6 : 1, msm = lk ? 1 : 6;
+          double M[36];
 #pragma unroll
-        for (int e = 0; e < 9; ++e) t1[e] = sh.T1[e];
+          for (int i = 0; i < 6; ++i)
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          v[m] = Bs[col ? SGCM_OFF(T2) + m * 6 + j : SGCM_OFF(t3) + m];
-          x2[m] = sh.X2[i * 3 + m];
-          lb[m] = Bs[rb + 72 + i * 6 + 3 + m];
+            for (int m = 0; m < 6; ++m) M[i * 6 + m] = Bs[mb + i * msi + m * msm];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const ColTask ct = col_task(part * 4 + c, pa, pb, cst, SGCM_OFF(zero), alpha);
+            double x1[6], v[6];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+              x1[m] = ct.u1 * Bs[ct.x1 + m * ct.s1];
+              v[m] = ct.u2 * Bs[ct.x2 + m * ct.s2];
+            }
+            if (ct.dst >= 0) {
+#pragma unroll
+              for (int i = 0; i < 6; ++i) {
+                double o = x1[i];
+#pragma unroll
+                for (int m = 0; m < 6; ++m) o = fma(M[i * 6 + m], v[m], o);
+                Bs[ct.dst + i * ct.ds] = o;
+              }
+            }
+          }
         }
-        const double p0 = Bs[col ? SGCM_OFF(X1) + i * 6 + j : SGCM_OFF(X3) + i];
-        const double p1 = Bs[col ? SGCM_OFF(zero) : SGCM_OFF(phic) + i];
-        const double g0 = Bs[col ? SGCM_OFF(Rk) + i * 6 + j : SGCM_OFF(rho) + i];
-        __builtin_amdgcn_sched_barrier(0);
-        double Z3[9], Zi[9];
+      }
+      lds_handoff();
+      // inputs of the next batch, in flight during the chain
+      const int nhi = klo - 1;
+      const int nlo = nhi - (kNB - 1) < 1 ? 1 : nhi - (kNB - 1);
+      if (nhi >= 1) load_points(nlo, nhi);
+      // the serial chain: three LDS exchanges per interval
+      for (int t = 0; t < nb; ++t) {
+        const int k = khi - t;
+        const int l = opaque_lane(lane0);
+        const bool cv = l < 60;
+        const int ci = cv ? l / 10 : 5, co = cv ? l % 10 : 0;
+        const bool cst_lane = cv && (co < 6 || co == 9);
+        const int cs = co < 6 ? co : 6;
+        const int c0 = SGCM_OFF(u.b.cst) + t * kCst;
+        // exchange 1: rows of [P_k | c_k]
+        if (cst_lane) sh.PR[ci * 8 + cs] = pv;
+        lds_handoff();
+        double prow[7], kcol[6], fh[12], kb[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const dbl2 v = *reinterpret_cast<const dbl2*>(&sh.PR[ci * 8 + 2 * q]);
+          prow[2 * q] = v.x;
+          prow[2 * q + 1] = v.y;
+        }
+        prow[6] = sh.PR[ci * 8 + 6];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const dbl2 v = *reinterpret_cast<const dbl2*>(&Bs[c0 + co * 8 + 2 * q]);
+          kcol[2 * q] = v.x;
+          kcol[2 * q + 1] = v.y;
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          const dbl2 v = *reinterpret_cast<const dbl2*>(&Bs[c0 + kKc + ci * kFHr + 2 * q]);
+          fh[2 * q] = v.x;
+          fh[2 * q + 1] = v.y;
+        }
+        const double gam = Bs[cst_lane ? c0 + kKc + ci * kFHr + 12 + cs : SGCM_OFF(zero)];
+        const double kio = Bs[c0 + co * 8 + ci];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) kb[a] = Bs[c0 + (6 + a) * 8 + ci];
+        // Q = [P | c] [K ; e_9],  C = H K + [Gam | 0 | -D^{-1} r^l]
+        double q = co == 9 ? prow[6] : 0.0;
+        double cc = gam;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+          q = fma(prow[m], kcol[m], q);
+          cc = fma(fh[6 + m], kcol[m], cc);
+        }
+        // exchange 2: columns of Q
+        if (cv) sh.QC[co * 8 + ci] = q;
+        lds_handoff();
+        double qcol[6];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const dbl2 v = *reinterpret_cast<const dbl2*>(&sh.QC[co * 8 + 2 * r]);
+          qcol[2 * r] = v.x;
+          qcol[2 * r + 1] = v.y;
+        }
+        double e = -cc;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) e = fma(fh[m], qcol[m], e);
+        const double tv = q + e;  // T = Psi_w [K ; e_9] on the rate rows
+        // exchange 3: columns of T, rows of E[:, 6..8]; T[:, 6..8] to every lane
+        if (cv && ci >= 3) sh.TT[co * 4 + ci - 3] = tv;
+        if (cv && co >= 6 && co <= 8) sh.ER[ci * 4 + co - 6] = e;
+        double t1[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) t1[a * 3 + c] = lane_bcast(tv, (3 + a) * 10 + 6 + c);
+        lds_handoff();
+        const dbl2 tc01 = *reinterpret_cast<const dbl2*>(&sh.TT[co * 4]);
+        const double tc2 = sh.TT[co * 4 + 2];
+        const dbl2 er01 = *reinterpret_cast<const dbl2*>(&sh.ER[ci * 4]);
+        const double er2 = sh.ER[ci * 4 + 2];
+        // Z3 = I + S_w T[:, 6..8]; its adjugate and determinant
+        double z[9];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            double t = (a == c) ? 1.0 : 0.0;
+            double s = (a == c) ? 1.0 : 0.0;
 #pragma unroll
-            for (int m = 0; m < 3; ++m) t = fma(P.Sw[a * 3 + m], t1[m * 3 + c], t);
-            Z3[a * 3 + c] = t;
+            for (int m = 0; m < 3; ++m) s = fma(P.Sw[a * 3 + m], t1[m * 3 + c], s);
+            z[a * 3 + c] = s;
           }
-        const double det = inv3(Z3, Zi);
+        const double j00 = z[4] * z[8] - z[5] * z[7], j01 = z[2] * z[7] - z[1] * z[8], j02 = z[1] * z[5] - z[2] * z[4];
+        const double j10 = z[5] * z[6] - z[3] * z[8], j11 = z[0] * z[8] - z[2] * z[6], j12 = z[2] * z[3] - z[0] * z[5];
+        const double j20 = z[3] * z[7] - z[4] * z[6], j21 = z[1] * z[6] - z[0] * z[7], j22 = z[0] * z[4] - z[1] * z[3];
+        const double det = z[0] * j00 + z[1] * j10 + z[2] * j20;
         if (det == 0.0) singular = true;
-        if (lane < 42 && !singular) {
-          double w[3], mu[3];
+        // y = adj(Z3) S_w T[:, o]; [M | m][:, o] = y / det
+        const double tc[3] = {tc01.x, tc01.y, tc2};
+        double w[3];
 #pragma unroll
-          for (int a = 0; a < 3; ++a) w[a] = P.Sw[a * 3 + 0] * v[0] + P.Sw[a * 3 + 1] * v[1] + P.Sw[a * 3 + 2] * v[2];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) mu[a] = Zi[a * 3 + 0] * w[0] + Zi[a * 3 + 1] * w[1] + Zi[a * 3 + 2] * w[2];
-          double pn = p0 + p1;
-          double gn = g0;
-#pragma unroll
-          for (int m = 0; m < 3; ++m) {
-            pn = fma(-x2[m], mu[m], pn);
-            gn = fma(-alpha * lb[m], mu[m], gn);
-          }
-          Bs[col ? SGCM_OFF(Pt) + j * 6 + i : SGCM_OFF(c) + i] = pn;
-          double* zk = sh.zsw + (k & (kBatch - 1)) * 84;
-          zk[i * 7 + j] = gn;
-          zk[(6 + i) * 7 + j] = pn;
+        for (int a = 0; a < 3; ++a) w[a] = fma(P.Sw[a * 3 + 0], tc[0], fma(P.Sw[a * 3 + 1], tc[1], P.Sw[a * 3 + 2] * tc[2]));
+        const double y0 = fma(j00, w[0], fma(j01, w[1], j02 * w[2]));
+        const double y1 = fma(j10, w[0], fma(j11, w[1], j12 * w[2]));
+        const double y2 = fma(j20, w[0], fma(j21, w[1], j22 * w[2]));
+        const double rd = 1.0 / det;
+        // P_{k-1} = E - E[:, 6..8] M, c_{k-1} = E[:, 9] - E[:, 6..8] m,
+        // G_k = K - B_k M, g_k = rho - B_k m
+        const double ey = fma(er01.x, y0, fma(er01.y, y1, er2 * y2));
+        const double ky = fma(kb[0], y0, fma(kb[1], y1, kb[2] * y2));
+        const double pn = fma(-rd, ey, e);
+        const double gn = fma(-rd, ky, kio);
+        if (cst_lane) {
+          double* zk = Zg + (int64_t)(k - 1) * kZI;
+          zk[ci * 8 + cs] = gn;
+          zk[(6 + ci) * 8 + cs] = pn;
         }
+        pv = pn;
+        if (singular) break;
       }
-      wave_lds_sync();
-      if (singular) break;
+      if (singular || nhi < 1) break;
+      khi = nhi;
+      klo = nlo;
     }
     if (singular) {
       st = SGCM_BVP_SINGULAR;
       if (it < 0) it = 0;
       break;
     }
-    if (zhi >= 1) flush_z(1);
 
-    // ---- forward pass; the step goes into R ----
-    wave_mem_sync();  // interval solutions Z visible to every lane
-    if (lane < 6) {
-      const double d = -sh.F0[lane];
-      sh.dx[0][lane] = d;
-      R[lane] = d;
-    }
-    double zr[kZPer];
-    auto zload = [&](int c0) {
-      const int lane = opaque_lane(lane0);
+    // ---- forward pass dx_0 = -F_0, dx_k = G_k dx_{k-1} + g_k,
+    //      dlambda_{k-1} = P_{k-1} dx_{k-1} + c_{k-1}, dlambda_N = p_w dx_N - F_N;
+    //      the step is added to Y in place ----
+    wave_mem_sync();  // interval solutions visible to every lane
+    double dx[6];
 #pragma unroll
-      for (int t = 0; t < kZPer; ++t) {
-        const int e = lane + 64 * t;
-        if (e < kChunk * 84 && c0 + e / 84 <= N) zr[t] = Zg[(int64_t)(c0 - 1) * 84 + e];
-      }
+    for (int j = 0; j < 6; ++j) dx[j] = -sh.F0[j];
+    if (lane < 6) Y[lane] += dx[lane < 6 ? lane : 0];
+    // chunk [c0, c0 + kFwd) of interval solutions and Y rows c0 - 1 .. c0 + kFwd - 1
+    // into buffer bf, direct to LDS
+    auto fwd_load = [&](int c0, int bf) {
+      const int l = opaque_lane(lane0);
+      const int nk = (N - c0 + 1) < kFwd ? (N - c0 + 1) : kFwd;
+      double* zb = sh.u.fwd + bf * kFwdBuf;
+      const double* zs = Zg + (int64_t)(c0 - 1) * kZI;
+#pragma unroll
+      for (int j = 0; j < kFwd * kZI / 128; ++j)
+        if (64 * j + l < nk * (kZI / 2)) g2lds16(zs + 128 * j + 2 * l, zb + 128 * j);
+      const double* ys = Y + 12 * (int64_t)(c0 - 1);
+#pragma unroll
+      for (int j = 0; j < (kFwdY + 127) / 128; ++j)
+        if (64 * j + l < 6 * (nk + 1)) g2lds16(ys + 128 * j + 2 * l, zb + kFwd * kZI + 128 * j);
     };
-    zload(1);
-    int cur = 0;
-    for (int c0 = 1; c0 <= N; c0 += kChunk) {
-      const int lane = opaque_lane(lane0);
+    fwd_load(1, 0);
+    int bf = 0;
+    for (int c0 = 1; c0 <= N; c0 += kFwd) {
+      wave_mem_sync();  // this chunk has landed
+      if (c0 + kFwd <= N) fwd_load(c0 + kFwd, bf ^ 1);
+      const int l = opaque_lane(lane0);
+      const int r = l < 12 ? l : 11;
+      const double* zb = sh.u.fwd + bf * kFwdBuf;
+      // lane r < 12 owns row r: dx_k (r < 6) or dlambda_{k-1} (r >= 6)
+      const int yo = kFwd * kZI + (r < 6 ? 12 : 0) + r;
+      const int nk = (N - c0 + 1) < kFwd ? (N - c0 + 1) : kFwd;
+      double zn[8], yn;
+      auto rd = [&](int s) {
 #pragma unroll
-      for (int t = 0; t < kZPer; ++t) {
-        const int e = lane + 64 * t;
-        if (e < kChunk * 84 && c0 + e / 84 <= N) {
-          const int kl = e / 84, rem = e % 84;
-          sh.u.zst[kl * kZInt + (rem / 7) * kZRow + rem % 7] = zr[t];
+        for (int q = 0; q < 4; ++q) {
+          const dbl2 v = *reinterpret_cast<const dbl2*>(&zb[s * kZI + r * 8 + 2 * q]);
+          zn[2 * q] = v.x;
+          zn[2 * q + 1] = v.y;
         }
-      }
-      wave_lds_sync();
-      if (c0 + kChunk <= N) zload(c0 + kChunk);
-      const int nk = (N - c0 + 1) < kChunk ? (N - c0 + 1) : kChunk;
-      for (int kl = 0; kl < nk; ++kl) {
-        if (lane < 12) {
-          const double* zrow = sh.u.zst + kl * kZInt + lane * kZRow;
-          double v = zrow[6];
+        yn = zb[yo + 12 * s];
+      };
+      rd(0);
+      for (int s = 0; s < nk; ++s) {
+        double z[8];
 #pragma unroll
-          for (int j = 0; j < 6; ++j) v = fma(zrow[j], sh.dx[cur][j], v);
-          if (lane < 6) {
-            sh.dx[cur ^ 1][lane] = v;
-            sh.dxs[kl * 6 + lane] = v;        // dx_k
-          } else {
-            sh.dls[kl * 6 + lane - 6] = v;    // dlambda_{k-1}
-          }
-        }
-        wave_lds_sync();
-        cur ^= 1;
+        for (int j = 0; j < 8; ++j) z[j] = zn[j];
+        const double yv = yn;
+        if (s + 1 < nk) rd(s + 1);
+        double v = z[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) v = fma(z[j], dx[j], v);
+        const int k = c0 + s;
+        if (l < 12) Y[12 * (int64_t)(r < 6 ? k : k - 1) + r] = yv + v;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) dx[j] = lane_bcast(v, j);
       }
-      // write out the chunk: dx of points c0..c0+nk-1, dlambda of points c0-1..c0+nk-2
-      for (int e = lane; e < 12 * nk; e += 64) {
-        const int half = e / (6 * nk), q = e % (6 * nk), kl = q / 6, i = q % 6;
-        if (half == 0) R[12 * (int64_t)(c0 + kl) + i] = sh.dxs[kl * 6 + i];
-        else R[12 * (int64_t)(c0 - 1 + kl) + 6 + i] = sh.dls[kl * 6 + i];
-      }
+      bf ^= 1;
     }
-    if (lane < 6) R[12 * (int64_t)N + 6 + lane] = P.pw * sh.dx[cur][lane] - sh.FN[lane];
-    wave_mem_sync();
-    for (int i = lane; i < 12 * NP; i += 64) Y[i] += R[i];
+    if (lane >= 6 && lane < 12) {
+      const int i = lane - 6;
+      double d = -sh.FN[i];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) d = fma(j == i ? P.pw : 0.0, dx[j], d);
+      Y[12 * (int64_t)N + 6 + i] += d;
+    }
     wave_mem_sync();
     ++it;
   }
@@ -814,7 +885,7 @@ int make_bvp_args(const sgcm_problem* p, BvpArgs* a) {
   a->alpha = 0.5 * a->h;
   a->tol = p->tol;
   const int64_t NP = (int64_t)p->N + 1;
-  const int64_t doubles = (12 + 12 + 4) * NP + 84 * (int64_t)p->N;
+  const int64_t doubles = (12 + 12 + 4) * NP + (int64_t)kZI * p->N;
   a->per_bvp = (doubles + 31) / 32 * 32;  // 256-byte multiples
   return SGCM_OK;
 }
