@@ -51,6 +51,8 @@ struct BvpArgs {
   double U[9];   // u* = U lambda_w, U[j][i] = -B[i][j] / (r_w J_i), row-major m x 3
   double q, r, pw, T, h, alpha, tol;
   int64_t per_bvp;  // doubles of workspace per BVP
+  int sinv;         // 1: S_w is invertible and Si holds its inverse
+  double Si[9];
 };
 
 // Phi, A = df/dx and W = -q I - Hessian_x(lambda^T f) at one mesh point.
@@ -226,13 +228,16 @@ __device__ __forceinline__ void g2lds16(const double* src, double* dst) {
   __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
 }
 
+// LDS strides are skewed so that the lanes of one access fall on distinct
+// banks (32 banks of 4 bytes): consecutive point slots start 20 banks apart,
+// columns of K and Q 12 banks apart, rows of [F | H | Gam'] 12 banks apart.
 constexpr int kNB = 8;             // intervals per sweep batch
-constexpr int kPt = 120;           // per point: A (36), W (36), L (36), r (12)
-constexpr int kKc = 80;            // K = [R | B | rho], column-major, columns padded to 8
-constexpr int kFHr = 20;           // row of F (6), H (6), Gam' (7), pad
-constexpr int kCst = kKc + 6 * kFHr;
+constexpr int kPt = 122;           // per point: A (36), W (36), L (36), r (12), pad
+constexpr int kKc = 60;            // K = [R | B | rho], column-major, 6 per column
+constexpr int kFHr = 22;           // row of F (6), H (6), Gam' (7), pad
+constexpr int kCst = kKc + 6 * kFHr + 2;  // per interval, 4 banks apart
 constexpr int kFwd = 12;           // intervals per forward-pass chunk (two chunk buffers)
-constexpr int kZI = 96;            // interval solution: 12 rows padded to 8
+constexpr int kZI = 84;            // interval solution [G g ; P c], row-major 12 x 7
 constexpr int kFwdY = 12 * (kFwd + 1);     // rows of Y a chunk updates
 constexpr int kFwdBuf = kFwd * kZI + kFwdY;
 constexpr int kStage = 256;        // point inputs of one batch: y [9][12], r [9][12], trig [9][4]
@@ -247,10 +252,10 @@ struct __align__(16) SweepShared {
     double pa[2 * 64 * 12];         // residual pass: Phi and y of one 64-point chunk
   } u;
   double stage[kStage];  // point inputs of the next batch (filled by direct global-to-LDS loads)
-  double PR[48];   // [P | c] rows (c in column 6), 8 per row
-  double QC[80];   // columns of Q, 8 per column
-  double TT[40];   // columns of T = (Q + E) rate rows, 4 per column
-  double ER[24];   // rows of E[:, 6..8], 4 per row
+  double PR[60];   // [P | c] rows (c in column 6), 10 per row
+  double QC[60];   // columns of Q, 6 per column
+  double TT[30];   // columns of T = (Q + E) rate rows, 3 per column
+  double ER[18];   // rows of E[:, 6..8], 3 per row
   double carry_phi[12], carry_y[12];
   double xb[6], F0[6], FN[6];
   double zero[8];
@@ -356,53 +361,6 @@ __device__ __forceinline__ void point_blocks(const BvpArgs& P, const double (&y)
   }
 }
 
-// One column task of the interval constants: out = u1 x1 + M (u2 x2), with M
-// = L_k (tasks 0..11) or L_{k-1}^T (tasks 12..31), x1 and x2 6-vectors read
-// from LDS with a stride, out written with a stride.  Tasks: 0..9 columns of
-// K = L_k [I + a A_{k-1} | a e_rates | -r^x]; 12..17 columns of
-// F = L_{k-1}^T (I + a A_k^T); 18: -D^{-1} r^l; 19..24 columns of
-// H = a L_{k-1}^T W_k; 25..30 columns of Gam = a L_{k-1}^T W_{k-1};
-// 10, 11, 31 are empty (dst < 0).
-struct ColTask {
-  int x1, s1, x2, s2, dst, ds;
-  double u1, u2;
-};
-
-__device__ __forceinline__ ColTask col_task(int tau, int pa, int pb, int cst, int zero, double alpha) {
-  ColTask c;
-  c.x1 = zero; c.s1 = 0; c.u1 = 0.0;
-  c.x2 = zero; c.s2 = 0; c.u2 = 0.0;
-  c.dst = -1; c.ds = 1;
-  if (tau < 6) {
-    c.x1 = pb + 72 + tau; c.s1 = 6; c.u1 = 1.0;
-    c.x2 = pa + tau; c.s2 = 6; c.u2 = alpha;
-    c.dst = cst + tau * 8;
-  } else if (tau < 9) {
-    c.x1 = pb + 72 + tau - 3; c.s1 = 6; c.u1 = alpha;
-    c.dst = cst + tau * 8;
-  } else if (tau == 9) {
-    c.x2 = pb + 108; c.s2 = 1; c.u2 = -1.0;
-    c.dst = cst + 72;
-  } else if (tau >= 12 && tau < 18) {
-    const int j = tau - 12;
-    c.x1 = pa + 72 + 6 * j; c.s1 = 1; c.u1 = 1.0;
-    c.x2 = pb + 6 * j; c.s2 = 1; c.u2 = alpha;
-    c.dst = cst + kKc + j; c.ds = kFHr;
-  } else if (tau == 18) {
-    c.x2 = pb + 114; c.s2 = 1; c.u2 = -1.0;
-    c.dst = cst + kKc + 18; c.ds = kFHr;
-  } else if (tau >= 19 && tau < 25) {
-    const int j = tau - 19;
-    c.x2 = pb + 36 + j; c.s2 = 6; c.u2 = alpha;
-    c.dst = cst + kKc + 6 + j; c.ds = kFHr;
-  } else if (tau >= 25 && tau < 31) {
-    const int j = tau - 25;
-    c.x2 = pa + 36 + j; c.s2 = 6; c.u2 = alpha;
-    c.dst = cst + kKc + 12 + j; c.ds = kFHr;
-  }
-  return c;
-}
-
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_newton(
     BvpArgs P, const double* __restrict__ x0, double* __restrict__ lam0, double* __restrict__ u0,
     double* __restrict__ Vout, double* __restrict__ traj, int32_t* __restrict__ status,
@@ -504,12 +462,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
     if (lane == 0) sh.flag = 0;
     lds_handoff();
-    // chain state: lane (i, o), o in 0..5 and 9, holds [P_k | c_k][i][o]
+    // chain state: lane (i, o), o in 0..5 and 9, holds [P_k | c_k][i][o];
+    // P_N = p_w I, c_N = -F_N
     double pv;
     {
       const int l = opaque_lane(lane0);
-      const int ci = l < 60 ? l / 10 : 5, co = l < 60 ? l % 10 : 0;
-      pv = (co < 6) ? (ci == co ? P.pw : 0.0) : -sh.FN[ci];
+      const int i = l < 60 ? l / 10 : 5, o = l < 60 ? l - 10 * i : 0;
+      pv = (o < 6) ? (o == i ? P.pw : 0.0) : -sh.FN[i];
     }
     // point inputs (y, r, trig) of points [lo - 1, hi] into the LDS stage;
     // rows are contiguous in global memory, 16 bytes per lane
@@ -553,39 +512,90 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         singular = true;
         break;
       }
-      // interval constants: lane (interval tl, part), four column tasks each
+      // interval constants of interval k = khi - tl, lane (tl, rows i and i + 3):
+      // rows of K = L_k [I + a A_{k-1} | a e_rates | -r^x], F = L_{k-1}^T (I + a A_k^T),
+      // H = a L_{k-1}^T W_k, Gam = a L_{k-1}^T W_{k-1} and -D^{-1} r^l = -L_{k-1}^T r^l.
+      // Every LDS access is an immediate offset from a per-lane base.
       {
         const int l = opaque_lane(lane0);
-        const int tl = l >> 3, part = l & 7;
-        if (tl < nb) {
+        const int tl = l & 7, ip = l >> 3;
+        if (ip < 3 && tl < nb) {
           const int k = khi - tl;
-          const int pa = SGCM_OFF(u.b.pts) + (k - klo) * kPt;  // point k - 1
-          const int pb = pa + kPt;                              // point k
-          const int cst = SGCM_OFF(u.b.cst) + tl * kCst;
-          const bool lk = part < 3;
-          const int mb = (lk ? pb : pa) + 72, msi = lk ? 6 : 1, msm = lk ? 1 : 6;
-          double M[36];
+          const double* pa = sh.u.b.pts + (k - klo) * kPt;  // point k - 1
+          const double* pb = pa + kPt;                       // point k
+          double* cst = sh.u.b.cst + tl * kCst;
+          double lb[2][6], la[2][6];  // rows i, i + 3 of L_k and of L_{k-1}^T
 #pragma unroll
-          for (int i = 0; i < 6; ++i)
-#pragma unroll
-            for (int m = 0; m < 6; ++m) M[i * 6 + m] = Bs[mb + i * msi + m * msm];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const ColTask ct = col_task(part * 4 + c, pa, pb, cst, SGCM_OFF(zero), alpha);
-            double x1[6], v[6];
+          for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int m = 0; m < 6; ++m) {
-              x1[m] = ct.u1 * Bs[ct.x1 + m * ct.s1];
-              v[m] = ct.u2 * Bs[ct.x2 + m * ct.s2];
+              lb[h][m] = pb[72 + (ip + 3 * h) * 6 + m];
+              la[h][m] = pa[72 + m * 6 + ip + 3 * h];
             }
-            if (ct.dst >= 0) {
+          double* kc = cst + ip;              // K[i][o] at kc[o * 6 + 3 h]
+          double* fh = cst + kKc + ip * kFHr;  // row i of [F | H | Gam'] at fh[3 h kFHr + j]
 #pragma unroll
-              for (int i = 0; i < 6; ++i) {
-                double o = x1[i];
+          for (int o = 0; o < 6; ++o) {
+            double v[6];
 #pragma unroll
-                for (int m = 0; m < 6; ++m) o = fma(M[i * 6 + m], v[m], o);
-                Bs[ct.dst + i * ct.ds] = o;
+            for (int m = 0; m < 6; ++m) v[m] = pa[m * 6 + o];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              double q = 0.0;
+#pragma unroll
+              for (int m = 0; m < 6; ++m) q = fma(lb[h][m], v[m], q);
+              kc[o * 6 + 3 * h] = fma(alpha, q, lb[h][o]);
+            }
+          }
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) kc[(6 + c) * 6 + 3 * h] = alpha * lb[h][3 + c];
+          {
+            double v[6];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) v[m] = pb[108 + m];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              double q = 0.0;
+#pragma unroll
+              for (int m = 0; m < 6; ++m) q = fma(lb[h][m], v[m], q);
+              kc[54 + 3 * h] = -q;
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < 6; ++j) {
+            double vf[6], vh[6], vg[6];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+              vf[m] = pb[j * 6 + m];        // A_k[j][m]
+              vh[m] = pb[36 + m * 6 + j];   // W_k[m][j]
+              vg[m] = pa[36 + m * 6 + j];   // W_{k-1}[m][j]
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              double qf = 0.0, qh = 0.0, qg = 0.0;
+#pragma unroll
+              for (int m = 0; m < 6; ++m) {
+                qf = fma(la[h][m], vf[m], qf);
+                qh = fma(la[h][m], vh[m], qh);
+                qg = fma(la[h][m], vg[m], qg);
               }
+              fh[3 * h * kFHr + j] = fma(alpha, qf, la[h][j]);
+              fh[3 * h * kFHr + 6 + j] = alpha * qh;
+              fh[3 * h * kFHr + 12 + j] = alpha * qg;
+            }
+          }
+          {
+            double v[6];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) v[m] = pb[114 + m];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              double q = 0.0;
+#pragma unroll
+              for (int m = 0; m < 6; ++m) q = fma(la[h][m], v[m], q);
+              fh[3 * h * kFHr + 18] = -q;
             }
           }
         }
@@ -595,42 +605,63 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       const int nhi = klo - 1;
       const int nlo = nhi - (kNB - 1) < 1 ? 1 : nhi - (kNB - 1);
       if (nhi >= 1) load_points(nlo, nhi);
-      // the serial chain: three LDS exchanges per interval
-      for (int t = 0; t < nb; ++t) {
-        const int k = khi - t;
+      // the serial chain: three LDS exchanges per interval.  Lane (i, o),
+      // 60 lanes, owns entry (i, o) of the step; columns o = 0..5 (R), 6..8
+      // (B) and 9 (rho) of [K ; e_9]; the state columns 0..5 and 9 carry
+      // [P | c] (slot 6 for column 9).  The constants of interval t + 1 are
+      // read while interval t finishes.
+      int ci, co, cs;
+      bool cv, cst_lane;
+      {
         const int l = opaque_lane(lane0);
-        const bool cv = l < 60;
-        const int ci = cv ? l / 10 : 5, co = cv ? l % 10 : 0;
-        const bool cst_lane = cv && (co < 6 || co == 9);
-        const int cs = co < 6 ? co : 6;
-        const int c0 = SGCM_OFF(u.b.cst) + t * kCst;
-        // exchange 1: rows of [P_k | c_k]
-        if (cst_lane) sh.PR[ci * 8 + cs] = pv;
-        lds_handoff();
-        double prow[7], kcol[6], fh[12], kb[3];
+        cv = l < 60;
+        ci = cv ? l / 10 : 5;
+        co = cv ? l - 10 * ci : 0;
+        cst_lane = cv && (co < 6 || co == 9);
+        cs = co < 6 ? co : 6;
+      }
+      double kcol[6], fh[12], kb[3], gam, kio;
+      auto load_consts = [&](int t) {
+        const double* cst = sh.u.b.cst + t * kCst;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          const dbl2 v = *reinterpret_cast<const dbl2*>(&sh.PR[ci * 8 + 2 * q]);
-          prow[2 * q] = v.x;
-          prow[2 * q + 1] = v.y;
-        }
-        prow[6] = sh.PR[ci * 8 + 6];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const dbl2 v = *reinterpret_cast<const dbl2*>(&Bs[c0 + co * 8 + 2 * q]);
+          const dbl2 v = *reinterpret_cast<const dbl2*>(&cst[co * 6 + 2 * q]);
           kcol[2 * q] = v.x;
           kcol[2 * q + 1] = v.y;
         }
+        const double* fr = cst + kKc + ci * kFHr;
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-          const dbl2 v = *reinterpret_cast<const dbl2*>(&Bs[c0 + kKc + ci * kFHr + 2 * q]);
+          const dbl2 v = *reinterpret_cast<const dbl2*>(&fr[2 * q]);
           fh[2 * q] = v.x;
           fh[2 * q + 1] = v.y;
         }
-        const double gam = Bs[cst_lane ? c0 + kKc + ci * kFHr + 12 + cs : SGCM_OFF(zero)];
-        const double kio = Bs[c0 + co * 8 + ci];
+        gam = cst_lane ? fr[12 + cs] : 0.0;
+        kio = cst[co * 6 + ci];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) kb[a] = Bs[c0 + (6 + a) * 8 + ci];
+        for (int a = 0; a < 3; ++a) kb[a] = cst[(6 + a) * 6 + ci];
+      };
+      // S_w^{-1} in VGPRs: it is added to T1, which arrives in SGPRs
+      double siv[9];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) {
+        siv[e] = P.Si[e];
+        asm volatile("" : "+v"(siv[e]));
+      }
+      load_consts(0);
+      for (int t = 0; t < nb; ++t) {
+        const int k = khi - t;
+        // exchange 1: rows of [P_k | c_k]
+        if (cst_lane) sh.PR[ci * 10 + cs] = pv;
+        lds_handoff();
+        double prow[7];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const dbl2 v = *reinterpret_cast<const dbl2*>(&sh.PR[ci * 10 + 2 * q]);
+          prow[2 * q] = v.x;
+          prow[2 * q + 1] = v.y;
+        }
+        prow[6] = sh.PR[ci * 10 + 6];
         // Q = [P | c] [K ; e_9],  C = H K + [Gam | 0 | -D^{-1} r^l]
         double q = co == 9 ? prow[6] : 0.0;
         double cc = gam;
@@ -640,12 +671,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
           cc = fma(fh[6 + m], kcol[m], cc);
         }
         // exchange 2: columns of Q
-        if (cv) sh.QC[co * 8 + ci] = q;
+        if (cv) sh.QC[co * 6 + ci] = q;
         lds_handoff();
         double qcol[6];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-          const dbl2 v = *reinterpret_cast<const dbl2*>(&sh.QC[co * 8 + 2 * r]);
+          const dbl2 v = *reinterpret_cast<const dbl2*>(&sh.QC[co * 6 + 2 * r]);
           qcol[2 * r] = v.x;
           qcol[2 * r + 1] = v.y;
         }
@@ -653,54 +684,67 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
         for (int m = 0; m < 6; ++m) e = fma(fh[m], qcol[m], e);
         const double tv = q + e;  // T = Psi_w [K ; e_9] on the rate rows
+        const double kio_t = kio, kb0 = kb[0], kb1 = kb[1], kb2 = kb[2];
         // exchange 3: columns of T, rows of E[:, 6..8]; T[:, 6..8] to every lane
-        if (cv && ci >= 3) sh.TT[co * 4 + ci - 3] = tv;
-        if (cv && co >= 6 && co <= 8) sh.ER[ci * 4 + co - 6] = e;
+        if (cv && ci >= 3) sh.TT[co * 3 + ci - 3] = tv;
+        if (cv && co >= 6 && co <= 8) sh.ER[ci * 3 + co - 6] = e;
         double t1[9];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
           for (int c = 0; c < 3; ++c) t1[a * 3 + c] = lane_bcast(tv, (3 + a) * 10 + 6 + c);
         lds_handoff();
-        const dbl2 tc01 = *reinterpret_cast<const dbl2*>(&sh.TT[co * 4]);
-        const double tc2 = sh.TT[co * 4 + 2];
-        const dbl2 er01 = *reinterpret_cast<const dbl2*>(&sh.ER[ci * 4]);
-        const double er2 = sh.ER[ci * 4 + 2];
-        // Z3 = I + S_w T[:, 6..8]; its adjugate and determinant
-        double z[9];
+        double tc[3], er[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a) {
+          tc[a] = sh.TT[co * 3 + a];
+          er[a] = sh.ER[ci * 3 + a];
+        }
+        if (t + 1 < nb) load_consts(t + 1);
+        // the 3 x 3 system Z M = W: Z = S_w^{-1} + T[:, 6..8], W = T when S_w
+        // is invertible, else Z = I + S_w T[:, 6..8], W = S_w T; M by the
+        // adjugate of Z
+        double z[9], w[3];
+        if (P.sinv) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            double s = (a == c) ? 1.0 : 0.0;
+          for (int e2 = 0; e2 < 9; ++e2) z[e2] = siv[e2] + t1[e2];
 #pragma unroll
-            for (int m = 0; m < 3; ++m) s = fma(P.Sw[a * 3 + m], t1[m * 3 + c], s);
-            z[a * 3 + c] = s;
-          }
+          for (int a = 0; a < 3; ++a) w[a] = tc[a];
+        } else {
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              double s = (a == c) ? 1.0 : 0.0;
+#pragma unroll
+              for (int m = 0; m < 3; ++m) s = fma(P.Sw[a * 3 + m], t1[m * 3 + c], s);
+              z[a * 3 + c] = s;
+            }
+#pragma unroll
+          for (int a = 0; a < 3; ++a) w[a] = fma(P.Sw[a * 3 + 0], tc[0], fma(P.Sw[a * 3 + 1], tc[1], P.Sw[a * 3 + 2] * tc[2]));
+        }
         const double j00 = z[4] * z[8] - z[5] * z[7], j01 = z[2] * z[7] - z[1] * z[8], j02 = z[1] * z[5] - z[2] * z[4];
         const double j10 = z[5] * z[6] - z[3] * z[8], j11 = z[0] * z[8] - z[2] * z[6], j12 = z[2] * z[3] - z[0] * z[5];
         const double j20 = z[3] * z[7] - z[4] * z[6], j21 = z[1] * z[6] - z[0] * z[7], j22 = z[0] * z[4] - z[1] * z[3];
         const double det = z[0] * j00 + z[1] * j10 + z[2] * j20;
         if (det == 0.0) singular = true;
-        // y = adj(Z3) S_w T[:, o]; [M | m][:, o] = y / det
-        const double tc[3] = {tc01.x, tc01.y, tc2};
-        double w[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) w[a] = fma(P.Sw[a * 3 + 0], tc[0], fma(P.Sw[a * 3 + 1], tc[1], P.Sw[a * 3 + 2] * tc[2]));
+        // 1/det: hardware reciprocal estimate refined by two Newton steps
+        // (det is O(1) here: no scaling is needed)
+        double rd = __builtin_amdgcn_rcp(det);
+        rd = fma(rd, fma(-det, rd, 1.0), rd);
+        rd = fma(rd, fma(-det, rd, 1.0), rd);
+        // y = adj(Z) W[:, o]; [M | m][:, o] = y / det
         const double y0 = fma(j00, w[0], fma(j01, w[1], j02 * w[2]));
         const double y1 = fma(j10, w[0], fma(j11, w[1], j12 * w[2]));
         const double y2 = fma(j20, w[0], fma(j21, w[1], j22 * w[2]));
-        const double rd = 1.0 / det;
         // P_{k-1} = E - E[:, 6..8] M, c_{k-1} = E[:, 9] - E[:, 6..8] m,
         // G_k = K - B_k M, g_k = rho - B_k m
-        const double ey = fma(er01.x, y0, fma(er01.y, y1, er2 * y2));
-        const double ky = fma(kb[0], y0, fma(kb[1], y1, kb[2] * y2));
-        const double pn = fma(-rd, ey, e);
-        const double gn = fma(-rd, ky, kio);
+        const double pn = fma(-rd, fma(er[0], y0, fma(er[1], y1, er[2] * y2)), e);
+        const double gn = fma(-rd, fma(kb0, y0, fma(kb1, y1, kb2 * y2)), kio_t);
         if (cst_lane) {
           double* zk = Zg + (int64_t)(k - 1) * kZI;
-          zk[ci * 8 + cs] = gn;
-          zk[(6 + ci) * 8 + cs] = pn;
+          zk[ci * 7 + cs] = gn;
+          zk[(6 + ci) * 7 + cs] = pn;
         }
         pv = pn;
         if (singular) break;
@@ -731,7 +775,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       double* zb = sh.u.fwd + bf * kFwdBuf;
       const double* zs = Zg + (int64_t)(c0 - 1) * kZI;
 #pragma unroll
-      for (int j = 0; j < kFwd * kZI / 128; ++j)
+      for (int j = 0; j < (kFwd * kZI + 127) / 128; ++j)
         if (64 * j + l < nk * (kZI / 2)) g2lds16(zs + 128 * j + 2 * l, zb + 128 * j);
       const double* ys = Y + 12 * (int64_t)(c0 - 1);
 #pragma unroll
@@ -749,21 +793,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       // lane r < 12 owns row r: dx_k (r < 6) or dlambda_{k-1} (r >= 6)
       const int yo = kFwd * kZI + (r < 6 ? 12 : 0) + r;
       const int nk = (N - c0 + 1) < kFwd ? (N - c0 + 1) : kFwd;
-      double zn[8], yn;
+      double zn[7], yn;
       auto rd = [&](int s) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const dbl2 v = *reinterpret_cast<const dbl2*>(&zb[s * kZI + r * 8 + 2 * q]);
-          zn[2 * q] = v.x;
-          zn[2 * q + 1] = v.y;
-        }
+        for (int j = 0; j < 7; ++j) zn[j] = zb[s * kZI + r * 7 + j];
         yn = zb[yo + 12 * s];
       };
       rd(0);
       for (int s = 0; s < nk; ++s) {
-        double z[8];
+        double z[7];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) z[j] = zn[j];
+        for (int j = 0; j < 7; ++j) z[j] = zn[j];
         const double yv = yn;
         if (s + 1 < nk) rd(s + 1);
         double v = z[6];
@@ -884,6 +924,31 @@ int make_bvp_args(const sgcm_problem* p, BvpArgs* a) {
   a->h = p->T / p->N;
   a->alpha = 0.5 * a->h;
   a->tol = p->tol;
+  // With three independent controls S_w is invertible and the 3 x 3 system of
+  // a sweep step, (I + S_w T1) M = S_w T, is solved as (S_w^{-1} + T1) M = T.
+  a->sinv = 0;
+  if (p->m == 3) {
+    const double* S = a->Sw;
+    const double c00 = S[4] * S[8] - S[5] * S[7], c01 = S[5] * S[6] - S[3] * S[8], c02 = S[3] * S[7] - S[4] * S[6];
+    const double det = S[0] * c00 + S[1] * c01 + S[2] * c02;
+    double nrm = 0.0;
+    for (int e = 0; e < 9; ++e) nrm = std::fmax(nrm, std::fabs(S[e]));
+    if (std::isfinite(det) && std::fabs(det) > 1e-6 * nrm * nrm * nrm) {
+      const double r = 1.0 / det;
+      a->Si[0] = c00 * r;
+      a->Si[1] = (S[2] * S[7] - S[1] * S[8]) * r;
+      a->Si[2] = (S[1] * S[5] - S[2] * S[4]) * r;
+      a->Si[3] = c01 * r;
+      a->Si[4] = (S[0] * S[8] - S[2] * S[6]) * r;
+      a->Si[5] = (S[2] * S[3] - S[0] * S[5]) * r;
+      a->Si[6] = c02 * r;
+      a->Si[7] = (S[1] * S[6] - S[0] * S[7]) * r;
+      a->Si[8] = (S[0] * S[4] - S[1] * S[3]) * r;
+      a->sinv = 1;
+    }
+  }
+  if (!a->sinv)
+    for (int e = 0; e < 9; ++e) a->Si[e] = 0.0;
   const int64_t NP = (int64_t)p->N + 1;
   const int64_t doubles = (12 + 12 + 4) * NP + (int64_t)kZI * p->N;
   a->per_bvp = (doubles + 31) / 32 * 32;  // 256-byte multiples
