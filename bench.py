@@ -39,6 +39,28 @@ FLOPS_PER_INTERVAL_SOLVE = 1098 + 1152 + 2016 + 156
 FLOPS_PER_POINT_EVAL = 172 + 48
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_newton_full_L4_N256_counters.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1507_04769_amd", "csrc", "bvp.hip")
+
+
+def measured_traffic() -> float | None:
+    """HBM bytes per k_newton launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel source has changed since the counters
+    were taken (the summary records the sha256 of the profiled source)."""
+    import hashlib
+    import re
+    try:
+        text = open(COUNTERS_FILE).read()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    h = re.search(r"sha256: ([0-9a-f]{64})", text)
+    t = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+)", text)
+    if not h or not t or h.group(1) != src:
+        return None
+    return float(t.group(1))
+
+
 def newton_flops(N: int, iters: np.ndarray) -> float:
     """Algorithmic flops of one sgcm_solve_bvps launch: (iters + 1) linear
     solves (the first is the linearised step) and (iters + 2) evaluations."""
@@ -197,7 +219,8 @@ def main():
         "wall_s_timed": wall,
         "roofline": {"kernel": "k_newton (sgcm_solve_bvps)", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": None, "algorithmic_flops_per_launch": flops},
+                     "traffic": measured_traffic() if wl.name == W.FULL.name else None,
+                     "algorithmic_flops_per_launch": flops},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, nodes, xq_host)
