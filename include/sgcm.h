@@ -18,7 +18,8 @@
  *     returns SGCM_EDEVICE.
  *   - Pointers documented as "device" must point to device memory of the
  *     current HIP device (or be NULL where allowed).  The caller owns every
- *     device buffer and the stream; the library owns only sgcm_grid objects.
+ *     device buffer and the stream; the library owns only sgcm_grid and
+ *     sgcm_batch objects.
  *   - Calls on a stream are stream-ordered and do not synchronise the host.
  *     "stream" is a hipStream_t passed as void*; NULL means the null stream.
  *   - Arrays are row-major and densely packed unless stated otherwise.
@@ -133,6 +134,47 @@ int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const double* x0,
  *   dphi  device, n_points x 12 x 12 (row-major d phi_i / d y_j), or NULL. */
 int sgcm_characteristic_rhs(const sgcm_problem* p, int64_t n_points, const double* y,
                             double* phi, double* dphi, void* stream);
+
+/* ---- batches of BVPs with mixed meshes and horizons --------------------- */
+
+/* Plan for n_bvps BVPs of one problem whose mesh size N and horizon T differ
+ * per BVP (the problem's own N and T are ignored).  The plan holds device
+ * tables (per-BVP N and mesh width, workspace offsets, the processing order
+ * and a work counter) on the device current at creation, so that
+ * sgcm_solve_bvps_batch allocates nothing and can be captured in a HIP graph.
+ * Created and destroyed on the host; not thread-safe to use concurrently on
+ * two streams (the persistent schedule shares one counter). */
+typedef struct sgcm_batch sgcm_batch;
+
+/* Schedule of a batch:
+ *   order:        0 = BVPs in the given order; 1 = larger N * T first
+ *   slots_per_cu: 0 = one workgroup per BVP; 1..8 = one persistent launch of
+ *                 slots_per_cu workgroups per compute unit, each taking the
+ *                 next BVP of the order from a device work counter. */
+typedef struct sgcm_schedule {
+  int32_t order;
+  int32_t slots_per_cu;
+} sgcm_schedule;
+
+/* N, T: host arrays of n_bvps (>= 1) mesh sizes (1..65536) and horizons
+ * (finite, > 0); sched: NULL for {order 1, slots_per_cu 0}.  On success *out
+ * owns device memory of about 24 bytes per BVP on the current device. */
+int sgcm_batch_create(const sgcm_problem* p, int64_t n_bvps, const int32_t* N, const double* T,
+                      const sgcm_schedule* sched, sgcm_batch** out);
+
+/* Bytes of device workspace sgcm_solve_bvps_batch needs. */
+int sgcm_batch_workspace(const sgcm_batch* b, size_t* bytes);
+
+/* Solve every BVP of the plan from x0 (device, n_bvps x 6); outputs as in
+ * sgcm_solve_bvps (lambda0 n x 6, u0 n x m, V n or NULL, status n, iters n,
+ * indexed in the given order), without trajectories.  workspace: at least
+ * sgcm_batch_workspace() bytes, 256-byte aligned.  Must be called with the
+ * plan's device current.  Results do not depend on the schedule. */
+int sgcm_solve_bvps_batch(const sgcm_batch* b, const double* x0, double* lambda0, double* u0,
+                          double* V, int32_t* status, int32_t* iters, void* workspace,
+                          size_t ws_bytes, void* stream);
+
+void sgcm_batch_destroy(sgcm_batch* b);
 
 /* ---- sparse grid (Sec. 3.2) --------------------------------------------- */
 

@@ -28,7 +28,8 @@ FP64, FP32 = 0, 1
 
 # every extern "C" symbol declared in include/sgcm.h
 EXPORTS = ("sgcm_strerror", "sgcm_version", "sgcm_solve_bvps_workspace", "sgcm_solve_bvps",
-           "sgcm_characteristic_rhs", "sgcm_grid_create", "sgcm_grid_size", "sgcm_grid_nodes",
+           "sgcm_characteristic_rhs", "sgcm_batch_create", "sgcm_batch_workspace", "sgcm_solve_bvps_batch",
+           "sgcm_batch_destroy", "sgcm_grid_create", "sgcm_grid_size", "sgcm_grid_nodes",
            "sgcm_grid_keys", "sgcm_grid_destroy", "sgcm_build_interpolant", "sgcm_eval_feedback")
 
 
@@ -82,6 +83,10 @@ class Problem:
 _lib = None
 
 
+class _CSchedule(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("slots_per_cu", ctypes.c_int32)]
+
+
 def lib() -> ctypes.CDLL:
     """The loaded libsgcm.so; raises if it has not been built."""
     global _lib
@@ -99,6 +104,10 @@ def lib() -> ctypes.CDLL:
         "sgcm_solve_bvps_workspace": (ctypes.c_int, [P, i64, ctypes.POINTER(ctypes.c_size_t)]),
         "sgcm_solve_bvps": (ctypes.c_int, [P, i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
         "sgcm_characteristic_rhs": (ctypes.c_int, [P, i64, vp, vp, vp, vp]),
+        "sgcm_batch_create": (ctypes.c_int, [P, i64, vp, vp, ctypes.POINTER(_CSchedule), ctypes.POINTER(vp)]),
+        "sgcm_batch_workspace": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "sgcm_solve_bvps_batch": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
+        "sgcm_batch_destroy": (None, [vp]),
         "sgcm_grid_create": (ctypes.c_int, [i32, i32, vp, vp, ctypes.POINTER(vp)]),
         "sgcm_grid_size": (i64, [vp]),
         "sgcm_grid_nodes": (ctypes.c_int, [vp, vp]),
@@ -192,6 +201,59 @@ def sgcm_characteristic_rhs(problem: Problem, y, phi, dphi=None, stream=None):
                                        _ptr(phi, torch.float64, "phi", 12 * n),
                                        _ptr(dphi, torch.float64, "dphi", 144 * n), _stream(stream))
     _check(rc, "sgcm_characteristic_rhs")
+
+
+ORDER_GIVEN, ORDER_LONGEST_FIRST = 0, 1
+
+
+class Batch:
+    """sgcm_batch: a plan for BVPs of one problem with per-BVP mesh size N and
+    horizon T (the problem's own N and T are ignored), owned by libsgcm."""
+
+    def __init__(self, problem: Problem, N, T, order: int = ORDER_LONGEST_FIRST, slots_per_cu: int = 0):
+        N = np.ascontiguousarray(N, dtype=np.int32).reshape(-1)
+        T = np.ascontiguousarray(T, dtype=np.float64).reshape(-1)
+        if N.shape != T.shape:
+            raise ValueError("N and T must have the same length")
+        self.n, self.N, self.T = int(N.size), N, T
+        self.m = int(problem.m)
+        self.schedule = (int(order), int(slots_per_cu))
+        h = ctypes.c_void_p()
+        sc = _CSchedule(int(order), int(slots_per_cu))
+        _check(lib().sgcm_batch_create(ctypes.byref(problem.c()), self.n, N.ctypes.data_as(ctypes.c_void_p),
+                                       T.ctypes.data_as(ctypes.c_void_p), ctypes.byref(sc), ctypes.byref(h)),
+               "sgcm_batch_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace_bytes(self) -> int:
+        out = ctypes.c_size_t(0)
+        _check(lib().sgcm_batch_workspace(self._h, ctypes.byref(out)), "sgcm_batch_workspace")
+        return int(out.value)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.sgcm_batch_destroy(h)
+            self._h = None
+
+
+def sgcm_solve_bvps_batch(batch: Batch, x0, lambda0, u0, V, status, iters, workspace, stream=None):
+    import torch
+    f64, i32 = torch.float64, torch.int32
+    n, m = batch.n, batch.m
+    if x0.dim() != 2 or x0.shape[1] != 6 or x0.shape[0] != n:
+        raise ValueError("x0 must be n x 6 with n = %d" % n)
+    ws_bytes = workspace.numel() * workspace.element_size()
+    rc = lib().sgcm_solve_bvps_batch(batch.handle, _ptr(x0, f64, "x0"), _ptr(lambda0, f64, "lambda0", 6 * n),
+                                     _ptr(u0, f64, "u0", m * n), _ptr(V, f64, "V", n),
+                                     _ptr(status, i32, "status", n), _ptr(iters, i32, "iters", n),
+                                     _ptr(workspace, None, "workspace"), ctypes.c_size_t(ws_bytes),
+                                     _stream(stream))
+    _check(rc, "sgcm_solve_bvps_batch")
 
 
 class Grid:
@@ -297,6 +359,27 @@ def solve_bvps(problem: Problem, x0, want_traj: bool = False, want_V: bool = Tru
         workspace = torch.empty((max(nbytes, 256) + 255) // 256 * 32, dtype=torch.float64, device=dev)
     sgcm_solve_bvps(problem, x0, lam, u0, V, traj, st, it, workspace, stream)
     return BVPSolution(lam, u0, V, traj, st, it)
+
+
+def batch_workspace(batch: Batch, device):
+    import torch
+    nbytes = batch.workspace_bytes()
+    return torch.empty((max(nbytes, 256) + 255) // 256 * 32, dtype=torch.float64, device=device)
+
+
+def solve_bvps_batch(batch: Batch, x0, want_V: bool = True, workspace=None, stream=None) -> BVPSolution:
+    import torch
+    dev = x0.device
+    n = batch.n
+    lam = torch.empty((n, 6), dtype=torch.float64, device=dev)
+    u0 = torch.empty((n, batch.m), dtype=torch.float64, device=dev)
+    V = torch.empty((n,), dtype=torch.float64, device=dev) if want_V else None
+    st = torch.empty((n,), dtype=torch.int32, device=dev)
+    it = torch.empty((n,), dtype=torch.int32, device=dev)
+    if workspace is None:
+        workspace = batch_workspace(batch, dev)
+    sgcm_solve_bvps_batch(batch, x0, lam, u0, V, st, it, workspace, stream)
+    return BVPSolution(lam, u0, V, None, st, it)
 
 
 def characteristic_rhs(problem: Problem, y, jacobian: bool = True, stream=None):

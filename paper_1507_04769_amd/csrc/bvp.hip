@@ -36,7 +36,10 @@
 // Mesh-point work and the residual are lane-parallel over k.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
+#include <new>
+#include <vector>
 
 #include "sgcm_internal.h"
 
@@ -269,8 +272,8 @@ struct __align__(16) SweepShared {
 // A = df/dx, W and L = (I - a A)^{-1} of one mesh point into an LDS slot
 // (row-major 6 x 6 each).  Entries are stored as soon as they are formed so
 // that few values stay live; the structural zeros of A and W are written too.
-__device__ __forceinline__ void point_blocks(const BvpArgs& P, const double (&y)[12], const double (&tr)[4],
-                                             double* slot, int* flag) {
+__device__ __forceinline__ void point_blocks(const BvpArgs& P, const double a, const double (&y)[12],
+                                             const double (&tr)[4], double* slot, int* flag) {
   const double w1 = y[3], w2 = y[4], w3 = y[5];
   const double l1 = y[6], l2 = y[7], l3 = y[8], l4 = y[9], l5 = y[10], l6 = y[11];
   double* A = slot;
@@ -336,7 +339,6 @@ __device__ __forceinline__ void point_blocks(const BvpArgs& P, const double (&y)
       A[i * 6 + 3 + j] = E[i * 3 + j];
       A[(3 + i) * 6 + 3 + j] = Om[i * 3 + j];
     }
-  const double a = P.alpha;
   double M1[9] = {1.0 - a * a00, -a * a01, 0.0, -a * a10, 1.0, 0.0, -a * a20, -a * a21, 1.0};
   double M2[9], Xb[9], Yb[9];
 #pragma unroll
@@ -361,21 +363,22 @@ __device__ __forceinline__ void point_blocks(const BvpArgs& P, const double (&y)
   }
 }
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_newton(
-    BvpArgs P, const double* __restrict__ x0, double* __restrict__ lam0, double* __restrict__ u0,
-    double* __restrict__ Vout, double* __restrict__ traj, int32_t* __restrict__ status,
-    int32_t* __restrict__ iters, double* __restrict__ ws) {
+// Newton's method for one BVP (index b, mesh of N intervals of width h,
+// workspace ws_b) by one 64-lane workgroup.
+__device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const double h, const int64_t b,
+                                           double* ws_b, const double* __restrict__ x0, double* __restrict__ lam0,
+                                           double* __restrict__ u0, double* __restrict__ Vout,
+                                           double* __restrict__ traj, int32_t* __restrict__ status,
+                                           int32_t* __restrict__ iters, SweepShared& sh) {
   const int lane0 = threadIdx.x;
   const int lane = lane0;
-  const int64_t b = blockIdx.x;
-  const int N = P.N, NP = N + 1;
-  const double alpha = P.alpha;
-  double* Y = ws + b * P.per_bvp;      // NP x 12: the iterate
+  const int NP = N + 1;
+  const double alpha = 0.5 * h;
+  double* Y = ws_b;                    // NP x 12: the iterate
   double* R = Y + 12 * (int64_t)NP;    // NP x 12: residuals r_k (row 0 = [F_0, F_N])
   double* TR = R + 12 * (int64_t)NP;   // NP x 4: sin phi, cos phi, tan theta, sec theta
   double* Zg = TR + 4 * (int64_t)NP;   // N x 96: interval solutions, 12 rows of 8
 
-  __shared__ SweepShared sh;
   double* const Bs = reinterpret_cast<double*>(&sh);
   if (lane < 6) sh.xb[lane] = x0[b * 6 + lane];
   if (lane < 8) sh.zero[lane] = 0.0;
@@ -504,7 +507,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
           }
 #pragma unroll
           for (int i = 0; i < 4; ++i) pt[i] = sh.stage[216 + l * 4 + i];
-          point_blocks(P, py, pt, slot, &sh.flag);
+          point_blocks(P, alpha, py, pt, slot, &sh.flag);
         }
       }
       lds_handoff();
@@ -849,7 +852,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       const double* yN = Y + 12 * (int64_t)N;
       double xx = 0.0;
       for (int i = 0; i < 6; ++i) xx += yN[i] * yN[i];
-      Vout[b] = P.h * part + 0.5 * P.pw * xx;
+      Vout[b] = h * part + 0.5 * P.pw * xx;
     }
   }
   if (traj) {
@@ -860,6 +863,52 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     status[b] = st;
     iters[b] = it < 0 ? 0 : it;
   }
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_newton(
+    BvpArgs P, const double* __restrict__ x0, double* __restrict__ lam0, double* __restrict__ u0,
+    double* __restrict__ Vout, double* __restrict__ traj, int32_t* __restrict__ status,
+    int32_t* __restrict__ iters, double* __restrict__ ws) {
+  __shared__ SweepShared sh;
+  const int64_t b = blockIdx.x;
+  newton_bvp(P, P.N, P.h, b, ws + b * P.per_bvp, x0, lam0, u0, Vout, traj, status, iters, sh);
+}
+
+// A batch of BVPs with per-BVP mesh size and horizon.  Plain mode: workgroup
+// g solves BVP order[g].  Persistent mode: each workgroup takes the next
+// position of the schedule from a device counter until the batch is done.
+struct BatchArgs {
+  const int32_t* N;      // per BVP: mesh intervals
+  const double* h;       // per BVP: mesh width T / N
+  const int64_t* off;    // per BVP: workspace offset in doubles
+  const int32_t* order;  // schedule: BVP index at each position
+  int32_t* counter;      // persistent mode: next schedule position
+  int64_t n;
+  int persistent;
+};
+
+__device__ __forceinline__ int64_t next_position(int32_t* counter) {
+  int v = 0;
+  if (threadIdx.x == 0) v = atomicAdd(counter, 1);
+  return __shfl(v, 0);
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_newton_batch(
+    BvpArgs P, BatchArgs B, const double* __restrict__ x0, double* __restrict__ lam0, double* __restrict__ u0,
+    double* __restrict__ Vout, int32_t* __restrict__ status, int32_t* __restrict__ iters,
+    double* __restrict__ ws) {
+  __shared__ SweepShared sh;
+  int64_t pos = B.persistent ? next_position(B.counter) : (int64_t)blockIdx.x;
+  while (pos < B.n) {
+    const int64_t j = B.order[pos];
+    newton_bvp(P, B.N[j], B.h[j], j, ws + B.off[j], x0, lam0, u0, Vout, nullptr, status, iters, sh);
+    if (!B.persistent) break;
+    pos = next_position(B.counter);
+  }
+}
+
+__global__ void k_reset_counter(int32_t* counter) {
+  if (threadIdx.x == 0) *counter = 0;
 }
 
 __global__ __launch_bounds__(256) void k_rhs(BvpArgs P, int64_t n, const double* __restrict__ y,
@@ -999,4 +1048,123 @@ extern "C" int sgcm_characteristic_rhs(const sgcm_problem* p, int64_t n_points, 
   hipLaunchKernelGGL(k_rhs, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a, n_points, y, phi,
                      dphi);
   return hipGetLastError() == hipSuccess ? SGCM_OK : SGCM_EDEVICE;
+}
+
+// ---- batches with per-BVP mesh size and horizon ----------------------------
+
+struct sgcm_batch {
+  BvpArgs args;  // the problem; args.N, args.h, args.per_bvp are unused
+  int64_t n = 0;
+  int dev = -1;
+  int32_t* N = nullptr;
+  double* h = nullptr;
+  int64_t* off = nullptr;
+  int32_t* order = nullptr;
+  int32_t* counter = nullptr;
+  size_t ws_doubles = 0;
+  sgcm_schedule sched{1, 0};
+  int64_t slots = 0;  // persistent workgroups (0: one workgroup per BVP)
+};
+
+extern "C" int sgcm_batch_create(const sgcm_problem* p, int64_t n_bvps, const int32_t* N, const double* T,
+                                 const sgcm_schedule* sched, sgcm_batch** out) {
+  if (!out) return SGCM_EINVAL;
+  *out = nullptr;
+  if (!p || n_bvps < 1 || n_bvps > 0x7fffffffLL || !N || !T) return SGCM_EINVAL;
+  sgcm_schedule sc = sched ? *sched : sgcm_schedule{1, 0};
+  if (sc.order < 0 || sc.order > 1 || sc.slots_per_cu < 0 || sc.slots_per_cu > 8) return SGCM_EINVAL;
+  sgcm_problem q = *p;  // the problem's own mesh and horizon are not used
+  q.N = 1;
+  q.T = 1.0;
+  BvpArgs a;
+  int rc = make_bvp_args(&q, &a);
+  if (rc != SGCM_OK) return rc;
+  std::vector<int32_t> hN(N, N + n_bvps), horder(n_bvps);
+  std::vector<double> hh(n_bvps);
+  std::vector<int64_t> hoff(n_bvps);
+  int64_t total = 0;
+  for (int64_t i = 0; i < n_bvps; ++i) {
+    if (N[i] < 1 || N[i] > 65536 || !(std::isfinite(T[i]) && T[i] > 0.0)) return SGCM_EINVAL;
+    hh[i] = T[i] / N[i];
+    hoff[i] = total;
+    const int64_t NP = (int64_t)N[i] + 1;
+    total += ((12 + 12 + 4) * NP + (int64_t)kZI * N[i] + 31) / 32 * 32;
+    horder[i] = (int32_t)i;
+  }
+  if (sc.order == 1)  // larger N T first (the longest chains start first)
+    std::stable_sort(horder.begin(), horder.end(), [&](int32_t x, int32_t y) {
+      return (double)N[x] * T[x] > (double)N[y] * T[y];
+    });
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return SGCM_EDEVICE;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return SGCM_EDEVICE;
+  sgcm_batch* b = new (std::nothrow) sgcm_batch();
+  if (!b) return SGCM_ENOMEM;
+  b->args = a;
+  b->n = n_bvps;
+  b->dev = dev;
+  b->ws_doubles = (size_t)total;
+  b->sched = sc;
+  b->slots = (int64_t)sc.slots_per_cu * cus;
+  auto up = [](void** dst, const void* src, size_t bytes) -> bool {
+    if (hipMalloc(dst, bytes) != hipSuccess) return false;
+    return src == nullptr || hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  const int32_t zero = 0;
+  const bool ok = up((void**)&b->N, hN.data(), n_bvps * sizeof(int32_t)) &&
+                  up((void**)&b->h, hh.data(), n_bvps * sizeof(double)) &&
+                  up((void**)&b->off, hoff.data(), n_bvps * sizeof(int64_t)) &&
+                  up((void**)&b->order, horder.data(), n_bvps * sizeof(int32_t)) &&
+                  up((void**)&b->counter, &zero, sizeof(int32_t));
+  if (!ok) {
+    sgcm_batch_destroy(b);
+    return SGCM_ENOMEM;
+  }
+  *out = b;
+  return SGCM_OK;
+}
+
+extern "C" int sgcm_batch_workspace(const sgcm_batch* b, size_t* bytes) {
+  if (!b || !bytes) return SGCM_EINVAL;
+  *bytes = b->ws_doubles * sizeof(double);
+  return SGCM_OK;
+}
+
+extern "C" int sgcm_solve_bvps_batch(const sgcm_batch* b, const double* x0, double* lambda0, double* u0,
+                                     double* V, int32_t* status, int32_t* iters, void* workspace,
+                                     size_t ws_bytes, void* stream) {
+  if (!b || !x0 || !lambda0 || !u0 || !status || !iters || !workspace) return SGCM_EINVAL;
+  if (((uintptr_t)workspace & 255u) != 0 || ws_bytes < b->ws_doubles * sizeof(double)) return SGCM_EINVAL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return SGCM_EDEVICE;
+  if (dev != b->dev) return SGCM_EINVAL;
+  BatchArgs B;
+  B.N = b->N;
+  B.h = b->h;
+  B.off = b->off;
+  B.order = b->order;
+  B.counter = b->counter;
+  B.n = b->n;
+  B.persistent = b->slots > 0;
+  hipStream_t s = (hipStream_t)stream;
+  if (B.persistent) {
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b->counter);
+    const int64_t g = b->slots < b->n ? b->slots : b->n;
+    hipLaunchKernelGGL(k_newton_batch, dim3((unsigned)g), dim3(64), 0, s, b->args, B, x0, lambda0, u0, V,
+                       status, iters, (double*)workspace);
+  } else {
+    hipLaunchKernelGGL(k_newton_batch, dim3((unsigned)b->n), dim3(64), 0, s, b->args, B, x0, lambda0, u0, V,
+                       status, iters, (double*)workspace);
+  }
+  return hipGetLastError() == hipSuccess ? SGCM_OK : SGCM_EDEVICE;
+}
+
+extern "C" void sgcm_batch_destroy(sgcm_batch* b) {
+  if (!b) return;
+  (void)hipFree(b->N);
+  (void)hipFree(b->h);
+  (void)hipFree(b->off);
+  (void)hipFree(b->order);
+  (void)hipFree(b->counter);
+  delete b;
 }

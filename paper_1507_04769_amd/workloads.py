@@ -44,6 +44,44 @@ SMALL = Workload("rigid-body-6d-L2-N64-q1e3", level=2, n_intervals=64, horizon=2
 FULL = Workload("rigid-body-6d-L4-N256-q1e6", level=4, n_intervals=256, horizon=20.0,
                 n_queries=1_000_000, query_seed=1)
 
+
+
+@dataclass(frozen=True)
+class MixedBatch:
+    """BVPs with per-BVP mesh size and horizon: the first n_nodes nodes (canonical
+    order) of a level-`level` grid plus n_random uniform states, each BVP's N and
+    T drawn from `meshes` and `horizons` by PCG64(assign_seed)."""
+    name: str
+    level: int
+    n_nodes: int
+    n_random: int
+    random_seed: int
+    meshes: tuple
+    horizons: tuple
+    assign_seed: int
+    m: int = 3
+
+
+# Batching: 3072 level-5 nodes + 1024 uniform states, N in {64, 128, 256, 512},
+# T in {10, 20, 40}.
+BATCH = MixedBatch("rigid-body-6d-L5n3072+u1024-mixedNT", level=5, n_nodes=3072, n_random=1024,
+                   random_seed=102, meshes=(64, 128, 256, 512), horizons=(10.0, 20.0, 40.0), assign_seed=202)
+
+
+def mixed_assignment(b: MixedBatch, n: int):
+    """Per-BVP (N, T) of a mixed batch of n BVPs (int32, float64)."""
+    g = np.random.default_rng(b.assign_seed)
+    N = g.choice(np.asarray(b.meshes), size=n).astype(np.int32)
+    T = g.choice(np.asarray(b.horizons, dtype=np.float64), size=n)
+    return N, T
+
+
+def batch_initial_states(b: MixedBatch, grid_nodes: np.ndarray) -> np.ndarray:
+    """Initial states of a mixed batch: the first n_nodes rows of the given grid
+    node table (canonical order, level b.level) and n_random uniform states."""
+    return np.vstack([np.asarray(grid_nodes)[:b.n_nodes], uniform_in_box(b.n_random, b.random_seed)])
+
+
 J_DIAG = (2.0, 3.0, 4.0)
 Q_W, R_W, P_W = 1.0, 0.1, 10.0
 TOL = 1e-10

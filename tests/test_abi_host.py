@@ -120,3 +120,39 @@ def test_entry_points_validate_before_device_work():
     assert L.sgcm_eval_feedback(None, 3, fake, 10, fake, fake, S.FP64, None) == S.SGCM_EINVAL
     assert L.sgcm_build_interpolant(g.handle, 3, fake, fake, None) == S.SGCM_EINVAL  # aliasing
     assert L.sgcm_build_interpolant(g.handle, 0, fake, vp(8192), None) == S.SGCM_EINVAL
+
+
+def test_batch_create_validates_before_device_work():
+    # every rejected argument is caught on the host, before any HIP call
+    L = S.lib()
+    p = S.Problem()
+    vp = ctypes.c_void_p
+    out = vp()
+
+    def create(N, T, sched=(1, 0), n=None, prob=p):
+        N = np.ascontiguousarray(N, dtype=np.int32)
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        sc = S._CSchedule(*sched)
+        return L.sgcm_batch_create(ctypes.byref(prob.c()), len(N) if n is None else n,
+                                   N.ctypes.data_as(vp), T.ctypes.data_as(vp), ctypes.byref(sc),
+                                   ctypes.byref(out))
+
+    assert create([64, 0], [1.0, 1.0]) == S.SGCM_EINVAL          # N < 1
+    assert create([64, 70000], [1.0, 1.0]) == S.SGCM_EINVAL      # N > 65536
+    assert create([64, 64], [1.0, 0.0]) == S.SGCM_EINVAL         # T <= 0
+    assert create([64, 64], [1.0, float("inf")]) == S.SGCM_EINVAL
+    assert create([64], [1.0], n=0) == S.SGCM_EINVAL             # empty batch
+    assert create([64], [1.0], sched=(2, 0)) == S.SGCM_EINVAL    # unknown order
+    assert create([64], [1.0], sched=(0, 9)) == S.SGCM_EINVAL    # too many slots
+    assert create([64], [1.0], prob=S.Problem(m=4)) == S.SGCM_EINVAL
+    assert out.value is None
+    # the problem's own N and T are ignored by a batch: valid arguments get past
+    # validation (without a GPU the device query then fails)
+    rc = create([64], [1.0], prob=S.Problem(N=0, T=-1.0))
+    assert rc in (S.SGCM_OK, S.SGCM_EDEVICE)
+    if rc == S.SGCM_OK:
+        L.sgcm_batch_destroy(out)
+    nb = ctypes.c_size_t(0)
+    assert L.sgcm_batch_workspace(None, ctypes.byref(nb)) == S.SGCM_EINVAL
+    assert L.sgcm_solve_bvps_batch(None, None, None, None, None, None, None, None, 0, None) == S.SGCM_EINVAL
+    L.sgcm_batch_destroy(None)
