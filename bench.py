@@ -109,6 +109,48 @@ def cpu_baseline(args, nodes: np.ndarray, xq: np.ndarray) -> dict:
             "feedback_evals_per_s": nq / t_eval, "solve_s": t_solve, "eval_s": t_eval}
 
 
+def batched_leg(dev, reps: int) -> dict:
+    """The mixed batch (3072 level-5 nodes + 1024 uniform states, N in
+    {64..512}, T in {10, 20, 40}): one persistent launch with the autotuned
+    schedule, captured in a HIP graph and replayed, against the same inputs
+    solved unbatched (one launch per (N, T) group)."""
+    import torch
+    import paper_1507_04769_amd as S
+    from paper_1507_04769_amd import autotune as A
+    order, slots, src = A.tuned_schedule()
+    problem = A.batch_problem()
+    x0h, N, T = A.batch_inputs()
+    x0 = torch.tensor(x0h, device=dev)
+    b = S.Batch(problem, N, T, order=order, slots_per_cu=slots)
+    ws = S.batch_workspace(b, dev)
+    n = b.n
+    lam = torch.empty((n, 6), dtype=torch.float64, device=dev)
+    u0 = torch.empty((n, b.m), dtype=torch.float64, device=dev)
+    V = torch.empty((n,), dtype=torch.float64, device=dev)
+    st = torch.empty((n,), dtype=torch.int32, device=dev)
+    it = torch.empty((n,), dtype=torch.int32, device=dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up on the capture stream
+        S.sgcm_solve_bvps_batch(b, x0, lam, u0, V, st, it, ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        S.sgcm_solve_bvps_batch(b, x0, lam, u0, V, st, it, ws)
+    ms = A.time_ms(graph.replay, reps)
+    converged = int((st == S.CONVERGED).sum().item())
+    run, ngroups = A.unbatched_runner(problem, x0, N, T)
+    ums = A.time_ms(run, reps)
+    bms, ubms = float(np.median(ms)), float(np.median(ums))
+    return {"workload": "mixed batch: " + A.W.BATCH.name, "n_bvps": n, "converged": converged,
+            "schedule": {"order": "larger N*T first" if order == S.ORDER_LONGEST_FIRST else "as given",
+                         "slots_per_cu": slots, "source": os.path.relpath(src, ROOT) if src else "default"},
+            "graph": True, "ms": bms, "bvps_per_s": converged / (bms / 1e3),
+            "unbatched": {"launches": ngroups, "ms": ubms, "bvps_per_s": converged / (ubms / 1e3)},
+            "speedup_vs_unbatched": ubms / bms}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +159,7 @@ def main():
     ap.add_argument("--workload", choices=["full", "small"], default="full")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=20000)
+    ap.add_argument("--no-batched", action="store_true", help="skip the mixed-batch leg")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -187,6 +230,8 @@ def main():
     flops = newton_flops(wl.n_intervals, iters)
     achieved = flops / (float(np.mean(solve_ms)) / 1e3) / 1e12
 
+    batched = None if args.no_batched or args.workload != "full" else batched_leg(dev, 5)
+
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 8
         a = torch.ones(n, dtype=torch.float64, device=dev)
@@ -222,6 +267,8 @@ def main():
                      "traffic": measured_traffic() if wl.name == W.FULL.name else None,
                      "algorithmic_flops_per_launch": flops},
     }
+    if batched is not None:
+        out["batched"] = batched
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, nodes, xq_host)
     print(json.dumps(out), flush=True)
