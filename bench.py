@@ -151,6 +151,57 @@ def batched_leg(dev, reps: int) -> dict:
             "speedup_vs_unbatched": ubms / bms}
 
 
+def precision_leg(dev, prob, grid, x0, lam64, u064, it64, surplus, reps: int) -> dict:
+    """FP32 variants beside the FP64 path on the same MI355X: the FP32 inexact
+    Newton solve of the full workload (errors against the FP64 GPU solve, which
+    matches the oracle to ~1e-13) and FP32 feedback evaluation at 1e7 uniform
+    states (errors against the FP64 GPU evaluation of the same interpolant)."""
+    import dataclasses
+    import torch
+    import paper_1507_04769_amd as S
+    from paper_1507_04769_amd import autotune as A
+    from paper_1507_04769_amd import workloads as W
+    p32 = dataclasses.replace(prob, precision=S.FP32)
+    M = x0.shape[0]
+    lam = torch.empty_like(lam64)
+    u0 = torch.empty_like(u064)
+    V = torch.empty((M,), dtype=torch.float64, device=dev)
+    st = torch.empty((M,), dtype=torch.int32, device=dev)
+    it = torch.empty((M,), dtype=torch.int32, device=dev)
+    ws = torch.empty((S.sgcm_solve_bvps_workspace(p32, M) // 8 + 32,), dtype=torch.float64, device=dev)
+    p64 = dataclasses.replace(prob, precision=S.FP64)
+    ws64 = torch.empty_like(ws)
+    lam2, u02, V2 = torch.empty_like(lam), torch.empty_like(u0), torch.empty_like(V)
+    st2, it2 = torch.empty_like(st), torch.empty_like(it)
+    ms32 = A.time_ms(lambda: S.sgcm_solve_bvps(p32, x0, lam, u0, V, None, st, it, ws), reps)
+    ms64 = A.time_ms(lambda: S.sgcm_solve_bvps(p64, x0, lam2, u02, V2, None, st2, it2, ws64), reps)
+    conv = int((st == S.CONVERGED).sum().item())
+    el = ((lam - lam64).abs().amax(dim=1) / lam64.abs().amax(dim=1).clamp_min(1e-8)).cpu().numpy()
+    eu = ((u0 - u064).abs().amax(dim=1) / u064.abs().amax(dim=1).clamp_min(1e-8)).cpu().numpy()
+    i32, i64 = it.cpu().numpy(), it64
+    solve = {"ms": float(np.median(ms32)), "fp64_ms": float(np.median(ms64)),
+             "bvps_per_s": conv / (float(np.median(ms32)) / 1e3), "converged": conv,
+             "mean_iters": float(i32.mean()), "fp64_mean_iters": float(i64.mean()),
+             "lambda0_rel_err": {"max": float(el.max()), "rms": float(np.sqrt(np.mean(el ** 2)))},
+             "u0_rel_err": {"max": float(eu.max()), "rms": float(np.sqrt(np.mean(eu ** 2)))}}
+    nq = 10_000_000
+    xq = torch.tensor(W.uniform_in_box(nq, seed=3), device=dev)
+    xq32 = xq.float()
+    w32 = surplus.float()
+    uq = torch.empty((nq, surplus.shape[1]), dtype=torch.float64, device=dev)
+    uq32 = torch.empty((nq, surplus.shape[1]), dtype=torch.float32, device=dev)
+    e64 = A.time_ms(lambda: S.sgcm_eval_feedback(grid, surplus, xq, uq, S.FP64), reps)
+    e32 = A.time_ms(lambda: S.sgcm_eval_feedback_f32(grid, w32, xq32, uq32), reps)
+    err = (uq32.double() - uq).abs()
+    scale = float(uq.abs().max().item())
+    ev = {"queries": nq, "ms": float(np.median(e32)), "fp64_ms": float(np.median(e64)),
+          "evals_per_s": nq / (float(np.median(e32)) / 1e3), "fp64_evals_per_s": nq / (float(np.median(e64)) / 1e3),
+          "abs_err": {"max": float(err.max().item()), "rms": float(err.pow(2).mean().sqrt().item())},
+          "max_abs_u": scale}
+    return {"fp32_newton": solve, "fp32_eval": ev,
+            "note": "errors against the FP64 GPU results, which match the FP64 oracle to ~1e-13"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +211,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=20000)
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-batch leg")
+    ap.add_argument("--no-precision", action="store_true", help="skip the FP32 leg")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -231,6 +283,9 @@ def main():
     achieved = flops / (float(np.mean(solve_ms)) / 1e3) / 1e12
 
     batched = None if args.no_batched or args.workload != "full" else batched_leg(dev, 5)
+    precision = None
+    if not args.no_precision and args.workload == "full":
+        precision = precision_leg(dev, prob, grid, x0, lam, u0, iters, surplus, 5)
 
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 8
@@ -269,6 +324,8 @@ def main():
     }
     if batched is not None:
         out["batched"] = batched
+    if precision is not None:
+        out["precision"] = precision
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, nodes, xq_host)
     print(json.dumps(out), flush=True)

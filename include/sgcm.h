@@ -225,10 +225,21 @@ int sgcm_build_interpolant(const sgcm_grid* g, int32_t m, const double* values,
  *   surplus  device, M x m from sgcm_build_interpolant
  *   xq       device, n_q x d query states
  *   uq       device, n_q x m results
- *   precision  SGCM_FP64 (SGCM_FP32 returns SGCM_EUNSUPPORTED in this build)
+ *   precision  SGCM_FP64 (FP32 evaluation is sgcm_eval_feedback_f32, with
+ *            FP32 arrays; SGCM_FP32 here returns SGCM_EUNSUPPORTED)
  * n_q == 0 is a valid no-op. */
 int sgcm_eval_feedback(const sgcm_grid* g, int32_t m, const double* surplus, int64_t n_q,
                        const double* xq, double* uq, int32_t precision, void* stream);
+
+/* The same evaluation in FP32 (the reduced-precision variant of the on-line
+ * step): surplus (M x m), xq (n_q x d) and uq (n_q x m) are FP32 device
+ * arrays; the 1-D Lagrange basis values, their products and the sum over the
+ * nodes are computed in FP32 (the map to the unit cube in FP64, then rounded).
+ * Supported for d = 6, levels 1..4 and m <= 3, else SGCM_EUNSUPPORTED.  The
+ * error against the FP64 evaluation is that of FP32 rounding in a sum of M
+ * terms (about 1e-6 of max|u| on the rigid-body feedback). */
+int sgcm_eval_feedback_f32(const sgcm_grid* g, int32_t m, const float* surplus, int64_t n_q,
+                           const float* xq, float* uq, void* stream);
 
 #ifdef __cplusplus
 }

@@ -30,7 +30,8 @@ FP64, FP32 = 0, 1
 EXPORTS = ("sgcm_strerror", "sgcm_version", "sgcm_solve_bvps_workspace", "sgcm_solve_bvps",
            "sgcm_characteristic_rhs", "sgcm_batch_create", "sgcm_batch_workspace", "sgcm_solve_bvps_batch",
            "sgcm_batch_destroy", "sgcm_grid_create", "sgcm_grid_size", "sgcm_grid_nodes",
-           "sgcm_grid_keys", "sgcm_grid_destroy", "sgcm_build_interpolant", "sgcm_eval_feedback")
+           "sgcm_grid_keys", "sgcm_grid_destroy", "sgcm_build_interpolant", "sgcm_eval_feedback",
+           "sgcm_eval_feedback_f32")
 
 
 class SgcmError(RuntimeError):
@@ -115,6 +116,7 @@ def lib() -> ctypes.CDLL:
         "sgcm_grid_destroy": (None, [vp]),
         "sgcm_build_interpolant": (ctypes.c_int, [vp, i32, vp, vp, vp]),
         "sgcm_eval_feedback": (ctypes.c_int, [vp, i32, vp, i64, vp, vp, i32, vp]),
+        "sgcm_eval_feedback_f32": (ctypes.c_int, [vp, i32, vp, i64, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -395,6 +397,29 @@ def build_interpolant(grid: Grid, values, stream=None):
     surplus = torch.empty_like(values)
     sgcm_build_interpolant(grid, values, surplus, stream)
     return surplus
+
+
+def sgcm_eval_feedback_f32(grid: Grid, surplus, xq, uq, stream=None):
+    import torch
+    f32 = torch.float32
+    m = surplus.shape[1]
+    if xq.dim() != 2 or xq.shape[1] != grid.d:
+        raise ValueError("xq must be n x %d" % grid.d)
+    n = xq.shape[0]
+    rc = lib().sgcm_eval_feedback_f32(grid.handle, int(m), _ptr(surplus, f32, "surplus", len(grid) * m), int(n),
+                                      _ptr(xq, f32, "xq"), _ptr(uq, f32, "uq", n * m), _stream(stream))
+    _check(rc, "sgcm_eval_feedback_f32")
+
+
+def eval_feedback_f32(grid: Grid, surplus, xq, stream=None):
+    """FP32 evaluation: surplus and xq are rounded to FP32 if they are not
+    already; returns FP32 results."""
+    import torch
+    surplus = surplus.to(torch.float32).contiguous()
+    xq = xq.to(torch.float32).contiguous()
+    uq = torch.empty((xq.shape[0], surplus.shape[1]), dtype=torch.float32, device=xq.device)
+    sgcm_eval_feedback_f32(grid, surplus, xq, uq, stream)
+    return uq
 
 
 def eval_feedback(grid: Grid, surplus, xq, precision: int = FP64, stream=None):

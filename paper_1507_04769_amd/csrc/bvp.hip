@@ -55,6 +55,7 @@ struct BvpArgs {
   double q, r, pw, T, h, alpha, tol;
   int64_t per_bvp;  // doubles of workspace per BVP
   int sinv;         // 1: S_w is invertible and Si holds its inverse
+  int fp32;         // 1: Newton linear solve in FP32 (inexact Newton)
   double Si[9];
 };
 
@@ -222,7 +223,26 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+__device__ __forceinline__ float lane_bcast(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
 typedef double dbl2 __attribute__((ext_vector_type(2)));
+typedef float flt2 __attribute__((ext_vector_type(2)));
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+  using type = dbl2;
+};
+template <>
+struct Vec2<float> {
+  using type = flt2;
+};
+
+// Hardware reciprocal estimate (refined by the caller).
+__device__ __forceinline__ double hw_rcp(double x) { return __builtin_amdgcn_rcp(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // 16 bytes from src (per lane) into LDS at dst + 16 * lane, without passing
 // through registers (gfx950 global_load_lds_dwordx4); dst is wave-uniform.
@@ -245,40 +265,42 @@ constexpr int kFwdY = 12 * (kFwd + 1);     // rows of Y a chunk updates
 constexpr int kFwdBuf = kFwd * kZI + kFwdY;
 constexpr int kStage = 256;        // point inputs of one batch: y [9][12], r [9][12], trig [9][4]
 
+// T is the arithmetic type of the Newton linear solve (double, or float for
+// the FP32 inexact Newton); the residual pass, the stage and the Y rows of the
+// forward pass are FP64 in both.
+template <typename T>
 struct __align__(16) SweepShared {
   union {
     struct {
-      double pts[(kNB + 1) * kPt];  // point blocks of one batch (slot l: point klo - 1 + l)
-      double cst[kNB * kCst];       // interval constants of one batch
+      T pts[(kNB + 1) * kPt];  // point blocks of one batch (slot l: point klo - 1 + l)
+      T cst[kNB * kCst];       // interval constants of one batch
     } b;
     double fwd[2 * kFwdBuf];        // forward pass: two chunks of [Z | Y rows]
     double pa[2 * 64 * 12];         // residual pass: Phi and y of one 64-point chunk
   } u;
   double stage[kStage];  // point inputs of the next batch (filled by direct global-to-LDS loads)
-  double PR[60];   // [P | c] rows (c in column 6), 10 per row
-  double QC[60];   // columns of Q, 6 per column
-  double TT[30];   // columns of T = (Q + E) rate rows, 3 per column
-  double ER[18];   // rows of E[:, 6..8], 3 per row
+  T PR[60];   // [P | c] rows (c in column 6), 10 per row
+  T QC[60];   // columns of Q, 6 per column
+  T TT[30];   // columns of T = (Q + E) rate rows, 3 per column
+  T ER[18];   // rows of E[:, 6..8], 3 per row
   double carry_phi[12], carry_y[12];
   double xb[6], F0[6], FN[6];
   double zero[8];
   int flag;
 };
 
-// Flat double offsets into SweepShared: lanes address LDS as one array so that
-// every lane runs the same instructions with per-lane offsets.
-#define SGCM_OFF(field) ((int)(offsetof(SweepShared, field) / sizeof(double)))
 
 // A = df/dx, W and L = (I - a A)^{-1} of one mesh point into an LDS slot
 // (row-major 6 x 6 each).  Entries are stored as soon as they are formed so
 // that few values stay live; the structural zeros of A and W are written too.
+template <typename T>
 __device__ __forceinline__ void point_blocks(const BvpArgs& P, const double a, const double (&y)[12],
-                                             const double (&tr)[4], double* slot, int* flag) {
+                                             const double (&tr)[4], T* slot, int* flag) {
   const double w1 = y[3], w2 = y[4], w3 = y[5];
   const double l1 = y[6], l2 = y[7], l3 = y[8], l4 = y[9], l5 = y[10], l6 = y[11];
-  double* A = slot;
-  double* W = slot + 36;
-  double* L = slot + 72;
+  T* A = slot;
+  T* W = slot + 36;
+  T* L = slot + 72;
 #pragma unroll
   for (int e = 0; e < 36; ++e) {
     A[e] = 0.0;
@@ -365,21 +387,23 @@ __device__ __forceinline__ void point_blocks(const BvpArgs& P, const double a, c
 
 // Newton's method for one BVP (index b, mesh of N intervals of width h,
 // workspace ws_b) by one 64-lane workgroup.
+template <typename T>
 __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const double h, const int64_t b,
                                            double* ws_b, const double* __restrict__ x0, double* __restrict__ lam0,
                                            double* __restrict__ u0, double* __restrict__ Vout,
                                            double* __restrict__ traj, int32_t* __restrict__ status,
-                                           int32_t* __restrict__ iters, SweepShared& sh) {
+                                           int32_t* __restrict__ iters, SweepShared<T>& sh) {
+  using V2 = typename Vec2<T>::type;
   const int lane0 = threadIdx.x;
   const int lane = lane0;
   const int NP = N + 1;
   const double alpha = 0.5 * h;
+  const T at = (T)alpha;
   double* Y = ws_b;                    // NP x 12: the iterate
   double* R = Y + 12 * (int64_t)NP;    // NP x 12: residuals r_k (row 0 = [F_0, F_N])
   double* TR = R + 12 * (int64_t)NP;   // NP x 4: sin phi, cos phi, tan theta, sec theta
-  double* Zg = TR + 4 * (int64_t)NP;   // N x 96: interval solutions, 12 rows of 8
+  T* Zg = reinterpret_cast<T*>(TR + 4 * (int64_t)NP);  // N x 84: interval solutions, 12 x 7 rows
 
-  double* const Bs = reinterpret_cast<double*>(&sh);
   if (lane < 6) sh.xb[lane] = x0[b * 6 + lane];
   if (lane < 8) sh.zero[lane] = 0.0;
   for (int i = lane; i < 12 * NP; i += 64) Y[i] = 0.0;
@@ -467,11 +491,11 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
     lds_handoff();
     // chain state: lane (i, o), o in 0..5 and 9, holds [P_k | c_k][i][o];
     // P_N = p_w I, c_N = -F_N
-    double pv;
+    T pv;
     {
       const int l = opaque_lane(lane0);
       const int i = l < 60 ? l / 10 : 5, o = l < 60 ? l - 10 * i : 0;
-      pv = (o < 6) ? (o == i ? P.pw : 0.0) : -sh.FN[i];
+      pv = (T)((o < 6) ? (o == i ? P.pw : 0.0) : -sh.FN[i]);
     }
     // point inputs (y, r, trig) of points [lo - 1, hi] into the LDS stage;
     // rows are contiguous in global memory, 16 bytes per lane
@@ -499,7 +523,7 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
         const int l = opaque_lane(lane0);
         if (l <= nb) {
           double py[12], pt[4];
-          double* slot = sh.u.b.pts + l * kPt;
+          T* slot = sh.u.b.pts + l * kPt;
 #pragma unroll
           for (int i = 0; i < 12; ++i) {
             py[i] = sh.stage[l * 12 + i];
@@ -524,10 +548,10 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
         const int tl = l & 7, ip = l >> 3;
         if (ip < 3 && tl < nb) {
           const int k = khi - tl;
-          const double* pa = sh.u.b.pts + (k - klo) * kPt;  // point k - 1
-          const double* pb = pa + kPt;                       // point k
-          double* cst = sh.u.b.cst + tl * kCst;
-          double lb[2][6], la[2][6];  // rows i, i + 3 of L_k and of L_{k-1}^T
+          const T* pa = sh.u.b.pts + (k - klo) * kPt;  // point k - 1
+          const T* pb = pa + kPt;                       // point k
+          T* cst = sh.u.b.cst + tl * kCst;
+          T lb[2][6], la[2][6];  // rows i, i + 3 of L_k and of L_{k-1}^T
 #pragma unroll
           for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -535,32 +559,32 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
               lb[h][m] = pb[72 + (ip + 3 * h) * 6 + m];
               la[h][m] = pa[72 + m * 6 + ip + 3 * h];
             }
-          double* kc = cst + ip;              // K[i][o] at kc[o * 6 + 3 h]
-          double* fh = cst + kKc + ip * kFHr;  // row i of [F | H | Gam'] at fh[3 h kFHr + j]
+          T* kc = cst + ip;              // K[i][o] at kc[o * 6 + 3 h]
+          T* fh = cst + kKc + ip * kFHr;  // row i of [F | H | Gam'] at fh[3 h kFHr + j]
 #pragma unroll
           for (int o = 0; o < 6; ++o) {
-            double v[6];
+            T v[6];
 #pragma unroll
             for (int m = 0; m < 6; ++m) v[m] = pa[m * 6 + o];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-              double q = 0.0;
+              T q = T(0);
 #pragma unroll
               for (int m = 0; m < 6; ++m) q = fma(lb[h][m], v[m], q);
-              kc[o * 6 + 3 * h] = fma(alpha, q, lb[h][o]);
+              kc[o * 6 + 3 * h] = fma(at, q, lb[h][o]);
             }
           }
 #pragma unroll
           for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) kc[(6 + c) * 6 + 3 * h] = alpha * lb[h][3 + c];
+            for (int c = 0; c < 3; ++c) kc[(6 + c) * 6 + 3 * h] = at * lb[h][3 + c];
           {
-            double v[6];
+            T v[6];
 #pragma unroll
             for (int m = 0; m < 6; ++m) v[m] = pb[108 + m];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-              double q = 0.0;
+              T q = T(0);
 #pragma unroll
               for (int m = 0; m < 6; ++m) q = fma(lb[h][m], v[m], q);
               kc[54 + 3 * h] = -q;
@@ -568,7 +592,7 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
           }
 #pragma unroll
           for (int j = 0; j < 6; ++j) {
-            double vf[6], vh[6], vg[6];
+            T vf[6], vh[6], vg[6];
 #pragma unroll
             for (int m = 0; m < 6; ++m) {
               vf[m] = pb[j * 6 + m];        // A_k[j][m]
@@ -577,25 +601,25 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
             }
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-              double qf = 0.0, qh = 0.0, qg = 0.0;
+              T qf = T(0), qh = T(0), qg = T(0);
 #pragma unroll
               for (int m = 0; m < 6; ++m) {
                 qf = fma(la[h][m], vf[m], qf);
                 qh = fma(la[h][m], vh[m], qh);
                 qg = fma(la[h][m], vg[m], qg);
               }
-              fh[3 * h * kFHr + j] = fma(alpha, qf, la[h][j]);
-              fh[3 * h * kFHr + 6 + j] = alpha * qh;
-              fh[3 * h * kFHr + 12 + j] = alpha * qg;
+              fh[3 * h * kFHr + j] = fma(at, qf, la[h][j]);
+              fh[3 * h * kFHr + 6 + j] = at * qh;
+              fh[3 * h * kFHr + 12 + j] = at * qg;
             }
           }
           {
-            double v[6];
+            T v[6];
 #pragma unroll
             for (int m = 0; m < 6; ++m) v[m] = pb[114 + m];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-              double q = 0.0;
+              T q = T(0);
 #pragma unroll
               for (int m = 0; m < 6; ++m) q = fma(la[h][m], v[m], q);
               fh[3 * h * kFHr + 18] = -q;
@@ -623,32 +647,32 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
         cst_lane = cv && (co < 6 || co == 9);
         cs = co < 6 ? co : 6;
       }
-      double kcol[6], fh[12], kb[3], gam, kio;
+      T kcol[6], fh[12], kb[3], gam, kio;
       auto load_consts = [&](int t) {
-        const double* cst = sh.u.b.cst + t * kCst;
+        const T* cst = sh.u.b.cst + t * kCst;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          const dbl2 v = *reinterpret_cast<const dbl2*>(&cst[co * 6 + 2 * q]);
+          const V2 v = *reinterpret_cast<const V2*>(&cst[co * 6 + 2 * q]);
           kcol[2 * q] = v.x;
           kcol[2 * q + 1] = v.y;
         }
-        const double* fr = cst + kKc + ci * kFHr;
+        const T* fr = cst + kKc + ci * kFHr;
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-          const dbl2 v = *reinterpret_cast<const dbl2*>(&fr[2 * q]);
+          const V2 v = *reinterpret_cast<const V2*>(&fr[2 * q]);
           fh[2 * q] = v.x;
           fh[2 * q + 1] = v.y;
         }
-        gam = cst_lane ? fr[12 + cs] : 0.0;
+        gam = cst_lane ? fr[12 + cs] : T(0);
         kio = cst[co * 6 + ci];
 #pragma unroll
         for (int a = 0; a < 3; ++a) kb[a] = cst[(6 + a) * 6 + ci];
       };
       // S_w^{-1} in VGPRs: it is added to T1, which arrives in SGPRs
-      double siv[9];
+      T siv[9];
 #pragma unroll
       for (int e = 0; e < 9; ++e) {
-        siv[e] = P.Si[e];
+        siv[e] = (T)P.Si[e];
         asm volatile("" : "+v"(siv[e]));
       }
       load_consts(0);
@@ -657,17 +681,17 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
         // exchange 1: rows of [P_k | c_k]
         if (cst_lane) sh.PR[ci * 10 + cs] = pv;
         lds_handoff();
-        double prow[7];
+        T prow[7];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          const dbl2 v = *reinterpret_cast<const dbl2*>(&sh.PR[ci * 10 + 2 * q]);
+          const V2 v = *reinterpret_cast<const V2*>(&sh.PR[ci * 10 + 2 * q]);
           prow[2 * q] = v.x;
           prow[2 * q + 1] = v.y;
         }
         prow[6] = sh.PR[ci * 10 + 6];
         // Q = [P | c] [K ; e_9],  C = H K + [Gam | 0 | -D^{-1} r^l]
-        double q = co == 9 ? prow[6] : 0.0;
-        double cc = gam;
+        T q = co == 9 ? prow[6] : T(0);
+        T cc = gam;
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
           q = fma(prow[m], kcol[m], q);
@@ -676,28 +700,28 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
         // exchange 2: columns of Q
         if (cv) sh.QC[co * 6 + ci] = q;
         lds_handoff();
-        double qcol[6];
+        T qcol[6];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-          const dbl2 v = *reinterpret_cast<const dbl2*>(&sh.QC[co * 6 + 2 * r]);
+          const V2 v = *reinterpret_cast<const V2*>(&sh.QC[co * 6 + 2 * r]);
           qcol[2 * r] = v.x;
           qcol[2 * r + 1] = v.y;
         }
-        double e = -cc;
+        T e = -cc;
 #pragma unroll
         for (int m = 0; m < 6; ++m) e = fma(fh[m], qcol[m], e);
-        const double tv = q + e;  // T = Psi_w [K ; e_9] on the rate rows
-        const double kio_t = kio, kb0 = kb[0], kb1 = kb[1], kb2 = kb[2];
+        const T tv = q + e;  // T = Psi_w [K ; e_9] on the rate rows
+        const T kio_t = kio, kb0 = kb[0], kb1 = kb[1], kb2 = kb[2];
         // exchange 3: columns of T, rows of E[:, 6..8]; T[:, 6..8] to every lane
         if (cv && ci >= 3) sh.TT[co * 3 + ci - 3] = tv;
         if (cv && co >= 6 && co <= 8) sh.ER[ci * 3 + co - 6] = e;
-        double t1[9];
+        T t1[9];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
           for (int c = 0; c < 3; ++c) t1[a * 3 + c] = lane_bcast(tv, (3 + a) * 10 + 6 + c);
         lds_handoff();
-        double tc[3], er[3];
+        T tc[3], er[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           tc[a] = sh.TT[co * 3 + a];
@@ -707,7 +731,7 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
         // the 3 x 3 system Z M = W: Z = S_w^{-1} + T[:, 6..8], W = T when S_w
         // is invertible, else Z = I + S_w T[:, 6..8], W = S_w T; M by the
         // adjugate of Z
-        double z[9], w[3];
+        T z[9], w[3];
         if (P.sinv) {
 #pragma unroll
           for (int e2 = 0; e2 < 9; ++e2) z[e2] = siv[e2] + t1[e2];
@@ -718,34 +742,35 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
           for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-              double s = (a == c) ? 1.0 : 0.0;
+              T s = (a == c) ? T(1) : T(0);
 #pragma unroll
-              for (int m = 0; m < 3; ++m) s = fma(P.Sw[a * 3 + m], t1[m * 3 + c], s);
+              for (int m = 0; m < 3; ++m) s = fma((T)P.Sw[a * 3 + m], t1[m * 3 + c], s);
               z[a * 3 + c] = s;
             }
 #pragma unroll
-          for (int a = 0; a < 3; ++a) w[a] = fma(P.Sw[a * 3 + 0], tc[0], fma(P.Sw[a * 3 + 1], tc[1], P.Sw[a * 3 + 2] * tc[2]));
+          for (int a = 0; a < 3; ++a)
+            w[a] = fma((T)P.Sw[a * 3 + 0], tc[0], fma((T)P.Sw[a * 3 + 1], tc[1], (T)P.Sw[a * 3 + 2] * tc[2]));
         }
-        const double j00 = z[4] * z[8] - z[5] * z[7], j01 = z[2] * z[7] - z[1] * z[8], j02 = z[1] * z[5] - z[2] * z[4];
-        const double j10 = z[5] * z[6] - z[3] * z[8], j11 = z[0] * z[8] - z[2] * z[6], j12 = z[2] * z[3] - z[0] * z[5];
-        const double j20 = z[3] * z[7] - z[4] * z[6], j21 = z[1] * z[6] - z[0] * z[7], j22 = z[0] * z[4] - z[1] * z[3];
-        const double det = z[0] * j00 + z[1] * j10 + z[2] * j20;
+        const T j00 = z[4] * z[8] - z[5] * z[7], j01 = z[2] * z[7] - z[1] * z[8], j02 = z[1] * z[5] - z[2] * z[4];
+        const T j10 = z[5] * z[6] - z[3] * z[8], j11 = z[0] * z[8] - z[2] * z[6], j12 = z[2] * z[3] - z[0] * z[5];
+        const T j20 = z[3] * z[7] - z[4] * z[6], j21 = z[1] * z[6] - z[0] * z[7], j22 = z[0] * z[4] - z[1] * z[3];
+        const T det = z[0] * j00 + z[1] * j10 + z[2] * j20;
         if (det == 0.0) singular = true;
         // 1/det: hardware reciprocal estimate refined by two Newton steps
         // (det is O(1) here: no scaling is needed)
-        double rd = __builtin_amdgcn_rcp(det);
-        rd = fma(rd, fma(-det, rd, 1.0), rd);
-        rd = fma(rd, fma(-det, rd, 1.0), rd);
+        T rd = hw_rcp(det);
+        rd = fma(rd, fma(-det, rd, T(1)), rd);
+        rd = fma(rd, fma(-det, rd, T(1)), rd);
         // y = adj(Z) W[:, o]; [M | m][:, o] = y / det
-        const double y0 = fma(j00, w[0], fma(j01, w[1], j02 * w[2]));
-        const double y1 = fma(j10, w[0], fma(j11, w[1], j12 * w[2]));
-        const double y2 = fma(j20, w[0], fma(j21, w[1], j22 * w[2]));
+        const T y0 = fma(j00, w[0], fma(j01, w[1], j02 * w[2]));
+        const T y1 = fma(j10, w[0], fma(j11, w[1], j12 * w[2]));
+        const T y2 = fma(j20, w[0], fma(j21, w[1], j22 * w[2]));
         // P_{k-1} = E - E[:, 6..8] M, c_{k-1} = E[:, 9] - E[:, 6..8] m,
         // G_k = K - B_k M, g_k = rho - B_k m
-        const double pn = fma(-rd, fma(er[0], y0, fma(er[1], y1, er[2] * y2)), e);
-        const double gn = fma(-rd, fma(kb0, y0, fma(kb1, y1, kb2 * y2)), kio_t);
+        const T pn = fma(-rd, fma(er[0], y0, fma(er[1], y1, er[2] * y2)), e);
+        const T gn = fma(-rd, fma(kb0, y0, fma(kb1, y1, kb2 * y2)), kio_t);
         if (cst_lane) {
-          double* zk = Zg + (int64_t)(k - 1) * kZI;
+          T* zk = Zg + (int64_t)(k - 1) * kZI;
           zk[ci * 7 + cs] = gn;
           zk[(6 + ci) * 7 + cs] = pn;
         }
@@ -766,20 +791,22 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
     //      dlambda_{k-1} = P_{k-1} dx_{k-1} + c_{k-1}, dlambda_N = p_w dx_N - F_N;
     //      the step is added to Y in place ----
     wave_mem_sync();  // interval solutions visible to every lane
-    double dx[6];
+    T dx[6];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) dx[j] = -sh.F0[j];
-    if (lane < 6) Y[lane] += dx[lane < 6 ? lane : 0];
+    for (int j = 0; j < 6; ++j) dx[j] = (T)(-sh.F0[j]);
+    if (lane < 6) Y[lane] += (double)dx[lane < 6 ? lane : 0];
     // chunk [c0, c0 + kFwd) of interval solutions and Y rows c0 - 1 .. c0 + kFwd - 1
     // into buffer bf, direct to LDS
     auto fwd_load = [&](int c0, int bf) {
       const int l = opaque_lane(lane0);
       const int nk = (N - c0 + 1) < kFwd ? (N - c0 + 1) : kFwd;
       double* zb = sh.u.fwd + bf * kFwdBuf;
-      const double* zs = Zg + (int64_t)(c0 - 1) * kZI;
+      // the interval solutions (T) move as 16-byte units
+      const double* zs = reinterpret_cast<const double*>(Zg + (int64_t)(c0 - 1) * kZI);
+      const int units = nk * kZI * (int)sizeof(T) / 16;
 #pragma unroll
       for (int j = 0; j < (kFwd * kZI + 127) / 128; ++j)
-        if (64 * j + l < nk * (kZI / 2)) g2lds16(zs + 128 * j + 2 * l, zb + 128 * j);
+        if (64 * j + l < units) g2lds16(zs + 128 * j + 2 * l, zb + 128 * j);
       const double* ys = Y + 12 * (int64_t)(c0 - 1);
 #pragma unroll
       for (int j = 0; j < (kFwdY + 127) / 128; ++j)
@@ -793,27 +820,29 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       const int l = opaque_lane(lane0);
       const int r = l < 12 ? l : 11;
       const double* zb = sh.u.fwd + bf * kFwdBuf;
+      const T* zt = reinterpret_cast<const T*>(zb);
       // lane r < 12 owns row r: dx_k (r < 6) or dlambda_{k-1} (r >= 6)
       const int yo = kFwd * kZI + (r < 6 ? 12 : 0) + r;
       const int nk = (N - c0 + 1) < kFwd ? (N - c0 + 1) : kFwd;
-      double zn[7], yn;
+      T zn[7];
+      double yn;
       auto rd = [&](int s) {
 #pragma unroll
-        for (int j = 0; j < 7; ++j) zn[j] = zb[s * kZI + r * 7 + j];
+        for (int j = 0; j < 7; ++j) zn[j] = zt[s * kZI + r * 7 + j];
         yn = zb[yo + 12 * s];
       };
       rd(0);
       for (int s = 0; s < nk; ++s) {
-        double z[7];
+        T z[7];
 #pragma unroll
         for (int j = 0; j < 7; ++j) z[j] = zn[j];
         const double yv = yn;
         if (s + 1 < nk) rd(s + 1);
-        double v = z[6];
+        T v = z[6];
 #pragma unroll
         for (int j = 0; j < 6; ++j) v = fma(z[j], dx[j], v);
         const int k = c0 + s;
-        if (l < 12) Y[12 * (int64_t)(r < 6 ? k : k - 1) + r] = yv + v;
+        if (l < 12) Y[12 * (int64_t)(r < 6 ? k : k - 1) + r] = yv + (double)v;
 #pragma unroll
         for (int j = 0; j < 6; ++j) dx[j] = lane_bcast(v, j);
       }
@@ -823,7 +852,7 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       const int i = lane - 6;
       double d = -sh.FN[i];
 #pragma unroll
-      for (int j = 0; j < 6; ++j) d = fma(j == i ? P.pw : 0.0, dx[j], d);
+      for (int j = 0; j < 6; ++j) d = fma(j == i ? P.pw : 0.0, (double)dx[j], d);
       Y[12 * (int64_t)N + 6 + i] += d;
     }
     wave_mem_sync();
@@ -865,11 +894,12 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
   }
 }
 
+template <typename T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_newton(
     BvpArgs P, const double* __restrict__ x0, double* __restrict__ lam0, double* __restrict__ u0,
     double* __restrict__ Vout, double* __restrict__ traj, int32_t* __restrict__ status,
     int32_t* __restrict__ iters, double* __restrict__ ws) {
-  __shared__ SweepShared sh;
+  __shared__ SweepShared<T> sh;
   const int64_t b = blockIdx.x;
   newton_bvp(P, P.N, P.h, b, ws + b * P.per_bvp, x0, lam0, u0, Vout, traj, status, iters, sh);
 }
@@ -893,11 +923,12 @@ __device__ __forceinline__ int64_t next_position(int32_t* counter) {
   return __shfl(v, 0);
 }
 
+template <typename T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_newton_batch(
     BvpArgs P, BatchArgs B, const double* __restrict__ x0, double* __restrict__ lam0, double* __restrict__ u0,
     double* __restrict__ Vout, int32_t* __restrict__ status, int32_t* __restrict__ iters,
     double* __restrict__ ws) {
-  __shared__ SweepShared sh;
+  __shared__ SweepShared<T> sh;
   int64_t pos = B.persistent ? next_position(B.counter) : (int64_t)blockIdx.x;
   while (pos < B.n) {
     const int64_t j = B.order[pos];
@@ -948,7 +979,6 @@ int make_bvp_args(const sgcm_problem* p, BvpArgs* a) {
   if (p->N < 1 || p->N > 65536) return SGCM_EINVAL;
   if (!(p->tol >= 0.0) || p->max_iter < 0 || p->max_iter > 1000) return SGCM_EINVAL;
   if (p->precision != SGCM_FP64 && p->precision != SGCM_FP32) return SGCM_EINVAL;
-  if (p->precision != SGCM_FP64) return SGCM_EUNSUPPORTED;
   a->model = p->model;
   a->m = p->m;
   a->N = p->N;
@@ -973,6 +1003,7 @@ int make_bvp_args(const sgcm_problem* p, BvpArgs* a) {
   a->h = p->T / p->N;
   a->alpha = 0.5 * a->h;
   a->tol = p->tol;
+  a->fp32 = p->precision == SGCM_FP32;
   // With three independent controls S_w is invertible and the 3 x 3 system of
   // a sweep step, (I + S_w T1) M = S_w T, is solved as (S_w^{-1} + T1) M = T.
   a->sinv = 0;
@@ -1030,8 +1061,12 @@ extern "C" int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const doub
   if (!x0 || !lambda0 || !u0 || !status || !iters || !workspace) return SGCM_EINVAL;
   if (((uintptr_t)workspace & 255u) != 0) return SGCM_EINVAL;
   if (ws_bytes < (size_t)a.per_bvp * sizeof(double) * (size_t)n_bvps) return SGCM_EINVAL;
-  hipLaunchKernelGGL(k_newton, dim3((unsigned)n_bvps), dim3(64), 0, (hipStream_t)stream, a, x0, lambda0,
-                     u0, V, traj, status, iters, (double*)workspace);
+  if (a.fp32)
+    hipLaunchKernelGGL(k_newton<float>, dim3((unsigned)n_bvps), dim3(64), 0, (hipStream_t)stream, a, x0,
+                       lambda0, u0, V, traj, status, iters, (double*)workspace);
+  else
+    hipLaunchKernelGGL(k_newton<double>, dim3((unsigned)n_bvps), dim3(64), 0, (hipStream_t)stream, a, x0,
+                       lambda0, u0, V, traj, status, iters, (double*)workspace);
   return hipGetLastError() == hipSuccess ? SGCM_OK : SGCM_EDEVICE;
 }
 
@@ -1149,13 +1184,14 @@ extern "C" int sgcm_solve_bvps_batch(const sgcm_batch* b, const double* x0, doub
   hipStream_t s = (hipStream_t)stream;
   if (B.persistent) {
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b->counter);
-    const int64_t g = b->slots < b->n ? b->slots : b->n;
-    hipLaunchKernelGGL(k_newton_batch, dim3((unsigned)g), dim3(64), 0, s, b->args, B, x0, lambda0, u0, V,
-                       status, iters, (double*)workspace);
-  } else {
-    hipLaunchKernelGGL(k_newton_batch, dim3((unsigned)b->n), dim3(64), 0, s, b->args, B, x0, lambda0, u0, V,
-                       status, iters, (double*)workspace);
   }
+  const unsigned g = (unsigned)(B.persistent ? (b->slots < b->n ? b->slots : b->n) : b->n);
+  if (b->args.fp32)
+    hipLaunchKernelGGL(k_newton_batch<float>, dim3(g), dim3(64), 0, s, b->args, B, x0, lambda0, u0, V, status,
+                       iters, (double*)workspace);
+  else
+    hipLaunchKernelGGL(k_newton_batch<double>, dim3(g), dim3(64), 0, s, b->args, B, x0, lambda0, u0, V, status,
+                       iters, (double*)workspace);
   return hipGetLastError() == hipSuccess ? SGCM_OK : SGCM_EDEVICE;
 }
 

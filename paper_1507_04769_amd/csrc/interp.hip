@@ -38,38 +38,40 @@ __host__ __device__ constexpr int upto(int b) { return b <= 0 ? 1 : (1 << b) + 1
 
 // Lagrange basis values of the new points of level I (2 <= I <= L+1) at xi,
 // from prefix and suffix products of (xi - x_s) over X^I.
-template <int L, int I>
-__device__ __forceinline__ void level_basis(const GridArgs& g, double xi, double (&out)[kMaxPoints]) {
+// F is the arithmetic type (double; float for the FP32 evaluation path, whose
+// point and scale tables are rounded from the FP64 ones).
+template <int L, int I, typename F = double>
+__device__ __forceinline__ void level_basis(const GridArgs& g, F xi, F (&out)[kMaxPoints]) {
   if constexpr (I <= L + 1) {
     constexpr int n = (1 << (I - 1)) + 1;
     constexpr int stride = 1 << (L + 1 - I);
     // suffix products suf[s] = prod_{s' > s} (xi - x_s'), then one forward
     // sweep with a running prefix product
-    double suf[n];
-    suf[n - 1] = 1.0;
+    F suf[n];
+    suf[n - 1] = F(1);
 #pragma unroll
-    for (int s = n - 2; s >= 0; --s) suf[s] = suf[s + 1] * (xi - g.X[(s + 1) * stride]);
-    double pre = 1.0;
+    for (int s = n - 2; s >= 0; --s) suf[s] = suf[s + 1] * (xi - (F)g.X[(s + 1) * stride]);
+    F pre = F(1);
 #pragma unroll
     for (int s = 0; s < n; ++s) {
       if constexpr (I == 2) {
-        if (s != 1) out[1 + s / 2] = pre * suf[s] * g.scale[1 + s / 2];
+        if (s != 1) out[1 + s / 2] = pre * suf[s] * (F)g.scale[1 + s / 2];
       } else {
         if (s & 1) {
           constexpr int base = (1 << (I - 2)) + 1;
-          out[base + s / 2] = pre * suf[s] * g.scale[base + s / 2];
+          out[base + s / 2] = pre * suf[s] * (F)g.scale[base + s / 2];
         }
       }
-      pre *= xi - g.X[s * stride];
+      pre *= xi - (F)g.X[s * stride];
     }
-    level_basis<L, I + 1>(g, xi, out);
+    level_basis<L, I + 1, F>(g, xi, out);
   }
 }
 
-template <int L>
-__device__ __forceinline__ void basis_row_l(const GridArgs& g, double xi, double (&out)[kMaxPoints]) {
-  out[0] = 1.0;
-  level_basis<L, 2>(g, xi, out);
+template <int L, typename F = double>
+__device__ __forceinline__ void basis_row_l(const GridArgs& g, F xi, F (&out)[kMaxPoints]) {
+  out[0] = F(1);
+  level_basis<L, 2, F>(g, xi, out);
 }
 
 __device__ __forceinline__ void basis_row(const GridArgs& g, double xi, double (&out)[kMaxPoints]) {
@@ -216,80 +218,81 @@ __host__ __device__ constexpr int child_off(int r, int b, int e) {
 // Sum over the subtree of R remaining (unrolled) dimensions with budget B whose
 // nodes start at offset OFF; E is the child being visited.  bv[j] holds the
 // basis values of unrolled dimension j.
-template <int KU, int P, int M, int R, int B, int OFF, int E>
-__device__ __forceinline__ void uwalk(const double (&bv)[KU][P], const double* __restrict__ w, double p,
-                                      double (&acc)[M]) {
+template <int KU, int P, int M, int R, int B, int OFF, int E, typename F>
+__device__ __forceinline__ void uwalk(const F (&bv)[KU][P], const F* __restrict__ w, F p, F (&acc)[M]) {
   if constexpr (E < upto(B)) {
     constexpr int ex = excess_of(E);
     constexpr int off = OFF + child_off(R, B, E);
     if constexpr (R == 1) {
-      const double pe = p * bv[KU - 1][E];
+      const F pe = p * bv[KU - 1][E];
 #pragma unroll
       for (int c = 0; c < M; ++c) acc[c] = fma(pe, w[off * M + c], acc[c]);
     } else if constexpr (R == 2) {
       constexpr int n = upto(B - ex);
-      double t[M];
+      F t[M];
 #pragma unroll
-      for (int c = 0; c < M; ++c) t[c] = 0.0;
+      for (int c = 0; c < M; ++c) t[c] = F(0);
 #pragma unroll
       for (int q = 0; q < n; ++q)
 #pragma unroll
         for (int c = 0; c < M; ++c) t[c] = fma(bv[KU - 1][q], w[(off + q) * M + c], t[c]);
-      const double pe = p * bv[KU - 2][E];
+      const F pe = p * bv[KU - 2][E];
 #pragma unroll
       for (int c = 0; c < M; ++c) acc[c] = fma(pe, t[c], acc[c]);
     } else {
-      uwalk<KU, P, M, R - 1, B - ex, off, 0>(bv, w, p * bv[KU - R][E], acc);
+      uwalk<KU, P, M, R - 1, B - ex, off, 0, F>(bv, w, p * bv[KU - R][E], acc);
     }
-    uwalk<KU, P, M, R, B, OFF, E + 1>(bv, w, p, acc);
+    uwalk<KU, P, M, R, B, OFF, E + 1, F>(bv, w, p, acc);
   }
 }
 
-template <int KU, int P, int M, int BB>
-__device__ __forceinline__ void uwalk_budget(int b, const double (&bv)[KU][P], const double* __restrict__ w,
-                                             double p, double (&acc)[M]) {
+template <int KU, int P, int M, int BB, typename F>
+__device__ __forceinline__ void uwalk_budget(int b, const F (&bv)[KU][P], const F* __restrict__ w, F p,
+                                             F (&acc)[M]) {
   if (b == BB) {
-    uwalk<KU, P, M, KU, BB, 0, 0>(bv, w, p, acc);
+    uwalk<KU, P, M, KU, BB, 0, 0, F>(bv, w, p, acc);
   } else if constexpr (BB > 0) {
-    uwalk_budget<KU, P, M, BB - 1>(b, bv, w, p, acc);
+    uwalk_budget<KU, P, M, BB - 1, F>(b, bv, w, p, acc);
   }
 }
 
-template <int D, int L, int M, int KO, int KU, int K>
-__device__ __forceinline__ void owalk(const GridArgs& g, const double* __restrict__ w, int bL, int64_t base,
-                                      double p, double (&acc)[M], const double (&bv)[KU][upto(L)],
-                                      const double* lds_lane) {
+template <int D, int L, int M, int KO, int KU, int K, typename F>
+__device__ __forceinline__ void owalk(const GridArgs& g, const F* __restrict__ w, int bL, int64_t base, F p,
+                                      F (&acc)[M], const F (&bv)[KU][upto(L)], const F* lds_lane) {
   constexpr int P = upto(L);
   if constexpr (K == KO) {
-    uwalk_budget<KU, P, M, L>(bL, bv, w + base * M, p, acc);
+    uwalk_budget<KU, P, M, L, F>(bL, bv, w + base * M, p, acc);
   } else {
     const int cE = upto(bL);
     const int32_t* offrow = g.off + ((D - K - 1) * (L + 1) + bL) * P;
     for (int e = 0; e < cE; ++e) {
       const int ex = g.excess[e];
-      const double pk = (K == 0) ? lds_lane[(K * P + e) * 64] : p * lds_lane[(K * P + e) * 64];
-      owalk<D, L, M, KO, KU, K + 1>(g, w, bL - ex, base + offrow[e], pk, acc, bv, lds_lane);
+      const F pk = (K == 0) ? lds_lane[(K * P + e) * 64] : p * lds_lane[(K * P + e) * 64];
+      owalk<D, L, M, KO, KU, K + 1, F>(g, w, bL - ex, base + offrow[e], pk, acc, bv, lds_lane);
     }
   }
 }
 
-template <int D, int L, int M>
-__global__ __launch_bounds__(64) void k_eval_fast(GridArgs g, const double* __restrict__ w, int64_t nq,
-                                                  const double* __restrict__ xq, double* __restrict__ uq) {
+// F = double: the FP64 path.  F = float: the FP32 path (surplus, states and
+// outputs in FP32; the map to the unit cube in FP64, then rounded).
+template <int D, int L, int M, typename F = double>
+__global__ __launch_bounds__(64) void k_eval_fast(GridArgs g, const F* __restrict__ w, int64_t nq,
+                                                  const F* __restrict__ xq, F* __restrict__ uq) {
   constexpr int P = upto(L);
   constexpr int KU = D < 4 ? D : 4;
   constexpr int KO = D - KU;
-  extern __shared__ double lds[];
+  extern __shared__ double lds_d[];
+  F* lds = reinterpret_cast<F*>(lds_d);
   const int lane = threadIdx.x;
   const int64_t q = (int64_t)blockIdx.x * 64 + lane;
   const bool active = q < nq;
-  double* lds_lane = lds + lane;
-  double bv[KU][P];
+  F* lds_lane = lds + lane;
+  F bv[KU][P];
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    const double xi = active ? (xq[q * D + k] - g.lo[k]) * g.inv_width[k] : 0.5;
-    double row[kMaxPoints];
-    basis_row_l<L>(g, xi, row);
+    const F xi = active ? (F)(((double)xq[q * D + k] - g.lo[k]) * g.inv_width[k]) : F(0.5);
+    F row[kMaxPoints];
+    basis_row_l<L, F>(g, xi, row);
     if (k < KO) {
 #pragma unroll
       for (int e = 0; e < P; ++e) lds_lane[(k * P + e) * 64] = row[e];
@@ -298,10 +301,10 @@ __global__ __launch_bounds__(64) void k_eval_fast(GridArgs g, const double* __re
       for (int e = 0; e < P; ++e) bv[k - KO][e] = row[e];
     }
   }
-  double acc[M];
+  F acc[M];
 #pragma unroll
-  for (int c = 0; c < M; ++c) acc[c] = 0.0;
-  owalk<D, L, M, KO, KU, 0>(g, w, L, 0, 1.0, acc, bv, lds_lane);
+  for (int c = 0; c < M; ++c) acc[c] = F(0);
+  owalk<D, L, M, KO, KU, 0, F>(g, w, L, 0, F(1), acc, bv, lds_lane);
   if (active) {
 #pragma unroll
     for (int c = 0; c < M; ++c) uq[q * M + c] = acc[c];
@@ -431,36 +434,35 @@ hipError_t level_chunk(int d, int mc, const GridArgs& a, size_t lds, const doubl
 #undef CALL_LEVEL
 }
 
-template <int L, int M>
-hipError_t launch_fast(const GridArgs& a, int64_t nq, const double* w, const double* xq, double* uq,
-                       hipStream_t s) {
+template <int L, int M, typename F>
+hipError_t launch_fast(const GridArgs& a, int64_t nq, const F* w, const F* xq, F* uq, hipStream_t s) {
   constexpr int D = 6;
-  const size_t lds = (size_t)(D - 4) * upto(L) * 64 * sizeof(double);
+  const size_t lds = (size_t)(D - 4) * upto(L) * 64 * sizeof(F);
   const int64_t blocks = (nq + 63) / 64;
-  hipLaunchKernelGGL((k_eval_fast<D, L, M>), dim3((unsigned)blocks), dim3(64), lds, s, a, w, nq, xq, uq);
+  hipLaunchKernelGGL((k_eval_fast<D, L, M, F>), dim3((unsigned)blocks), dim3(64), lds, s, a, w, nq, xq, uq);
   return hipGetLastError();
 }
 
-template <int L>
-hipError_t fast_m(int m, const GridArgs& a, int64_t nq, const double* w, const double* xq, double* uq,
-                  hipStream_t s) {
+template <int L, typename F>
+hipError_t fast_m(int m, const GridArgs& a, int64_t nq, const F* w, const F* xq, F* uq, hipStream_t s) {
   switch (m) {
-    case 1: return launch_fast<L, 1>(a, nq, w, xq, uq, s);
-    case 2: return launch_fast<L, 2>(a, nq, w, xq, uq, s);
-    default: return launch_fast<L, 3>(a, nq, w, xq, uq, s);
+    case 1: return launch_fast<L, 1, F>(a, nq, w, xq, uq, s);
+    case 2: return launch_fast<L, 2, F>(a, nq, w, xq, uq, s);
+    default: return launch_fast<L, 3, F>(a, nq, w, xq, uq, s);
   }
 }
 
 // The unrolled kernel covers d = 6, levels 1..4, m <= 3 (the rigid-body feedback).
 bool fast_eval_applies(const Grid& G, int m) { return G.d == 6 && G.level >= 1 && G.level <= 4 && m <= 3; }
 
-hipError_t eval_fast(const Grid& G, int m, const GridArgs& a, int64_t nq, const double* w, const double* xq,
-                     double* uq, hipStream_t s) {
+template <typename F>
+hipError_t eval_fast(const Grid& G, int m, const GridArgs& a, int64_t nq, const F* w, const F* xq, F* uq,
+                     hipStream_t s) {
   switch (G.level) {
-    case 1: return fast_m<1>(m, a, nq, w, xq, uq, s);
-    case 2: return fast_m<2>(m, a, nq, w, xq, uq, s);
-    case 3: return fast_m<3>(m, a, nq, w, xq, uq, s);
-    default: return fast_m<4>(m, a, nq, w, xq, uq, s);
+    case 1: return fast_m<1, F>(m, a, nq, w, xq, uq, s);
+    case 2: return fast_m<2, F>(m, a, nq, w, xq, uq, s);
+    case 3: return fast_m<3, F>(m, a, nq, w, xq, uq, s);
+    default: return fast_m<4, F>(m, a, nq, w, xq, uq, s);
   }
 }
 
@@ -542,4 +544,22 @@ extern "C" int sgcm_eval_feedback(const sgcm_grid* gh, int32_t m, const double* 
     if (eval_chunk(G.d, mc, a, lds, surplus, m, col0, n_q, xq, uq, s) != hipSuccess) return SGCM_EDEVICE;
   }
   return SGCM_OK;
+}
+
+extern "C" int sgcm_eval_feedback_f32(const sgcm_grid* gh, int32_t m, const float* surplus, int64_t n_q,
+                                      const float* xq, float* uq, void* stream) {
+  if (!gh || m < 1 || m > 64 || n_q < 0) return SGCM_EINVAL;
+  if (n_q == 0) return SGCM_OK;
+  if (!surplus || !xq || !uq) return SGCM_EINVAL;
+  if ((n_q + 63) / 64 > 0x7fffffffLL) return SGCM_EUNSUPPORTED;
+  Grid& G = const_cast<Grid&>(gh->g);
+  if (!fast_eval_applies(G, m)) return SGCM_EUNSUPPORTED;
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc != SGCM_OK) return rc;
+  rc = ensure_device_tables(G, dev);
+  if (rc != SGCM_OK) return rc;
+  GridArgs a = make_args(G, G.dev[dev]);
+  return eval_fast<float>(G, m, a, n_q, surplus, xq, uq, (hipStream_t)stream) == hipSuccess ? SGCM_OK
+                                                                                              : SGCM_EDEVICE;
 }

@@ -90,7 +90,8 @@ def test_problem_validation():
     for kw in bad:
         p = S.Problem(**kw)
         assert _ws(p, 1)[0] == S.SGCM_EINVAL, kw
-    assert _ws(S.Problem(precision=S.FP32), 1)[0] == S.SGCM_EUNSUPPORTED
+    assert _ws(S.Problem(precision=S.FP32), 1)[0] == S.SGCM_OK  # FP32 inexact Newton
+    assert _ws(S.Problem(precision=7), 1)[0] == S.SGCM_EINVAL
 
 
 def test_entry_points_validate_before_device_work():
