@@ -202,6 +202,27 @@ def precision_leg(dev, prob, grid, x0, lam64, u064, it64, surplus, reps: int) ->
             "note": "errors against the FP64 GPU results, which match the FP64 oracle to ~1e-13"}
 
 
+def serving_leg(n_requests: int, rate: float) -> dict:
+    """The serving loop on a seeded Poisson stream of mixed requests: solves of
+    1..512 states (meshes 64..512, three- or two-wheel model) and queries of
+    1..1e5 states against resident level-3/4/5 interpolants (FP64 or FP32).
+    Reported: p50/p99 latency (arrival to results on the host) and throughput
+    at the given rate with continuous batching on four streams; the same stream
+    served one request per launch on one stream; and the capacity with every
+    request present at once."""
+    from paper_1507_04769_amd import serving as SV
+    interps = {lv: SV.build_interpolant(lv, N=256) for lv in (3, 4, 5)}
+    warm = SV.request_stream(40, rate, seed=700, levels=(3, 4, 5))
+    SV.Server(interps).run(warm, realtime=False)
+    reqs = SV.request_stream(n_requests, rate, seed=701, levels=(3, 4, 5))
+    out = {"requests": n_requests, "rate_per_s": rate, "seed": 701, "interpolant_levels": [3, 4, 5],
+           "streams": 4, "hbm_budget_bytes": 1 << 30}
+    out["continuous"] = SV.Server(interps, n_streams=4, hbm_budget=1 << 30).run(reqs, realtime=True)
+    out["one_per_launch"] = SV.Server(interps, n_streams=1, merge=False).run(reqs, realtime=True)
+    out["capacity_all_at_once"] = SV.Server(interps, n_streams=4).run(reqs, realtime=False)["throughput"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,6 +233,9 @@ def main():
     ap.add_argument("--cpu-queries", type=int, default=20000)
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-batch leg")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32 leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-rate", type=float, default=2000.0, help="requests per second")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -286,6 +310,9 @@ def main():
     precision = None
     if not args.no_precision and args.workload == "full":
         precision = precision_leg(dev, prob, grid, x0, lam, u0, iters, surplus, 5)
+    serving = None
+    if not args.no_serving and args.workload == "full":
+        serving = serving_leg(args.serving_requests, args.serving_rate)
 
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 8
@@ -326,6 +353,8 @@ def main():
         out["batched"] = batched
     if precision is not None:
         out["precision"] = precision
+    if serving is not None:
+        out["serving"] = serving
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, nodes, xq_host)
     print(json.dumps(out), flush=True)

@@ -235,7 +235,7 @@ int sgcm_eval_feedback(const sgcm_grid* g, int32_t m, const double* surplus, int
  * step): surplus (M x m), xq (n_q x d) and uq (n_q x m) are FP32 device
  * arrays; the 1-D Lagrange basis values, their products and the sum over the
  * nodes are computed in FP32 (the map to the unit cube in FP64, then rounded).
- * Supported for d = 6, levels 1..4 and m <= 3, else SGCM_EUNSUPPORTED.  The
+ * Supported for d = 6, levels 1..5 and m <= 3, else SGCM_EUNSUPPORTED.  The
  * error against the FP64 evaluation is that of FP32 rounding in a sum of M
  * terms (about 1e-6 of max|u| on the rigid-body feedback). */
 int sgcm_eval_feedback_f32(const sgcm_grid* g, int32_t m, const float* surplus, int64_t n_q,

@@ -452,8 +452,8 @@ hipError_t fast_m(int m, const GridArgs& a, int64_t nq, const F* w, const F* xq,
   }
 }
 
-// The unrolled kernel covers d = 6, levels 1..4, m <= 3 (the rigid-body feedback).
-bool fast_eval_applies(const Grid& G, int m) { return G.d == 6 && G.level >= 1 && G.level <= 4 && m <= 3; }
+// The unrolled kernel covers d = 6, levels 1..5, m <= 3 (the rigid-body feedback).
+bool fast_eval_applies(const Grid& G, int m) { return G.d == 6 && G.level >= 1 && G.level <= 5 && m <= 3; }
 
 template <typename F>
 hipError_t eval_fast(const Grid& G, int m, const GridArgs& a, int64_t nq, const F* w, const F* xq, F* uq,
@@ -462,7 +462,8 @@ hipError_t eval_fast(const Grid& G, int m, const GridArgs& a, int64_t nq, const 
     case 1: return fast_m<1, F>(m, a, nq, w, xq, uq, s);
     case 2: return fast_m<2, F>(m, a, nq, w, xq, uq, s);
     case 3: return fast_m<3, F>(m, a, nq, w, xq, uq, s);
-    default: return fast_m<4, F>(m, a, nq, w, xq, uq, s);
+    case 4: return fast_m<4, F>(m, a, nq, w, xq, uq, s);
+    default: return fast_m<5, F>(m, a, nq, w, xq, uq, s);
   }
 }
 

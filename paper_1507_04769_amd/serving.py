@@ -1,0 +1,316 @@
+"""Continuous-batching request loop for the hot path (the serving direction).
+
+Requests arrive over time (a seeded Poisson stream): BVP-solve requests (a
+few initial states of the three- or two-wheel model on a mesh of N intervals)
+and feedback-query requests (states to evaluate against an interpolant kept
+resident on the device, in FP64 or FP32).  The loop
+
+  * admits arrived requests into a pending list;
+  * merges pending requests with the same key (model and N for solves;
+    interpolant and precision for queries) into one launch: a solve launch
+    concatenates the initial states of several requests into one
+    sgcm_solve_bvps call, a query launch the states of several requests into
+    one evaluation call;
+  * starts a launch whenever one of its streams is free and the device
+    memory of the launches in flight stays within an HBM budget (admission by
+    footprint: states, outputs and workspace of the launch), so that requests
+    arriving while others run are admitted as slots and memory free up and
+    their work overlaps on the device;
+  * retires launches whose completion event has fired and hands every request
+    its slice of the outputs.
+
+Every output of a request depends only on that request's inputs (BVPs and
+query points are independent), so a request's results are the same alone and
+in any mix; the tests check this bitwise.  Latency = completion - arrival on
+the host clock (completions are seen by polling events).
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+import paper_1507_04769_amd as S
+from paper_1507_04769_amd import workloads as W
+
+
+@dataclass
+class SolveRequest:
+    rid: int
+    arrival: float      # seconds after the stream starts
+    x0: np.ndarray      # n x 6 initial states
+    N: int              # mesh intervals
+    m: int = 3          # wheels: 3 or 2
+    T: float = 20.0     # horizon
+    out: dict = field(default=None, repr=False)
+    done: float = None
+
+    def key(self):
+        return ("solve", self.m, self.N, self.T)
+
+
+@dataclass
+class QueryRequest:
+    rid: int
+    arrival: float
+    xq: np.ndarray      # n x 6 states
+    level: int          # resident interpolant (grid level)
+    fp32: bool = False
+    out: np.ndarray = field(default=None, repr=False)
+    done: float = None
+
+    def key(self):
+        return ("query", self.level, self.fp32)
+
+
+def problem(m: int, N: int, T: float = 20.0) -> S.Problem:
+    return S.Problem(m=m, J=W.J_DIAG, B=W.input_matrix(m), q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W, T=T, N=N,
+                     tol=W.TOL, max_iter=W.MAX_ITER)
+
+
+class Interpolant:
+    """A feedback interpolant resident on the device (FP64 and FP32 surplus)."""
+
+    def __init__(self, level: int, surplus64):
+        self.level = level
+        self.grid = S.Grid(6, level, W.BOX_LO, W.BOX_HI)
+        self.w64 = surplus64
+        self.w32 = surplus64.float().contiguous()
+
+
+def build_interpolant(level: int, N: int = 64):
+    """Interpolant of u(0) of the three-wheel problem on the level-`level` grid
+    (solved on the device)."""
+    import torch
+    g = S.Grid(6, level, W.BOX_LO, W.BOX_HI)
+    sol = S.solve_bvps(problem(3, N), torch.tensor(g.nodes(), device="cuda"))
+    return Interpolant(level, S.build_interpolant(g, sol.u0))
+
+
+@dataclass
+class _Launch:
+    reqs: list
+    stream: object
+    event: object
+    nbytes: int
+    outs: tuple
+
+
+def request_size(r) -> int:
+    return len(r.x0) if isinstance(r, SolveRequest) else len(r.xq)
+
+
+def footprint(key, n: int) -> int:
+    """Device bytes a launch of n states (solve) or points (query) holds:
+    inputs, outputs and, for a solve, the solver workspace."""
+    if key[0] == "solve":
+        m, N, T = key[1], key[2], key[3]
+        return S.sgcm_solve_bvps_workspace(problem(m, N, T), n) + n * 8 * (6 + 6 + m + 1) + n * 4 * 2
+    return n * (4 if key[2] else 8) * (6 + 3)
+
+
+class Admission:
+    """Which pending requests start next (host-side policy).
+
+    The oldest pending request leads (first come, first served, so nothing
+    starves); later pending requests with the same key join it while the
+    merged launch stays within its size cap and the device memory of all
+    launches in flight within the budget.  If the oldest request does not fit
+    next to the launches in flight, nothing starts until memory frees up; a
+    request larger than the whole budget starts alone on an idle device."""
+
+    def __init__(self, hbm_budget: int, max_bvps: int = 2048, max_points: int = 1 << 20,
+                 merge: bool = True, footprint=footprint):
+        self.budget = int(hbm_budget)
+        self.max_bvps = max_bvps
+        self.max_points = max_points
+        self.merge = merge
+        self.footprint = footprint
+
+    def select(self, pending: list, used: int):
+        """(key, chosen requests, merged size, bytes) or None."""
+        if not pending:
+            return None
+        key = pending[0].key()
+        cap = self.max_bvps if key[0] == "solve" else self.max_points
+        chosen, n = [pending[0]], request_size(pending[0])
+        if used > 0 and used + self.footprint(key, n) > self.budget:
+            return None
+        if self.merge:
+            for r in pending[1:]:
+                if r.key() != key:
+                    continue
+                k = request_size(r)
+                if n + k > cap or used + self.footprint(key, n + k) > self.budget:
+                    break
+                chosen.append(r)
+                n += k
+        return key, chosen, n, self.footprint(key, n)
+
+
+class Server:
+    def __init__(self, interpolants: dict, n_streams: int = 4, hbm_budget: int = 1 << 30,
+                 max_bvps: int = 2048, max_points: int = 1 << 20, merge: bool = True):
+        """interpolants: level -> resident Interpolant; n_streams: launches in
+        flight at once; hbm_budget: device bytes the launches in flight may
+        hold; max_bvps / max_points: size cap of one merged launch;
+        merge=False serves one request per launch."""
+        import torch
+        self.interp = interpolants
+        self.admit = Admission(hbm_budget, max_bvps, max_points, merge)
+        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.dev = torch.device("cuda")
+
+    def _launch(self, key, reqs, n, stream) -> _Launch:
+        import torch
+        with torch.cuda.stream(stream):
+            if key[0] == "solve":
+                m, N, T = key[1], key[2], key[3]
+                p = problem(m, N, T)
+                xh = torch.from_numpy(np.concatenate([r.x0 for r in reqs])).pin_memory()
+                x = xh.to(self.dev, non_blocking=True)
+                ws = torch.empty((max(S.sgcm_solve_bvps_workspace(p, n), 256) + 255) // 256 * 32,
+                                 dtype=torch.float64, device=self.dev)
+                lam = torch.empty((n, 6), dtype=torch.float64, device=self.dev)
+                u0 = torch.empty((n, m), dtype=torch.float64, device=self.dev)
+                V = torch.empty((n,), dtype=torch.float64, device=self.dev)
+                st = torch.empty((n,), dtype=torch.int32, device=self.dev)
+                it = torch.empty((n,), dtype=torch.int32, device=self.dev)
+                S.sgcm_solve_bvps(p, x, lam, u0, V, None, st, it, ws, stream)
+                outs = tuple(t.to("cpu", non_blocking=True) for t in (lam, u0, V, st, it))
+                keep = (xh, x, ws, lam, u0, V, st, it)
+            else:
+                itp = self.interp[key[1]]
+                fp32 = key[2]
+                xq = np.concatenate([r.xq for r in reqs])
+                xh = torch.from_numpy(xq.astype(np.float32) if fp32 else xq).pin_memory()
+                x = xh.to(self.dev, non_blocking=True)
+                if fp32:
+                    uq = torch.empty((n, itp.w32.shape[1]), dtype=torch.float32, device=self.dev)
+                    S.sgcm_eval_feedback_f32(itp.grid, itp.w32, x, uq, stream)
+                else:
+                    uq = torch.empty((n, itp.w64.shape[1]), dtype=torch.float64, device=self.dev)
+                    S.sgcm_eval_feedback(itp.grid, itp.w64, x, uq, S.FP64, stream)
+                outs = (uq.to("cpu", non_blocking=True),)
+                keep = (xh, x, uq)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        L = _Launch(reqs, stream, ev, footprint(key, n), outs)
+        L.keep = keep  # device buffers stay referenced until the launch retires
+        return L
+
+    def _retire(self, L: _Launch, now: float):
+        if L.reqs[0].key()[0] == "solve":
+            lam, u0, V, st, it = (t.numpy() for t in L.outs)
+            i = 0
+            for r in L.reqs:
+                k = len(r.x0)
+                r.out = {"lambda0": lam[i:i + k].copy(), "u0": u0[i:i + k].copy(), "V": V[i:i + k].copy(),
+                         "status": st[i:i + k].copy(), "iters": it[i:i + k].copy()}
+                r.done = now
+                i += k
+        else:
+            uq = L.outs[0].numpy()
+            i = 0
+            for r in L.reqs:
+                k = len(r.xq)
+                r.out = uq[i:i + k].copy()
+                r.done = now
+                i += k
+
+    def run(self, requests: list, realtime: bool = True) -> dict:
+        """Serve the requests (sorted by arrival).  realtime: inject each
+        request at its arrival time on the host clock; else all at once."""
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        pending, inflight = [], []
+        free = list(self.streams)
+        used = peak_used = peak_shared = peak_inflight = 0
+        i = 0
+        launches = 0
+        t0 = time.perf_counter()
+        while i < len(reqs) or pending or inflight:
+            now = time.perf_counter() - t0
+            while i < len(reqs) and (not realtime or reqs[i].arrival <= now):
+                pending.append(reqs[i])
+                i += 1
+            for L in list(inflight):
+                if L.event.query():
+                    self._retire(L, time.perf_counter() - t0)
+                    inflight.remove(L)
+                    free.append(L.stream)
+                    used -= L.nbytes
+            started = False
+            while free and pending:
+                g = self.admit.select(pending, used)
+                if g is None:
+                    break
+                key, chosen, n, _ = g
+                L = self._launch(key, chosen, n, free.pop(0))
+                for r in chosen:
+                    pending.remove(r)
+                inflight.append(L)
+                used += L.nbytes
+                launches += 1
+                started = True
+                peak_used = max(peak_used, used)
+                peak_inflight = max(peak_inflight, len(inflight))
+                if len(inflight) > 1:
+                    peak_shared = max(peak_shared, used)
+            if not started and not (i < len(reqs) and (not realtime or reqs[i].arrival <= now)):
+                time.sleep(20e-6)
+        wall = time.perf_counter() - t0
+        lat = np.array([r.done - (r.arrival if realtime else 0.0) for r in reqs]) * 1e3
+        n_bvps = sum(len(r.x0) for r in reqs if isinstance(r, SolveRequest))
+        n_pts = sum(len(r.xq) for r in reqs if isinstance(r, QueryRequest))
+        return {"requests": len(reqs), "launches": launches, "wall_s": wall,
+                "peak_inflight": peak_inflight, "peak_inflight_bytes": peak_used,
+                "peak_shared_bytes": peak_shared,
+                "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                               "max": float(lat.max())},
+                "throughput": {"requests_per_s": len(reqs) / wall, "bvps_per_s": n_bvps / wall,
+                               "evals_per_s": n_pts / wall}}
+
+
+def request_stream(n: int, rate: float, seed: int, levels=(3, 4), max_states: int = 512,
+                   max_points: int = 100_000, meshes=(64, 128, 256, 512)) -> list:
+    """A seeded Poisson stream of n requests at `rate` per second: half solve
+    requests (1..max_states states uniform in the box, N from `meshes`, T = 20;
+    one in four on the two-wheel model, whose states are drawn in 0.3 x the box
+    with T = 2, where its undamped Newton iteration converges), half query requests
+    (1..max_points states uniform in the box against one of `levels`, one in
+    two in FP32)."""
+    g = np.random.default_rng(seed)
+    t = np.cumsum(g.exponential(1.0 / rate, size=n))
+    out = []
+    for k in range(n):
+        if g.random() < 0.5:
+            m = 2 if g.random() < 0.25 else 3
+            ns = int(g.integers(1, max_states + 1))
+            x0 = W.uniform_in_box(ns, seed=int(g.integers(1 << 30)))
+            if m == 2:
+                x0 = 0.3 * x0
+            out.append(SolveRequest(k, float(t[k]), x0, int(g.choice(meshes)), m, 2.0 if m == 2 else 20.0))
+        else:
+            npts = int(np.exp(g.uniform(0.0, np.log(max_points))))
+            xq = W.uniform_in_box(max(npts, 1), seed=int(g.integers(1 << 30)))
+            out.append(QueryRequest(k, float(t[k]), xq, int(g.choice(levels)), bool(g.random() < 0.5)))
+    return out
+
+
+def solve_alone(r: SolveRequest) -> dict:
+    import torch
+    sol = S.solve_bvps(problem(r.m, r.N, r.T), torch.tensor(r.x0, device="cuda"))
+    torch.cuda.synchronize()
+    return {k: getattr(sol, k).cpu().numpy() for k in ("lambda0", "u0", "V", "status", "iters")}
+
+
+def query_alone(r: QueryRequest, itp: Interpolant) -> np.ndarray:
+    import torch
+    if r.fp32:
+        out = S.eval_feedback_f32(itp.grid, itp.w32, torch.tensor(r.xq, device="cuda"))
+    else:
+        out = S.eval_feedback(itp.grid, itp.w64, torch.tensor(r.xq, device="cuda"))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()

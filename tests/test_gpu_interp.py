@@ -31,7 +31,7 @@ def dev(a):
     return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
 
 
-# d = 6 with levels 1..4 and m <= 3 takes the kernel whose inner trie is
+# d = 6 with levels 1..5 and m <= 3 takes the kernel whose inner trie is
 # unrolled at compile time; everything else takes the generic trie walk.
 CASES = [(1, 0), (1, 5), (2, 3), (3, 4), (4, 1), (6, 1), (6, 2), (6, 3), (6, 4), (6, 5), (8, 2)]
 

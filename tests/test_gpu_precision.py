@@ -38,7 +38,7 @@ def rel_err(a, b):
     return np.max(np.abs(a - b), axis=1) / np.maximum(np.max(np.abs(b), axis=1), 1e-8)
 
 
-@pytest.mark.parametrize("level", [1, 2, 3, 4])
+@pytest.mark.parametrize("level", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("m", [1, 3])
 def test_fp32_eval_vs_oracle(level, m):
     torch = _torch()

@@ -1,0 +1,102 @@
+"""Serving loop (continuous batching of solve and query requests) on the GPU.
+
+Every request's results must be bitwise the same served alone (one call of
+the plain entry point on its own inputs) and served inside a mixed stream,
+merged with other requests into shared launches on several streams; a sample
+is also checked against the oracle.  The stream mixes three- and two-wheel
+solve requests on meshes of 64..512 intervals with FP64 and FP32 queries
+against resident level-3/4/5 interpolants.
+"""
+import numpy as np
+import pytest
+
+import paper_1507_04769_amd as S
+from oracle import oracle as O
+from paper_1507_04769_amd import serving as SV
+from paper_1507_04769_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def interps():
+    return {lv: SV.build_interpolant(lv) for lv in (3, 4, 5)}
+
+
+def check_alone(reqs, interps):
+    for r in reqs:
+        assert r.done is not None, r.rid
+        if isinstance(r, SV.SolveRequest):
+            a = SV.solve_alone(r)
+            for k in ("lambda0", "u0", "V", "status", "iters"):
+                assert np.array_equal(a[k], r.out[k]), (r.rid, k)
+            if r.m == 3:
+                assert np.all(r.out["status"] == S.CONVERGED), r.rid
+        else:
+            a = SV.query_alone(r, interps[r.level])
+            assert a.dtype == r.out.dtype and np.array_equal(a, r.out), r.rid
+
+
+def test_mixed_stream_all_at_once_matches_alone(interps):
+    reqs = SV.request_stream(48, rate=1e4, seed=600, levels=(3, 4, 5), max_states=96, max_points=30000)
+    srv = SV.Server(interps, n_streams=4)
+    st = srv.run(reqs, realtime=False)
+    assert st["launches"] < st["requests"]  # requests with a common key were merged
+    assert st["peak_inflight"] > 1
+    check_alone(reqs, interps)
+
+
+def test_realtime_stream_small_budget(interps):
+    # a budget of 64 MiB (a solve of 256 states on 512 intervals alone needs
+    # ~120 MiB of workspace): launches wait for memory, and whenever more than
+    # one launch is in flight their memory stays within the budget (a launch
+    # larger than the budget runs alone)
+    reqs = SV.request_stream(40, rate=400.0, seed=601, levels=(3, 4, 5), max_states=256, max_points=50000)
+    budget = 64 << 20
+    srv = SV.Server(interps, n_streams=3, hbm_budget=budget)
+    st = srv.run(reqs, realtime=True)
+    assert st["peak_shared_bytes"] <= budget
+    assert st["peak_inflight"] > 1
+    lat = st["latency_ms"]
+    assert 0 < lat["p50"] <= lat["p99"] <= lat["max"]
+    check_alone(reqs, interps)
+
+
+def test_unmerged_serial_equals_merged(interps):
+    reqs = SV.request_stream(16, rate=1e4, seed=602, levels=(3, 5), max_states=40, max_points=5000)
+    st = SV.Server(interps, n_streams=1, merge=False).run(reqs, realtime=False)
+    assert st["launches"] == st["requests"]
+    first = [r.out for r in reqs]
+    SV.Server(interps, n_streams=4).run(reqs, realtime=False)
+    for a, r in zip(first, reqs):
+        if isinstance(a, dict):
+            assert all(np.array_equal(a[k], r.out[k]) for k in a)
+        else:
+            assert np.array_equal(a, r.out)
+
+
+def test_served_results_match_oracle(interps):
+    # a few small solve requests and FP64 queries through the server, against
+    # the oracle: its BVP solver on the same states, and its interpolant
+    # evaluation of the resident surplus
+    g = np.random.default_rng(603)
+    reqs = [SV.SolveRequest(0, 0.0, W.uniform_in_box(3, seed=604), 64, 3, 20.0),
+            SV.SolveRequest(1, 0.0, W.uniform_in_box(2, seed=605), 64, 3, 20.0),
+            SV.SolveRequest(2, 0.0, 0.3 * W.uniform_in_box(2, seed=606), 128, 2, 2.0),
+            SV.QueryRequest(3, 0.0, W.uniform_in_box(300, seed=607), 4, False),
+            SV.QueryRequest(4, 0.0, W.uniform_in_box(200, seed=608), 5, False)]
+    g.shuffle(reqs)
+    SV.Server(interps, n_streams=2).run(reqs, realtime=False)
+    for r in reqs:
+        if isinstance(r, SV.SolveRequest):
+            op = O.Problem(n=6, m=r.m, J=W.J_DIAG, B=W.input_matrix(r.m), q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W,
+                           T=r.T, N=r.N, tol=W.TOL, max_iter=W.MAX_ITER)
+            o = O.solve_bvps(op, r.x0)
+            assert np.array_equal(r.out["status"], o.status) and np.array_equal(r.out["iters"], o.iters)
+            err = np.abs(r.out["lambda0"] - o.lambda0).max(axis=1) / np.abs(o.lambda0).max(axis=1)
+            assert np.all(err <= 1e-8)
+        else:
+            itp = interps[r.level]
+            w = itp.w64.cpu().numpy()
+            ref = O.eval_hier(6, r.level, w, r.xq, W.BOX_LO, W.BOX_HI)
+            assert np.max(np.abs(r.out - ref)) <= 1e-8 * max(1.0, np.abs(ref).max())
