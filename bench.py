@@ -216,10 +216,10 @@ def serving_leg(n_requests: int, rate: float) -> dict:
     SV.Server(interps).run(warm, realtime=False)
     reqs = SV.request_stream(n_requests, rate, seed=701, levels=(3, 4, 5))
     out = {"requests": n_requests, "rate_per_s": rate, "seed": 701, "interpolant_levels": [3, 4, 5],
-           "streams": 4, "hbm_budget_bytes": 1 << 30}
-    out["continuous"] = SV.Server(interps, n_streams=4, hbm_budget=1 << 30).run(reqs, realtime=True)
+           "streams": 4, "hbm_budget_bytes": 8 << 30}
+    out["continuous"] = SV.Server(interps, n_streams=4, hbm_budget=8 << 30).run(reqs, realtime=True)
     out["one_per_launch"] = SV.Server(interps, n_streams=1, merge=False).run(reqs, realtime=True)
-    out["capacity_all_at_once"] = SV.Server(interps, n_streams=4).run(reqs, realtime=False)["throughput"]
+    out["capacity_all_at_once"] = SV.Server(interps, n_streams=4, hbm_budget=8 << 30).run(reqs, realtime=False)["throughput"]
     return out
 
 
