@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "converged 6-D BVPs/s at tol 1e-10 + feedback evals/s; p50/p99 latency"
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector (and matrix) peak
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak
 
 # Algorithmic FP64 work of the Newton solve (the counts are derived in the
 # design notes):
@@ -35,7 +36,10 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector (and matrix) peak
 #   = 1152 + 2016 for n = 12, k = 7) and the forward pass with the update (156);
 #   per mesh point and evaluation: Phi, A = df/dx and W (172) and the interval
 #   residual (48).  Transcendentals (two sincos per point) are not counted.
-FLOPS_PER_INTERVAL_SOLVE = 1098 + 1152 + 2016 + 156
+#   In the first (linearised) step every interval has the same system, so its
+#   assembly is counted once per BVP, not once per interval.
+FLOPS_ASSEMBLY = 1098
+FLOPS_PER_INTERVAL_SOLVE = FLOPS_ASSEMBLY + 1152 + 2016 + 156
 FLOPS_PER_POINT_EVAL = 172 + 48
 
 
@@ -61,11 +65,20 @@ def measured_traffic() -> float | None:
     return float(t.group(1))
 
 
-def newton_flops(N: int, iters: np.ndarray) -> float:
-    """Algorithmic flops of one sgcm_solve_bvps launch: (iters + 1) linear
-    solves (the first is the linearised step) and (iters + 2) evaluations."""
+def newton_flops(N, iters: np.ndarray) -> float:
+    """Algorithmic flops of solving BVPs with N intervals (a number, or one per
+    BVP) in the given iteration counts: (iters + 1) linear solves (the first is
+    the linearised step) and (iters + 2) evaluations per BVP."""
     it = iters.astype(np.float64)
-    return float(np.sum((it + 1) * N * FLOPS_PER_INTERVAL_SOLVE + (it + 2) * (N + 1) * FLOPS_PER_POINT_EVAL))
+    N = np.asarray(N, dtype=np.float64) + 0 * it
+    solves = (it + 1) * N * FLOPS_PER_INTERVAL_SOLVE - (N - 1) * FLOPS_ASSEMBLY
+    return float(np.sum(solves + (it + 2) * (N + 1) * FLOPS_PER_POINT_EVAL))
+
+
+def alu_roofline(kernel: str, flops: float, ms: float, peak: float) -> dict:
+    achieved = flops / (ms / 1e3) / 1e12
+    return {"kernel": kernel, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "algorithmic_flops_per_launch": flops}
 
 
 def eval_flops_per_query(grid_keys: np.ndarray, level: int, m: int) -> float:
@@ -143,7 +156,9 @@ def batched_leg(dev, reps: int) -> dict:
     run, ngroups = A.unbatched_runner(problem, x0, N, T)
     ums = A.time_ms(run, reps)
     bms, ubms = float(np.median(ms)), float(np.median(ums))
+    flops = newton_flops(N, it.cpu().numpy())
     return {"workload": "mixed batch: " + A.W.BATCH.name, "n_bvps": n, "converged": converged,
+            "roofline": alu_roofline("k_newton_batch<double>", flops, bms, PEAK_FP64_TFLOPS),
             "schedule": {"order": "larger N*T first" if order == S.ORDER_LONGEST_FIRST else "as given",
                          "slots_per_cu": slots, "source": os.path.relpath(src, ROOT) if src else "default"},
             "graph": True, "ms": bms, "bvps_per_s": converged / (bms / 1e3),
@@ -151,7 +166,7 @@ def batched_leg(dev, reps: int) -> dict:
             "speedup_vs_unbatched": ubms / bms}
 
 
-def precision_leg(dev, prob, grid, x0, lam64, u064, it64, surplus, reps: int) -> dict:
+def precision_leg(dev, prob, grid, x0, lam64, u064, it64, surplus, eval_flops_q: float, reps: int) -> dict:
     """FP32 variants beside the FP64 path on the same MI355X: the FP32 inexact
     Newton solve of the full workload (errors against the FP64 GPU solve, which
     matches the oracle to ~1e-13) and FP32 feedback evaluation at 1e7 uniform
@@ -179,7 +194,12 @@ def precision_leg(dev, prob, grid, x0, lam64, u064, it64, surplus, reps: int) ->
     el = ((lam - lam64).abs().amax(dim=1) / lam64.abs().amax(dim=1).clamp_min(1e-8)).cpu().numpy()
     eu = ((u0 - u064).abs().amax(dim=1) / u064.abs().amax(dim=1).clamp_min(1e-8)).cpu().numpy()
     i32, i64 = it.cpu().numpy(), it64
-    solve = {"ms": float(np.median(ms32)), "fp64_ms": float(np.median(ms64)),
+    # the same algorithmic flops as the FP64 solve; the linear solve (95 % of
+    # them) runs in FP32, so the fraction is given against both peaks
+    f32 = newton_flops(prob.N, i32)
+    rf = alu_roofline("k_newton<float>", f32, float(np.median(ms32)), PEAK_FP32_TFLOPS)
+    rf["frac_of_fp64_peak"] = rf["achieved"] / PEAK_FP64_TFLOPS
+    solve = {"ms": float(np.median(ms32)), "fp64_ms": float(np.median(ms64)), "roofline": rf,
              "bvps_per_s": conv / (float(np.median(ms32)) / 1e3), "converged": conv,
              "mean_iters": float(i32.mean()), "fp64_mean_iters": float(i64.mean()),
              "lambda0_rel_err": {"max": float(el.max()), "rms": float(np.sqrt(np.mean(el ** 2)))},
@@ -197,7 +217,11 @@ def precision_leg(dev, prob, grid, x0, lam64, u064, it64, surplus, reps: int) ->
     ev = {"queries": nq, "ms": float(np.median(e32)), "fp64_ms": float(np.median(e64)),
           "evals_per_s": nq / (float(np.median(e32)) / 1e3), "fp64_evals_per_s": nq / (float(np.median(e64)) / 1e3),
           "abs_err": {"max": float(err.max().item()), "rms": float(err.pow(2).mean().sqrt().item())},
-          "max_abs_u": scale}
+          "max_abs_u": scale,
+          "roofline": alu_roofline("k_eval_fast<6, %d, 3, float>" % grid.level, eval_flops_q * nq,
+                                   float(np.median(e32)), PEAK_FP32_TFLOPS),
+          "fp64_roofline": alu_roofline("k_eval_fast<6, %d, 3, double>" % grid.level, eval_flops_q * nq,
+                                        float(np.median(e64)), PEAK_FP64_TFLOPS)}
     return {"fp32_newton": solve, "fp32_eval": ev,
             "note": "errors against the FP64 GPU results, which match the FP64 oracle to ~1e-13"}
 
@@ -305,11 +329,12 @@ def main():
     value = converged * args.steps / total_s
     flops = newton_flops(wl.n_intervals, iters)
     achieved = flops / (float(np.mean(solve_ms)) / 1e3) / 1e12
+    eval_flops_q = eval_flops_per_query(grid.keys(), wl.level, wl.m)
 
     batched = None if args.no_batched or args.workload != "full" else batched_leg(dev, 5)
     precision = None
     if not args.no_precision and args.workload == "full":
-        precision = precision_leg(dev, prob, grid, x0, lam, u0, iters, surplus, 5)
+        precision = precision_leg(dev, prob, grid, x0, lam, u0, iters, surplus, eval_flops_q, 5)
     serving = None
     if not args.no_serving and args.workload == "full":
         serving = serving_leg(args.serving_requests, args.serving_rate)
@@ -348,6 +373,8 @@ def main():
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": measured_traffic() if wl.name == W.FULL.name else None,
                      "algorithmic_flops_per_launch": flops},
+        "eval_roofline": alu_roofline("k_eval_fast<6, %d, %d, double>" % (wl.level, wl.m),
+                                      eval_flops_q * len(xq_host), float(np.mean(eval_ms)), PEAK_FP64_TFLOPS),
     }
     if batched is not None:
         out["batched"] = batched

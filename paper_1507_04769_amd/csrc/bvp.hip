@@ -515,123 +515,130 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
     bool singular = false;
     while (true) {
       const int nb = khi - klo + 1;
-      // point blocks of points klo - 1 .. khi into slots 0 .. nb (the
-      // residual of point p is r_p, the residual of interval p; row 0 of R
-      // holds F_0, F_N and is never used as an interval residual)
-      wave_mem_sync();  // the stage has landed
-      {
-        const int l = opaque_lane(lane0);
-        if (l <= nb) {
-          double py[12], pt[4];
-          T* slot = sh.u.b.pts + l * kPt;
+      // In the first (linearised) step Y = 0: every mesh point has the same
+      // y, trigonometric factors and interval residual (zero), so every
+      // interval has the same constants.  They are formed in the first batch
+      // and the later batches reuse them from LDS.
+      const bool reuse = it < 0 && khi != N;
+      if (!reuse) {
+        // point blocks of points klo - 1 .. khi into slots 0 .. nb (the
+        // residual of point p is r_p, the residual of interval p; row 0 of R
+        // holds F_0, F_N and is never used as an interval residual)
+        wave_mem_sync();  // the stage has landed
+        {
+          const int l = opaque_lane(lane0);
+          if (l <= nb) {
+            double py[12], pt[4];
+            T* slot = sh.u.b.pts + l * kPt;
 #pragma unroll
-          for (int i = 0; i < 12; ++i) {
-            py[i] = sh.stage[l * 12 + i];
-            slot[108 + i] = sh.stage[108 + l * 12 + i];
+            for (int i = 0; i < 12; ++i) {
+              py[i] = sh.stage[l * 12 + i];
+              slot[108 + i] = sh.stage[108 + l * 12 + i];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) pt[i] = sh.stage[216 + l * 4 + i];
+            point_blocks(P, alpha, py, pt, slot, &sh.flag);
           }
-#pragma unroll
-          for (int i = 0; i < 4; ++i) pt[i] = sh.stage[216 + l * 4 + i];
-          point_blocks(P, alpha, py, pt, slot, &sh.flag);
         }
-      }
-      lds_handoff();
-      if (sh.flag) {
-        singular = true;
-        break;
-      }
-      // interval constants of interval k = khi - tl, lane (tl, rows i and i + 3):
-      // rows of K = L_k [I + a A_{k-1} | a e_rates | -r^x], F = L_{k-1}^T (I + a A_k^T),
-      // H = a L_{k-1}^T W_k, Gam = a L_{k-1}^T W_{k-1} and -D^{-1} r^l = -L_{k-1}^T r^l.
-      // Every LDS access is an immediate offset from a per-lane base.
-      {
-        const int l = opaque_lane(lane0);
-        const int tl = l & 7, ip = l >> 3;
-        if (ip < 3 && tl < nb) {
-          const int k = khi - tl;
-          const T* pa = sh.u.b.pts + (k - klo) * kPt;  // point k - 1
-          const T* pb = pa + kPt;                       // point k
-          T* cst = sh.u.b.cst + tl * kCst;
-          T lb[2][6], la[2][6];  // rows i, i + 3 of L_k and of L_{k-1}^T
+        lds_handoff();
+        if (sh.flag) {
+          singular = true;
+          break;
+        }
+        // interval constants of interval k = khi - tl, lane (tl, rows i and i + 3):
+        // rows of K = L_k [I + a A_{k-1} | a e_rates | -r^x], F = L_{k-1}^T (I + a A_k^T),
+        // H = a L_{k-1}^T W_k, Gam = a L_{k-1}^T W_{k-1} and -D^{-1} r^l = -L_{k-1}^T r^l.
+        // Every LDS access is an immediate offset from a per-lane base.
+        {
+          const int l = opaque_lane(lane0);
+          const int tl = l & 7, ip = l >> 3;
+          if (ip < 3 && tl < nb) {
+            const int k = khi - tl;
+            const T* pa = sh.u.b.pts + (k - klo) * kPt;  // point k - 1
+            const T* pb = pa + kPt;                       // point k
+            T* cst = sh.u.b.cst + tl * kCst;
+            T lb[2][6], la[2][6];  // rows i, i + 3 of L_k and of L_{k-1}^T
 #pragma unroll
-          for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int m = 0; m < 6; ++m) {
-              lb[h][m] = pb[72 + (ip + 3 * h) * 6 + m];
-              la[h][m] = pa[72 + m * 6 + ip + 3 * h];
-            }
-          T* kc = cst + ip;              // K[i][o] at kc[o * 6 + 3 h]
-          T* fh = cst + kKc + ip * kFHr;  // row i of [F | H | Gam'] at fh[3 h kFHr + j]
-#pragma unroll
-          for (int o = 0; o < 6; ++o) {
-            T v[6];
-#pragma unroll
-            for (int m = 0; m < 6; ++m) v[m] = pa[m * 6 + o];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              T q = T(0);
-#pragma unroll
-              for (int m = 0; m < 6; ++m) q = fma(lb[h][m], v[m], q);
-              kc[o * 6 + 3 * h] = fma(at, q, lb[h][o]);
-            }
-          }
-#pragma unroll
-          for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) kc[(6 + c) * 6 + 3 * h] = at * lb[h][3 + c];
-          {
-            T v[6];
-#pragma unroll
-            for (int m = 0; m < 6; ++m) v[m] = pb[108 + m];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              T q = T(0);
-#pragma unroll
-              for (int m = 0; m < 6; ++m) q = fma(lb[h][m], v[m], q);
-              kc[54 + 3 * h] = -q;
-            }
-          }
-#pragma unroll
-          for (int j = 0; j < 6; ++j) {
-            T vf[6], vh[6], vg[6];
-#pragma unroll
-            for (int m = 0; m < 6; ++m) {
-              vf[m] = pb[j * 6 + m];        // A_k[j][m]
-              vh[m] = pb[36 + m * 6 + j];   // W_k[m][j]
-              vg[m] = pa[36 + m * 6 + j];   // W_{k-1}[m][j]
-            }
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              T qf = T(0), qh = T(0), qg = T(0);
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
               for (int m = 0; m < 6; ++m) {
-                qf = fma(la[h][m], vf[m], qf);
-                qh = fma(la[h][m], vh[m], qh);
-                qg = fma(la[h][m], vg[m], qg);
+                lb[h][m] = pb[72 + (ip + 3 * h) * 6 + m];
+                la[h][m] = pa[72 + m * 6 + ip + 3 * h];
               }
-              fh[3 * h * kFHr + j] = fma(at, qf, la[h][j]);
-              fh[3 * h * kFHr + 6 + j] = at * qh;
-              fh[3 * h * kFHr + 12 + j] = at * qg;
+            T* kc = cst + ip;              // K[i][o] at kc[o * 6 + 3 h]
+            T* fh = cst + kKc + ip * kFHr;  // row i of [F | H | Gam'] at fh[3 h kFHr + j]
+#pragma unroll
+            for (int o = 0; o < 6; ++o) {
+              T v[6];
+#pragma unroll
+              for (int m = 0; m < 6; ++m) v[m] = pa[m * 6 + o];
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                T q = T(0);
+#pragma unroll
+                for (int m = 0; m < 6; ++m) q = fma(lb[h][m], v[m], q);
+                kc[o * 6 + 3 * h] = fma(at, q, lb[h][o]);
+              }
             }
-          }
-          {
-            T v[6];
 #pragma unroll
-            for (int m = 0; m < 6; ++m) v[m] = pb[114 + m];
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              T q = T(0);
+              for (int c = 0; c < 3; ++c) kc[(6 + c) * 6 + 3 * h] = at * lb[h][3 + c];
+            {
+              T v[6];
 #pragma unroll
-              for (int m = 0; m < 6; ++m) q = fma(la[h][m], v[m], q);
-              fh[3 * h * kFHr + 18] = -q;
+              for (int m = 0; m < 6; ++m) v[m] = pb[108 + m];
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                T q = T(0);
+#pragma unroll
+                for (int m = 0; m < 6; ++m) q = fma(lb[h][m], v[m], q);
+                kc[54 + 3 * h] = -q;
+              }
+            }
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+              T vf[6], vh[6], vg[6];
+#pragma unroll
+              for (int m = 0; m < 6; ++m) {
+                vf[m] = pb[j * 6 + m];        // A_k[j][m]
+                vh[m] = pb[36 + m * 6 + j];   // W_k[m][j]
+                vg[m] = pa[36 + m * 6 + j];   // W_{k-1}[m][j]
+              }
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                T qf = T(0), qh = T(0), qg = T(0);
+#pragma unroll
+                for (int m = 0; m < 6; ++m) {
+                  qf = fma(la[h][m], vf[m], qf);
+                  qh = fma(la[h][m], vh[m], qh);
+                  qg = fma(la[h][m], vg[m], qg);
+                }
+                fh[3 * h * kFHr + j] = fma(at, qf, la[h][j]);
+                fh[3 * h * kFHr + 6 + j] = at * qh;
+                fh[3 * h * kFHr + 12 + j] = at * qg;
+              }
+            }
+            {
+              T v[6];
+#pragma unroll
+              for (int m = 0; m < 6; ++m) v[m] = pb[114 + m];
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                T q = T(0);
+#pragma unroll
+                for (int m = 0; m < 6; ++m) q = fma(la[h][m], v[m], q);
+                fh[3 * h * kFHr + 18] = -q;
+              }
             }
           }
         }
-      }
-      lds_handoff();
+        lds_handoff();
+      }  // !reuse
       // inputs of the next batch, in flight during the chain
       const int nhi = klo - 1;
       const int nlo = nhi - (kNB - 1) < 1 ? 1 : nhi - (kNB - 1);
-      if (nhi >= 1) load_points(nlo, nhi);
+      if (nhi >= 1 && it >= 0) load_points(nlo, nhi);
       // the serial chain: three LDS exchanges per interval.  Lane (i, o),
       // 60 lanes, owns entry (i, o) of the step; columns o = 0..5 (R), 6..8
       // (B) and 9 (rho) of [K ; e_9]; the state columns 0..5 and 9 carry
