@@ -279,10 +279,12 @@ struct __align__(16) SweepShared {
     double pa[2 * 64 * 12];         // residual pass: Phi and y of one 64-point chunk
   } u;
   double stage[kStage];  // point inputs of the next batch (filled by direct global-to-LDS loads)
-  T PR[60];   // [P | c] rows (c in column 6), 10 per row
-  T QC[60];   // columns of Q, 6 per column
-  T TT[30];   // columns of T = (Q + E) rate rows, 3 per column
-  T ER[18];   // rows of E[:, 6..8], 3 per row
+  // chain exchange buffers, one entry per lane: lane 10 i + o holds entry
+  // (i, o) of [P | c] (c in column 9), of Q, of T = (Q + E) and of E
+  T PL[64];
+  T QL[64];
+  T TL[64];
+  T EL[64];
   double carry_phi[12], carry_y[12];
   double xb[6], F0[6], FN[6];
   double zero[8];
@@ -670,7 +672,8 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
           fh[2 * q] = v.x;
           fh[2 * q + 1] = v.y;
         }
-        gam = cst_lane ? fr[12 + cs] : T(0);
+        const T g = fr[12 + cs];
+        gam = cst_lane ? g : T(0);
         kio = cst[co * 6 + ci];
 #pragma unroll
         for (int a = 0; a < 3; ++a) kb[a] = cst[(6 + a) * 6 + ci];
@@ -685,17 +688,19 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       load_consts(0);
       for (int t = 0; t < nb; ++t) {
         const int k = khi - t;
-        // exchange 1: rows of [P_k | c_k]
-        if (cst_lane) sh.PR[ci * 10 + cs] = pv;
+        // exchange 1: rows of [P_k | c_k].  Every exchange writes one entry
+        // per lane, unconditionally, so that no LDS access sits under a
+        // branch and each read waits only for its own exchange.
+        sh.PL[lane0] = pv;
         lds_handoff();
         T prow[7];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          const V2 v = *reinterpret_cast<const V2*>(&sh.PR[ci * 10 + 2 * q]);
+          const V2 v = *reinterpret_cast<const V2*>(&sh.PL[ci * 10 + 2 * q]);
           prow[2 * q] = v.x;
           prow[2 * q + 1] = v.y;
         }
-        prow[6] = sh.PR[ci * 10 + 6];
+        prow[6] = sh.PL[ci * 10 + 9];
         // Q = [P | c] [K ; e_9],  C = H K + [Gam | 0 | -D^{-1} r^l]
         T q = co == 9 ? prow[6] : T(0);
         T cc = gam;
@@ -705,36 +710,29 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
           cc = fma(fh[6 + m], kcol[m], cc);
         }
         // exchange 2: columns of Q
-        if (cv) sh.QC[co * 6 + ci] = q;
+        sh.QL[lane0] = q;
         lds_handoff();
         T qcol[6];
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          const V2 v = *reinterpret_cast<const V2*>(&sh.QC[co * 6 + 2 * r]);
-          qcol[2 * r] = v.x;
-          qcol[2 * r + 1] = v.y;
-        }
+        for (int r = 0; r < 6; ++r) qcol[r] = sh.QL[r * 10 + co];
         T e = -cc;
 #pragma unroll
         for (int m = 0; m < 6; ++m) e = fma(fh[m], qcol[m], e);
         const T tv = q + e;  // T = Psi_w [K ; e_9] on the rate rows
         const T kio_t = kio, kb0 = kb[0], kb1 = kb[1], kb2 = kb[2];
-        // exchange 3: columns of T, rows of E[:, 6..8]; T[:, 6..8] to every lane
-        if (cv && ci >= 3) sh.TT[co * 3 + ci - 3] = tv;
-        if (cv && co >= 6 && co <= 8) sh.ER[ci * 3 + co - 6] = e;
-        T t1[9];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) t1[a * 3 + c] = lane_bcast(tv, (3 + a) * 10 + 6 + c);
+        // exchange 3: column o of T's rate rows, row i of E[:, 6..8], and
+        // T[3..5][6..8] (the same for every lane)
+        sh.TL[lane0] = tv;
+        sh.EL[lane0] = e;
         lds_handoff();
-        T tc[3], er[3];
+        T tc[3], er[3], t1[9];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          tc[a] = sh.TT[co * 3 + a];
-          er[a] = sh.ER[ci * 3 + a];
+          tc[a] = sh.TL[(3 + a) * 10 + co];
+          er[a] = sh.EL[ci * 10 + 6 + a];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) t1[a * 3 + c] = sh.TL[(3 + a) * 10 + 6 + c];
         }
-        if (t + 1 < nb) load_consts(t + 1);
         // the 3 x 3 system Z M = W: Z = S_w^{-1} + T[:, 6..8], W = T when S_w
         // is invertible, else Z = I + S_w T[:, 6..8], W = S_w T; M by the
         // adjugate of Z
@@ -763,6 +761,12 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
         const T j20 = z[3] * z[7] - z[4] * z[6], j21 = z[1] * z[6] - z[0] * z[7], j22 = z[0] * z[4] - z[1] * z[3];
         const T det = z[0] * j00 + z[1] * j10 + z[2] * j20;
         if (det == 0.0) singular = true;
+        // the next interval's constants, issued once this interval's exchange
+        // reads have been consumed (a wait covers every LDS read in flight, so
+        // issued earlier they would lengthen it); the last interval of a
+        // batch reads its own again, so that the reads are not under a branch
+        lds_handoff();
+        load_consts(t + 1 < nb ? t + 1 : t);
         // 1/det: hardware reciprocal estimate refined by two Newton steps
         // (det is O(1) here: no scaling is needed)
         T rd = hw_rcp(det);
