@@ -215,16 +215,19 @@ __device__ __forceinline__ void lds_handoff() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Value of v in lane src (a wave-uniform constant), broadcast through SGPRs.
-__device__ __forceinline__ double lane_bcast(double v, int src) {
+// Value of v in lane J of each 16-lane row, to every lane of that row (DPP
+// row_newbcast): no SGPR round trip, the result lands in VGPRs.
+template <int J>
+__device__ __forceinline__ double row_bcast(double v) {
   const long long bits = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)bits, src);
-  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
+  const int lo = __builtin_amdgcn_mov_dpp((int)bits, 0x150 + J, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(bits >> 32), 0x150 + J, 0xf, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__device__ __forceinline__ float lane_bcast(float v, int src) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+template <int J>
+__device__ __forceinline__ float row_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + J, 0xf, 0xf, false));
 }
 
 typedef double dbl2 __attribute__((ext_vector_type(2)));
@@ -259,7 +262,7 @@ constexpr int kPt = 122;           // per point: A (36), W (36), L (36), r (12),
 constexpr int kKc = 60;            // K = [R | B | rho], column-major, 6 per column
 constexpr int kFHr = 22;           // row of F (6), H (6), Gam' (7), pad
 constexpr int kCst = kKc + 6 * kFHr + 2;  // per interval, 4 banks apart
-constexpr int kFwd = 12;           // intervals per forward-pass chunk (two chunk buffers)
+constexpr int kFwd = 12;           // intervals per forward-pass chunk (two chunk buffers; even)
 constexpr int kZI = 84;            // interval solution [G g ; P c], row-major 12 x 7
 constexpr int kFwdY = 12 * (kFwd + 1);     // rows of Y a chunk updates
 constexpr int kFwdBuf = kFwd * kZI + kFwdY;
@@ -829,33 +832,71 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       wave_mem_sync();  // this chunk has landed
       if (c0 + kFwd <= N) fwd_load(c0 + kFwd, bf ^ 1);
       const int l = opaque_lane(lane0);
-      const int r = l < 12 ? l : 11;
+      // lane r = min(l mod 16, 11) of every 16-lane row owns row r: dx_k
+      // (r < 6) or dlambda_{k-1} (r >= 6).  The four rows compute the same
+      // values, so the broadcast of dx stays inside a row and every lane may
+      // store (lanes with equal r store equal values to the same address).
+      const int r = (l & 15) < 12 ? (l & 15) : 11;
       const double* zb = sh.u.fwd + bf * kFwdBuf;
       const T* zt = reinterpret_cast<const T*>(zb);
-      // lane r < 12 owns row r: dx_k (r < 6) or dlambda_{k-1} (r >= 6)
       const int yo = kFwd * kZI + (r < 6 ? 12 : 0) + r;
       const int nk = (N - c0 + 1) < kFwd ? (N - c0 + 1) : kFwd;
-      T zn[7];
-      double yn;
-      auto rd = [&](int s) {
+      double* yrow = Y + 12 * (int64_t)(r < 6 ? c0 : c0 - 1) + r;
+      // step s: row r of [G_k g_k ; P_{k-1} c_{k-1}] (z) and the Y entry
+      // (yv) come from the chunk buffer
+      auto fload = [&](int s, T (&z)[7], double& yv) {
 #pragma unroll
-        for (int j = 0; j < 7; ++j) zn[j] = zt[s * kZI + r * 7 + j];
-        yn = zb[yo + 12 * s];
+        for (int j = 0; j < 7; ++j) z[j] = zt[s * kZI + r * 7 + j];
+        yv = zb[yo + 12 * s];
       };
-      rd(0);
-      for (int s = 0; s < nk; ++s) {
-        T z[7];
+      auto fstep = [&](int s, const T (&z)[7], const double yv) {
+        // two partial sums: a dependent depth of four instead of six
+        const T va = fma(z[2], dx[2], fma(z[1], dx[1], fma(z[0], dx[0], z[6])));
+        const T vb = fma(z[5], dx[5], fma(z[4], dx[4], z[3] * dx[3]));
+        const T v = va + vb;
+        yrow[12 * s] = yv + (double)v;
+        dx[0] = row_bcast<0>(v);
+        dx[1] = row_bcast<1>(v);
+        dx[2] = row_bcast<2>(v);
+        dx[3] = row_bcast<3>(v);
+        dx[4] = row_bcast<4>(v);
+        dx[5] = row_bcast<5>(v);
+      };
+      if (nk == kFwd) {
+        // a full chunk, unrolled, with the reads of step s + 1 in flight
+        // while step s computes.  The compiler's LDS waits here cover every
+        // read in flight, so each buffer is pinned (an empty asm that uses
+        // it, with a memory clobber) before the next reads are issued: the
+        // wait then falls on that buffer alone.  Scheduling barriers keep
+        // each step's arithmetic between the next reads and the next pin.
+        auto pin = [&](T (&z)[7], double& yv) {
 #pragma unroll
-        for (int j = 0; j < 7; ++j) z[j] = zn[j];
-        const double yv = yn;
-        if (s + 1 < nk) rd(s + 1);
-        T v = z[6];
+          for (int j = 0; j < 7; ++j) asm volatile("" : "+v"(z[j]) : : "memory");
+          asm volatile("" : "+v"(yv) : : "memory");
+        };
+        T za[7], zc[7];
+        double ya, yc;
+        fload(0, za, ya);
 #pragma unroll
-        for (int j = 0; j < 6; ++j) v = fma(z[j], dx[j], v);
-        const int k = c0 + s;
-        if (l < 12) Y[12 * (int64_t)(r < 6 ? k : k - 1) + r] = yv + (double)v;
-#pragma unroll
-        for (int j = 0; j < 6; ++j) dx[j] = lane_bcast(v, j);
+        for (int s = 0; s < kFwd; s += 2) {
+          pin(za, ya);
+          fload(s + 1, zc, yc);
+          __builtin_amdgcn_sched_barrier(0);
+          fstep(s, za, ya);
+          __builtin_amdgcn_sched_barrier(0);
+          pin(zc, yc);
+          if (s + 2 < kFwd) fload(s + 2, za, ya);
+          __builtin_amdgcn_sched_barrier(0);
+          fstep(s + 1, zc, yc);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else {
+        for (int s = 0; s < nk; ++s) {
+          T z[7];
+          double yv;
+          fload(s, z, yv);
+          fstep(s, z, yv);
+        }
       }
       bf ^= 1;
     }
