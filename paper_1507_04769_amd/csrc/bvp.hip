@@ -255,10 +255,10 @@ __device__ __forceinline__ void g2lds16(const double* src, double* dst) {
 }
 
 // LDS strides are skewed so that the lanes of one access fall on distinct
-// banks (32 banks of 4 bytes): consecutive point slots start 20 banks apart,
-// columns of K and Q 12 banks apart, rows of [F | H | Gam'] 12 banks apart.
+// banks (32 banks of 4 bytes): columns of K and Q 12 banks apart, rows of
+// [F | H | Gam'] 12 banks apart; point blocks are entry-major, so lanes that
+// read one entry of consecutive points read consecutive words.
 constexpr int kNB = 8;             // intervals per sweep batch
-constexpr int kPt = 122;           // per point: A (36), W (36), L (36), r (12), pad
 constexpr int kKc = 60;            // K = [R | B | rho], column-major, 6 per column
 constexpr int kFHr = 22;           // row of F (6), H (6), Gam' (7), pad
 constexpr int kCst = kKc + 6 * kFHr + 2;  // per interval, 4 banks apart
@@ -266,22 +266,79 @@ constexpr int kFwd = 12;           // intervals per forward-pass chunk (two chun
 constexpr int kZI = 84;            // interval solution [G g ; P c], row-major 12 x 7
 constexpr int kFwdY = 12 * (kFwd + 1);     // rows of Y a chunk updates
 constexpr int kFwdBuf = kFwd * kZI + kFwdY;
-constexpr int kStage = 256;        // point inputs of one batch: y [9][12], r [9][12], trig [9][4]
+
+// Structural zeros of A = df/dx and W at a mesh point (both models): the
+// rates do not depend on the angles, yaw does not enter the kinematics, and
+// the gyroscopic terms couple distinct rates only.  A point block stores the
+// structurally nonzero entries of A and W (row-major order), all of L and the
+// interval residual r.
+__host__ __device__ constexpr bool a_nz(int r, int c) {
+  return (r == 0 && c != 2) || (r == 1 && (c == 0 || c >= 4)) || (r == 2 && c != 3 && c != 2) ||
+         (r >= 3 && c >= 3 && c != r);
+}
+__host__ __device__ constexpr bool w_nz(int r, int c) {
+  return r == c || ((r == 0 || r == 1) && (c == 0 || c == 1 || c == 4 || c == 5)) ||
+         ((c == 0 || c == 1) && (r == 4 || r == 5)) || (r >= 3 && c >= 3);
+}
+__host__ __device__ constexpr int a_idx(int r, int c) {
+  int n = 0;
+  for (int e = 0; e < r * 6 + c; ++e) n += a_nz(e / 6, e % 6) ? 1 : 0;
+  return n;
+}
+__host__ __device__ constexpr int w_idx(int r, int c) {
+  int n = 0;
+  for (int e = 0; e < r * 6 + c; ++e) n += w_nz(e / 6, e % 6) ? 1 : 0;
+  return n;
+}
+constexpr int kPbW = a_idx(6, 0);        // W entries start after the 18 of A
+constexpr int kPbL = kPbW + w_idx(6, 0);  // L (36) after the 22 of W
+constexpr int kPbR = kPbL + 36;           // r (12)
+constexpr int kPB = kPbR + 12;            // entries per point block
+static_assert(kPbW == 18 && kPbL == 40 && kPB == 88, "point-block layout");
+// Entry of A[r][c] and of W[r][c] in a point block (-1: structural zero), as
+// tables so that an index known at compile time folds to a constant.
+struct PbIndex {
+  int a[36], w[36];
+};
+__host__ __device__ constexpr PbIndex make_pb_index() {
+  PbIndex t{};
+  for (int e = 0; e < 36; ++e) {
+    t.a[e] = a_nz(e / 6, e % 6) ? a_idx(e / 6, e % 6) : -1;
+    t.w[e] = w_nz(e / 6, e % 6) ? kPbW + w_idx(e / 6, e % 6) : -1;
+  }
+  return t;
+}
+__device__ constexpr PbIndex kPbIdx = make_pb_index();
+
+// Point blocks of a batch in LDS: entry e of point p0 + s at [e][s], kSP
+// points per entry (16-byte units, so p0 is a multiple of 16 / sizeof(T)
+// and the 9 points klo - 1 .. klo + 7 always fit).
+template <typename T>
+struct PointBlockLayout {
+  static constexpr int kU = 16 / (int)sizeof(T);        // points per 16-byte unit
+  static constexpr int kSP = sizeof(T) == 8 ? 10 : 12;  // points per entry in LDS
+};
+
+// Points per entry of a BVP's global point-block array (a multiple of 4 that
+// covers the last batch's 16-byte-aligned window).
+__host__ __device__ inline int64_t pb_stride(int64_t N) {
+  const int64_t n = N + 4 > 12 ? N + 4 : 12;
+  return (n + 3) / 4 * 4;
+}
 
 // T is the arithmetic type of the Newton linear solve (double, or float for
-// the FP32 inexact Newton); the residual pass, the stage and the Y rows of the
-// forward pass are FP64 in both.
+// the FP32 inexact Newton); the residual pass and the Y rows of the forward
+// pass are FP64 in both.
 template <typename T>
 struct __align__(16) SweepShared {
   union {
     struct {
-      T pts[(kNB + 1) * kPt];  // point blocks of one batch (slot l: point klo - 1 + l)
-      T cst[kNB * kCst];       // interval constants of one batch
+      T pts[kPB * PointBlockLayout<T>::kSP];  // point blocks of one batch, entry-major
+      T cst[kNB * kCst];                     // interval constants of one batch
     } b;
     double fwd[2 * kFwdBuf];        // forward pass: two chunks of [Z | Y rows]
     double pa[2 * 64 * 12];         // residual pass: Phi and y of one 64-point chunk
   } u;
-  double stage[kStage];  // point inputs of the next batch (filled by direct global-to-LDS loads)
   // chain exchange buffers, one entry per lane: lane 10 i + o holds entry
   // (i, o) of [P | c] (c in column 9), of Q, of T = (Q + E) and of E
   T PL[64];
@@ -291,89 +348,35 @@ struct __align__(16) SweepShared {
   double carry_phi[12], carry_y[12];
   double xb[6], F0[6], FN[6];
   double zero[8];
-  int flag;
 };
 
 
-// A = df/dx, W and L = (I - a A)^{-1} of one mesh point into an LDS slot
-// (row-major 6 x 6 each).  Entries are stored as soon as they are formed so
-// that few values stay live; the structural zeros of A and W are written too.
+// L = (I - a A)^{-1} of one mesh point from its A (row-major 6 x 6), and
+// the nonzeros of A and W and all of L stored as entries 0 .. kPbR - 1 of the
+// point's column of a point-block array (entry e at dst[e * stride]).  I - a A is block upper triangular (the
+// rates do not depend on the angles) with an angle block that has a zero
+// column, so L = [[X, X (a E) Y], [0, Y]] from two 3 x 3 inverses, X of the
+// angle block and Y of the rate block, E = A[0:3, 3:6].  Returns false when
+// either inverse is singular.
 template <typename T>
-__device__ __forceinline__ void point_blocks(const BvpArgs& P, const double a, const double (&y)[12],
-                                             const double (&tr)[4], T* slot, int* flag) {
-  const double w1 = y[3], w2 = y[4], w3 = y[5];
-  const double l1 = y[6], l2 = y[7], l3 = y[8], l4 = y[9], l5 = y[10], l6 = y[11];
-  T* A = slot;
-  T* W = slot + 36;
-  T* L = slot + 72;
-#pragma unroll
-  for (int e = 0; e < 36; ++e) {
-    A[e] = 0.0;
-    W[e] = 0.0;
-  }
-  // the entries of A that the inverse needs: angle block (A00 A01 A10 A20 A21),
-  // kinematic coupling E = A[0:3, 3:6], rate block Omega = A[3:6, 3:6]
-  double a00 = 0.0, a01 = 0.0, a10 = 0.0, a20 = 0.0, a21 = 0.0;
-  double E[9], Om[9];
-#pragma unroll
-  for (int e = 0; e < 9; ++e) {
-    E[e] = 0.0;
-    Om[e] = 0.0;
-  }
-  if (P.model == SGCM_MODEL_RIGID_BODY) {
-    const double s = tr[0], c = tr[1], t = tr[2], k = tr[3];
-    const double al = s * w2 + c * w3;
-    const double be = c * w2 - s * w3;
-    a00 = t * be;
-    a01 = k * k * al;
-    a10 = -al;
-    a20 = k * be;
-    a21 = k * t * al;
-    E[0] = 1.0; E[1] = t * s; E[2] = t * c;
-    E[3] = 0.0; E[4] = c;     E[5] = -s;
-    E[6] = 0.0; E[7] = k * s; E[8] = k * c;
-    Om[1] = P.a[0] * w3; Om[2] = P.a[0] * w2;
-    Om[3] = P.a[1] * w3; Om[5] = P.a[1] * w1;
-    Om[6] = P.a[2] * w2; Om[7] = P.a[2] * w1;
-    const double Pc = l1 * t + l3 * k;
-    const double Pt = l1 * k * k + l3 * k * t;
-    const double Ptt = 2.0 * l1 * k * k * t + l3 * k * (t * t + k * k);
-    W[0 * 6 + 0] = Pc * al + l2 * be - P.q;
-    W[0 * 6 + 1] = W[1 * 6 + 0] = -Pt * be;
-    W[0 * 6 + 4] = W[4 * 6 + 0] = l2 * s - Pc * c;
-    W[0 * 6 + 5] = W[5 * 6 + 0] = Pc * s + l2 * c;
-    W[1 * 6 + 1] = -Ptt * al - P.q;
-    W[1 * 6 + 4] = W[4 * 6 + 1] = -Pt * s;
-    W[1 * 6 + 5] = W[5 * 6 + 1] = -Pt * c;
-    W[3 * 6 + 4] = W[4 * 6 + 3] = -l6 * P.a[2];
-    W[3 * 6 + 5] = W[5 * 6 + 3] = -l5 * P.a[1];
-    W[4 * 6 + 5] = W[5 * 6 + 4] = -l4 * P.a[0];
-    W[2 * 6 + 2] = W[3 * 6 + 3] = W[4 * 6 + 4] = W[5 * 6 + 5] = -P.q;
-  } else {
-    E[0] = E[4] = E[8] = 1.0;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) W[i * 6 + i] = -P.q;
-  }
-  A[0 * 6 + 0] = a00;
-  A[0 * 6 + 1] = a01;
-  A[1 * 6 + 0] = a10;
-  A[2 * 6 + 0] = a20;
-  A[2 * 6 + 1] = a21;
+__device__ __forceinline__ bool point_block_store(const double a, const double (&A)[36], const double (&W)[36],
+                                                  T* __restrict__ dst, const int64_t stride) {
+  double M1[9], M2[9], E[9], Xb[9], Yb[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      A[i * 6 + 3 + j] = E[i * 3 + j];
-      A[(3 + i) * 6 + 3 + j] = Om[i * 3 + j];
+      M1[i * 3 + j] = (i == j ? 1.0 : 0.0) - a * A[i * 6 + j];
+      M2[i * 3 + j] = (i == j ? 1.0 : 0.0) - a * A[(3 + i) * 6 + 3 + j];
+      E[i * 3 + j] = A[i * 6 + 3 + j];
     }
-  double M1[9] = {1.0 - a * a00, -a * a01, 0.0, -a * a10, 1.0, 0.0, -a * a20, -a * a21, 1.0};
-  double M2[9], Xb[9], Yb[9];
-#pragma unroll
-  for (int e = 0; e < 9; ++e) M2[e] = ((e % 4) == 0 ? 1.0 : 0.0) - a * Om[e];
   const double d1 = inv3(M1, Xb);
   const double d2 = inv3(M2, Yb);
-  if (d1 == 0.0 || d2 == 0.0) *flag = 1;
-  // L = [[Xb, Xb (a E) Yb], [0, Yb]]
+#pragma unroll
+  for (int e = 0; e < 36; ++e) {
+    if (kPbIdx.a[e] >= 0) dst[kPbIdx.a[e] * stride] = (T)A[e];
+    if (kPbIdx.w[e] >= 0) dst[kPbIdx.w[e] * stride] = (T)W[e];
+  }
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     double xe[3];
@@ -382,12 +385,13 @@ __device__ __forceinline__ void point_blocks(const BvpArgs& P, const double a, c
       xe[j] = a * (Xb[i * 3 + 0] * E[0 * 3 + j] + Xb[i * 3 + 1] * E[1 * 3 + j] + Xb[i * 3 + 2] * E[2 * 3 + j]);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      L[i * 6 + j] = Xb[i * 3 + j];
-      L[i * 6 + 3 + j] = xe[0] * Yb[0 * 3 + j] + xe[1] * Yb[1 * 3 + j] + xe[2] * Yb[2 * 3 + j];
-      L[(3 + i) * 6 + j] = 0.0;
-      L[(3 + i) * 6 + 3 + j] = Yb[i * 3 + j];
+      dst[(kPbL + i * 6 + j) * stride] = (T)Xb[i * 3 + j];
+      dst[(kPbL + i * 6 + 3 + j) * stride] = (T)(xe[0] * Yb[0 * 3 + j] + xe[1] * Yb[1 * 3 + j] + xe[2] * Yb[2 * 3 + j]);
+      dst[(kPbL + (3 + i) * 6 + j) * stride] = T(0);
+      dst[(kPbL + (3 + i) * 6 + 3 + j) * stride] = (T)Yb[i * 3 + j];
     }
   }
+  return d1 != 0.0 && d2 != 0.0;
 }
 
 // Newton's method for one BVP (index b, mesh of N intervals of width h,
@@ -405,9 +409,12 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
   const double alpha = 0.5 * h;
   const T at = (T)alpha;
   double* Y = ws_b;                    // NP x 12: the iterate
-  double* R = Y + 12 * (int64_t)NP;    // NP x 12: residuals r_k (row 0 = [F_0, F_N])
-  double* TR = R + 12 * (int64_t)NP;   // NP x 4: sin phi, cos phi, tan theta, sec theta
-  T* Zg = reinterpret_cast<T*>(TR + 4 * (int64_t)NP);  // N x 84: interval solutions, 12 x 7 rows
+  double* R = Y + 12 * (int64_t)NP;    // 16: F_0 (6), F_N (6), pad
+  T* Zg = reinterpret_cast<T*>(R + 16);  // N x 84: interval solutions, 12 x 7 rows
+  // point blocks [A | W | L | r_k] of every mesh point, entry-major: entry e
+  // of point k at PBg[e * pbs + k]
+  T* PBg = reinterpret_cast<T*>(R + 16 + (int64_t)kZI * N);
+  const int64_t pbs = pb_stride(N);
 
   if (lane < 6) sh.xb[lane] = x0[b * 6 + lane];
   if (lane < 8) sh.zero[lane] = 0.0;
@@ -419,6 +426,7 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
     // ---- residual F(Y) and its max norm (lane-parallel over mesh points) ----
     double lmax = 0.0;
     int bad = 0;
+    bool regular = true;
     for (int base = 0; base < NP; base += 64) {
       const int lane = opaque_lane(lane0);
       const int k = base + lane;
@@ -427,10 +435,9 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       if (valid) {
 #pragma unroll
         for (int i = 0; i < 12; ++i) yk[i] = Y[12 * (int64_t)k + i];
-        double A[36], W[36], tr[4] = {0.0, 0.0, 0.0, 0.0};
-        point_eval(P, yk, ph, A, W, tr);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) TR[4 * (int64_t)k + i] = tr[i];
+        double A[36], W[36];
+        point_eval(P, yk, ph, A, W);
+        regular &= point_block_store(alpha, A, W, PBg + k, pbs);
 #pragma unroll
         for (int i = 0; i < 12; ++i) {
           sh.u.pa[lane * 12 + i] = ph[i];
@@ -447,13 +454,15 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
             bad |= !isfinite(v);
             lmax = fmax(lmax, fabs(v));
           }
+#pragma unroll
+          for (int i = 0; i < 12; ++i) PBg[(kPbR + i) * pbs] = T(0);  // point 0 has no interval
         } else {
           const double* pp = lane > 0 ? &sh.u.pa[(lane - 1) * 12] : sh.carry_phi;
           const double* yp = lane > 0 ? &sh.u.pa[768 + (lane - 1) * 12] : sh.carry_y;
 #pragma unroll
           for (int i = 0; i < 12; ++i) {
             const double v = yk[i] - yp[i] - alpha * (pp[i] + ph[i]);
-            R[12 * (int64_t)k + i] = v;
+            PBg[(kPbR + i) * pbs + k] = (T)v;
             bad |= !isfinite(v);
             lmax = fmax(lmax, fabs(v));
           }
@@ -478,13 +487,19 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       }
       lds_handoff();
     }
-    wave_mem_sync();  // residuals R visible to every lane
+    wave_mem_sync();  // residuals and point blocks visible to every lane
     const bool nonfinite = __any(bad);
+    const bool singular_point = __any(!regular);
     lmax = wave_max(lmax);
     if (it >= 0) {
       if (nonfinite) { st = SGCM_BVP_NONFINITE; break; }
       if (lmax <= P.tol) { st = SGCM_BVP_CONVERGED; break; }
       if (it == P.max_iter) { st = SGCM_BVP_MAXITER; break; }
+    }
+    if (singular_point) {  // I - a A is singular at a mesh point
+      st = SGCM_BVP_SINGULAR;
+      if (it < 0) it = 0;
+      break;
     }
 
     // ---- backward Riccati sweep, batches of kNB intervals from k = N down ----
@@ -492,7 +507,6 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       sh.F0[lane] = R[lane];
       sh.FN[lane] = R[6 + lane];
     }
-    if (lane == 0) sh.flag = 0;
     lds_handoff();
     // chain state: lane (i, o), o in 0..5 and 9, holds [P_k | c_k][i][o];
     // P_N = p_w I, c_N = -F_N
@@ -502,21 +516,28 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       const int i = l < 60 ? l / 10 : 5, o = l < 60 ? l - 10 * i : 0;
       pv = (T)((o < 6) ? (o == i ? P.pw : 0.0) : -sh.FN[i]);
     }
-    // point inputs (y, r, trig) of points [lo - 1, hi] into the LDS stage;
-    // rows are contiguous in global memory, 16 bytes per lane
-    auto load_points = [&](int lo, int hi) {
+    // point blocks of the window of kSP points from p0 = (lo - 1) rounded
+    // down to a 16-byte unit (it covers points lo - 1 .. lo + 7) into LDS,
+    // entry-major, by direct global-to-LDS loads: 16-byte unit u of the
+    // window (entry u / (kSP / kU), part u % (kSP / kU)) to LDS unit u
+    constexpr int kU = PointBlockLayout<T>::kU, kSP = PointBlockLayout<T>::kSP;
+    auto load_points = [&](int lo) {
       const int l = opaque_lane(lane0);
-      const int cnt = hi - lo + 2;
-      const int64_t p0 = lo - 1;
-      if (l < 6 * cnt) {
-        g2lds16(Y + 12 * p0 + 2 * l, sh.stage);
-        g2lds16(R + 12 * p0 + 2 * l, sh.stage + 108);
+      const int64_t p0 = (lo - 1) / kU * kU;
+      constexpr int upe = kSP / kU, units = kPB * upe;
+      double* dst = reinterpret_cast<double*>(sh.u.b.pts);
+#pragma unroll
+      for (int j = 0; j < (units + 63) / 64; ++j) {
+        const int u = 64 * j + l;
+        if (u < units) {
+          const int e = u / upe, q = u - e * upe;
+          g2lds16(reinterpret_cast<const double*>(PBg + e * pbs + p0 + q * kU), dst + 128 * j);
+        }
       }
-      if (l < 2 * cnt) g2lds16(TR + 4 * p0 + 2 * l, sh.stage + 216);
     };
     int khi = N;
     int klo = khi - (kNB - 1) < 1 ? 1 : khi - (kNB - 1);
-    load_points(klo, khi);
+    load_points(klo);
     bool singular = false;
     while (true) {
       const int nb = khi - klo + 1;
@@ -526,49 +547,30 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       // and the later batches reuse them from LDS.
       const bool reuse = it < 0 && khi != N;
       if (!reuse) {
-        // point blocks of points klo - 1 .. khi into slots 0 .. nb (the
-        // residual of point p is r_p, the residual of interval p; row 0 of R
-        // holds F_0, F_N and is never used as an interval residual)
-        wave_mem_sync();  // the stage has landed
-        {
-          const int l = opaque_lane(lane0);
-          if (l <= nb) {
-            double py[12], pt[4];
-            T* slot = sh.u.b.pts + l * kPt;
-#pragma unroll
-            for (int i = 0; i < 12; ++i) {
-              py[i] = sh.stage[l * 12 + i];
-              slot[108 + i] = sh.stage[108 + l * 12 + i];
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) pt[i] = sh.stage[216 + l * 4 + i];
-            point_blocks(P, alpha, py, pt, slot, &sh.flag);
-          }
-        }
+        wave_mem_sync();  // the point blocks of points klo - 1 .. khi have landed
         lds_handoff();
-        if (sh.flag) {
-          singular = true;
-          break;
-        }
+        const int p0b = (klo - 1) / kU * kU;
         // interval constants of interval k = khi - tl, lane (tl, rows i and i + 3):
         // rows of K = L_k [I + a A_{k-1} | a e_rates | -r^x], F = L_{k-1}^T (I + a A_k^T),
         // H = a L_{k-1}^T W_k, Gam = a L_{k-1}^T W_{k-1} and -D^{-1} r^l = -L_{k-1}^T r^l.
-        // Every LDS access is an immediate offset from a per-lane base.
+        // Every LDS access is an immediate offset from a per-lane base.  Terms
+        // with a structural zero are skipped at compile time: those of A and
+        // W, and L[3..5][0..2] = 0 (row i + 3 of L_k, column i of L_{k-1}).
         {
           const int l = opaque_lane(lane0);
           const int tl = l & 7, ip = l >> 3;
           if (ip < 3 && tl < nb) {
             const int k = khi - tl;
-            const T* pa = sh.u.b.pts + (k - klo) * kPt;  // point k - 1
-            const T* pb = pa + kPt;                       // point k
+            const T* pa = sh.u.b.pts + (k - 1 - p0b);  // point k - 1: entry e at pa[e * kSP]
+            const T* pb = pa + 1;                      // point k
             T* cst = sh.u.b.cst + tl * kCst;
             T lb[2][6], la[2][6];  // rows i, i + 3 of L_k and of L_{k-1}^T
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
               for (int m = 0; m < 6; ++m) {
-                lb[h][m] = pb[72 + (ip + 3 * h) * 6 + m];
-                la[h][m] = pa[72 + m * 6 + ip + 3 * h];
+                lb[h][m] = (h == 1 && m < 3) ? T(0) : pb[(kPbL + (ip + 3 * h) * 6 + m) * kSP];
+                la[h][m] = (h == 0 && m >= 3) ? T(0) : pa[(kPbL + m * 6 + ip + 3 * h) * kSP];
               }
             T* kc = cst + ip;              // K[i][o] at kc[o * 6 + 3 h]
             T* fh = cst + kKc + ip * kFHr;  // row i of [F | H | Gam'] at fh[3 h kFHr + j]
@@ -576,12 +578,13 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
             for (int o = 0; o < 6; ++o) {
               T v[6];
 #pragma unroll
-              for (int m = 0; m < 6; ++m) v[m] = pa[m * 6 + o];
+              for (int m = 0; m < 6; ++m) v[m] = kPbIdx.a[m * 6 + o] >= 0 ? pa[kPbIdx.a[m * 6 + o] * kSP] : T(0);  // A_{k-1}[m][o]
 #pragma unroll
               for (int h = 0; h < 2; ++h) {
                 T q = T(0);
 #pragma unroll
-                for (int m = 0; m < 6; ++m) q = fma(lb[h][m], v[m], q);
+                for (int m = 0; m < 6; ++m)
+                  if (kPbIdx.a[m * 6 + o] >= 0 && !(h == 1 && m < 3)) q = fma(lb[h][m], v[m], q);
                 kc[o * 6 + 3 * h] = fma(at, q, lb[h][o]);
               }
             }
@@ -592,12 +595,13 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
             {
               T v[6];
 #pragma unroll
-              for (int m = 0; m < 6; ++m) v[m] = pb[108 + m];
+              for (int m = 0; m < 6; ++m) v[m] = pb[(kPbR + m) * kSP];
 #pragma unroll
               for (int h = 0; h < 2; ++h) {
                 T q = T(0);
 #pragma unroll
-                for (int m = 0; m < 6; ++m) q = fma(lb[h][m], v[m], q);
+                for (int m = 0; m < 6; ++m)
+                  if (!(h == 1 && m < 3)) q = fma(lb[h][m], v[m], q);
                 kc[54 + 3 * h] = -q;
               }
             }
@@ -606,18 +610,22 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
               T vf[6], vh[6], vg[6];
 #pragma unroll
               for (int m = 0; m < 6; ++m) {
-                vf[m] = pb[j * 6 + m];        // A_k[j][m]
-                vh[m] = pb[36 + m * 6 + j];   // W_k[m][j]
-                vg[m] = pa[36 + m * 6 + j];   // W_{k-1}[m][j]
+                const int ia = kPbIdx.a[j * 6 + m], iw = kPbIdx.w[m * 6 + j];
+                vf[m] = ia >= 0 ? pb[ia * kSP] : T(0);  // A_k[j][m]
+                vh[m] = iw >= 0 ? pb[iw * kSP] : T(0);  // W_k[m][j]
+                vg[m] = iw >= 0 ? pa[iw * kSP] : T(0);  // W_{k-1}[m][j]
               }
 #pragma unroll
               for (int h = 0; h < 2; ++h) {
                 T qf = T(0), qh = T(0), qg = T(0);
 #pragma unroll
                 for (int m = 0; m < 6; ++m) {
-                  qf = fma(la[h][m], vf[m], qf);
-                  qh = fma(la[h][m], vh[m], qh);
-                  qg = fma(la[h][m], vg[m], qg);
+                  if (h == 0 && m >= 3) continue;
+                  if (kPbIdx.a[j * 6 + m] >= 0) qf = fma(la[h][m], vf[m], qf);
+                  if (kPbIdx.w[m * 6 + j] >= 0) {
+                    qh = fma(la[h][m], vh[m], qh);
+                    qg = fma(la[h][m], vg[m], qg);
+                  }
                 }
                 fh[3 * h * kFHr + j] = fma(at, qf, la[h][j]);
                 fh[3 * h * kFHr + 6 + j] = at * qh;
@@ -627,12 +635,13 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
             {
               T v[6];
 #pragma unroll
-              for (int m = 0; m < 6; ++m) v[m] = pb[114 + m];
+              for (int m = 0; m < 6; ++m) v[m] = pb[(kPbR + 6 + m) * kSP];
 #pragma unroll
               for (int h = 0; h < 2; ++h) {
                 T q = T(0);
 #pragma unroll
-                for (int m = 0; m < 6; ++m) q = fma(la[h][m], v[m], q);
+                for (int m = 0; m < 6; ++m)
+                  if (!(h == 0 && m >= 3)) q = fma(la[h][m], v[m], q);
                 fh[3 * h * kFHr + 18] = -q;
               }
             }
@@ -643,7 +652,7 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       // inputs of the next batch, in flight during the chain
       const int nhi = klo - 1;
       const int nlo = nhi - (kNB - 1) < 1 ? 1 : nhi - (kNB - 1);
-      if (nhi >= 1 && it >= 0) load_points(nlo, nhi);
+      if (nhi >= 1 && it >= 0) load_points(nlo);
       // the serial chain: three LDS exchanges per interval.  Lane (i, o),
       // 60 lanes, owns entry (i, o) of the step; columns o = 0..5 (R), 6..8
       // (B) and 9 (rho) of [K ; e_9]; the state columns 0..5 and 9 carry
@@ -1016,6 +1025,15 @@ __global__ __launch_bounds__(256) void k_rhs(BvpArgs P, int64_t n, const double*
   }
 }
 
+// Workspace of one BVP in doubles, a multiple of 256 bytes: Y (N + 1) x 12,
+// F_0 and F_N (16), the interval solutions N x 84 (in the solve's type) and
+// the point blocks 120 x pb_stride(N) (in the solve's type).
+int64_t bvp_doubles(int64_t N, int fp32) {
+  const int64_t esize = fp32 ? 4 : 8;
+  const int64_t d = 12 * (N + 1) + 16 + kZI * N + (kPB * pb_stride(N) * esize + 7) / 8;
+  return (d + 31) / 32 * 32;
+}
+
 // Validate a problem and derive the kernel arguments.
 int make_bvp_args(const sgcm_problem* p, BvpArgs* a) {
   if (!p) return SGCM_EINVAL;
@@ -1081,9 +1099,7 @@ int make_bvp_args(const sgcm_problem* p, BvpArgs* a) {
   }
   if (!a->sinv)
     for (int e = 0; e < 9; ++e) a->Si[e] = 0.0;
-  const int64_t NP = (int64_t)p->N + 1;
-  const int64_t doubles = (12 + 12 + 4) * NP + (int64_t)kZI * p->N;
-  a->per_bvp = (doubles + 31) / 32 * 32;  // 256-byte multiples
+  a->per_bvp = bvp_doubles(p->N, a->fp32);
   return SGCM_OK;
 }
 
@@ -1174,8 +1190,7 @@ extern "C" int sgcm_batch_create(const sgcm_problem* p, int64_t n_bvps, const in
     if (N[i] < 1 || N[i] > 65536 || !(std::isfinite(T[i]) && T[i] > 0.0)) return SGCM_EINVAL;
     hh[i] = T[i] / N[i];
     hoff[i] = total;
-    const int64_t NP = (int64_t)N[i] + 1;
-    total += ((12 + 12 + 4) * NP + (int64_t)kZI * N[i] + 31) / 32 * 32;
+    total += bvp_doubles(N[i], a.fp32);
     horder[i] = (int32_t)i;
   }
   if (sc.order == 1)  // larger N T first (the longest chains start first)
