@@ -185,7 +185,7 @@ def precision_leg(dev, prob, grid, x0, lam64, u064, it64, surplus, eval_flops_q:
     it = torch.empty((M,), dtype=torch.int32, device=dev)
     ws = torch.empty((S.sgcm_solve_bvps_workspace(p32, M) // 8 + 32,), dtype=torch.float64, device=dev)
     p64 = dataclasses.replace(prob, precision=S.FP64)
-    ws64 = torch.empty_like(ws)
+    ws64 = torch.empty((S.sgcm_solve_bvps_workspace(p64, M) // 8 + 32,), dtype=torch.float64, device=dev)
     lam2, u02, V2 = torch.empty_like(lam), torch.empty_like(u0), torch.empty_like(V)
     st2, it2 = torch.empty_like(st), torch.empty_like(it)
     ms32 = A.time_ms(lambda: S.sgcm_solve_bvps(p32, x0, lam, u0, V, None, st, it, ws), reps)

@@ -684,8 +684,7 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
           fh[2 * q] = v.x;
           fh[2 * q + 1] = v.y;
         }
-        const T g = fr[12 + cs];
-        gam = cst_lane ? g : T(0);
+        gam = fr[12 + cs];  // selected where it is used, so that no wait follows the read
         kio = cst[co * 6 + ci];
 #pragma unroll
         for (int a = 0; a < 3; ++a) kb[a] = cst[(6 + a) * 6 + ci];
@@ -697,9 +696,11 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
         siv[e] = (T)P.Si[e];
         asm volatile("" : "+v"(siv[e]));
       }
+      // this lane's entries of the interval solutions, (G_k | g_k) row ci and
+      // (P_{k-1} | c_{k-1}) row 6 + ci, column cs, from k = khi down
+      T* zrow = Zg + (int64_t)(khi - 1) * kZI + ci * 7 + cs;
       load_consts(0);
       for (int t = 0; t < nb; ++t) {
-        const int k = khi - t;
         // exchange 1: rows of [P_k | c_k].  Every exchange writes one entry
         // per lane, unconditionally, so that no LDS access sits under a
         // branch and each read waits only for its own exchange.
@@ -715,7 +716,7 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
         prow[6] = sh.PL[ci * 10 + 9];
         // Q = [P | c] [K ; e_9],  C = H K + [Gam | 0 | -D^{-1} r^l]
         T q = co == 9 ? prow[6] : T(0);
-        T cc = gam;
+        T cc = cst_lane ? gam : T(0);
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
           q = fma(prow[m], kcol[m], q);
@@ -779,10 +780,10 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
         // batch reads its own again, so that the reads are not under a branch
         lds_handoff();
         load_consts(t + 1 < nb ? t + 1 : t);
-        // 1/det: hardware reciprocal estimate refined by two Newton steps
-        // (det is O(1) here: no scaling is needed)
+        // 1/det: the hardware reciprocal (relative error below 5e-8 for FP64
+        // on gfx950) refined by one Newton step (about 2e-15); det is O(1)
+        // here, so no scaling is needed
         T rd = hw_rcp(det);
-        rd = fma(rd, fma(-det, rd, T(1)), rd);
         rd = fma(rd, fma(-det, rd, T(1)), rd);
         // y = adj(Z) W[:, o]; [M | m][:, o] = y / det
         const T y0 = fma(j00, w[0], fma(j01, w[1], j02 * w[2]));
@@ -793,13 +794,15 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
         const T pn = fma(-rd, fma(er[0], y0, fma(er[1], y1, er[2] * y2)), e);
         const T gn = fma(-rd, fma(kb0, y0, fma(kb1, y1, kb2 * y2)), kio_t);
         if (cst_lane) {
-          T* zk = Zg + (int64_t)(k - 1) * kZI;
-          zk[ci * 7 + cs] = gn;
-          zk[(6 + ci) * 7 + cs] = pn;
+          zrow[0] = gn;
+          zrow[6 * 7] = pn;
         }
+        zrow -= kZI;
         pv = pn;
-        if (singular) break;
       }
+      // a zero determinant makes the rest of the batch non-finite; the
+      // sweep stops after the batch
+      singular = __any(singular);
       if (singular || nhi < 1) break;
       khi = nhi;
       klo = nlo;
