@@ -8,6 +8,7 @@
 // [0, points_upto(b)), and the nodes below a prefix are contiguous in the
 // lexicographic order.  A kernel can therefore walk the grid as a trie with
 // uniform control flow and read the surplus table as a stream.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -51,7 +52,7 @@ void enumerate(int k, int d, int b, std::vector<int32_t>& cur, std::vector<int32
 
 }  // namespace
 
-int build_grid(int d, int level, const double* lo, const double* hi, Grid* g) {
+int build_grid(int d, int level, const double* lo, const double* hi, Grid* g, bool with_sub) {
   if (d < 1 || d > kMaxDim || level < 0 || level > kMaxLevel || !lo || !hi || !g)
     return SGCM_EINVAL;
   for (int j = 0; j < d; ++j)
@@ -120,6 +121,28 @@ int build_grid(int d, int level, const double* lo, const double* hi, Grid* g) {
     for (int s = 0; s < n; ++s)
       if (s != t) prod *= xt - cgl_coordinate(i, s);
     g->dtab[P + e] = 1.0 / prod;
+  }
+  // lower-level grids: both node lists are in lexicographic key order and
+  // the lower grid's keys are a subset, so one merge pass maps them
+  g->sub.clear();
+  g->sub_map.clear();
+  g->sub_map_off.assign(1, 0);
+  if (with_sub) {
+    for (int l = 0; l < L; ++l) {
+      g->sub.emplace_back(new Grid());
+      Grid* s = g->sub.back().get();
+      const int rc = build_grid(d, l, lo, hi, s, false);
+      if (rc != SGCM_OK) return rc;
+      int64_t a = 0;
+      for (int64_t i = 0; i < s->M; ++i) {
+        while (a < g->M && !std::equal(s->keys.begin() + i * d, s->keys.begin() + (i + 1) * d,
+                                       g->keys.begin() + a * d))
+          ++a;
+        if (a == g->M) return SGCM_EINVAL;  // not nested: cannot happen for these grids
+        g->sub_map.push_back((int32_t)a);
+      }
+      g->sub_map_off.push_back((int64_t)g->sub_map.size());
+    }
   }
   return SGCM_OK;
 }

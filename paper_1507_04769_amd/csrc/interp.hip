@@ -273,8 +273,40 @@ __device__ __forceinline__ void owalk(const GridArgs& g, const F* __restrict__ w
   }
 }
 
+// The interpolant of a level-L grid (d = D, m = M) at one point per lane:
+// xi_of(k) is the lane's coordinate in [0, 1] along dimension k.
+template <int D, int L, int M, typename F, typename XiOf>
+__device__ __forceinline__ void fast_point(const GridArgs& g, const F* __restrict__ w, XiOf xi_of, F (&acc)[M]) {
+  constexpr int P = upto(L);
+  constexpr int KU = D < 4 ? D : 4;
+  constexpr int KO = D - KU;
+  extern __shared__ double lds_d[];
+  F* lds = reinterpret_cast<F*>(lds_d);
+  const int lane = threadIdx.x;
+  F* lds_lane = lds + lane;
+  F bv[KU][P];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const F xi = xi_of(k);
+    F row[kMaxPoints];
+    basis_row_l<L, F>(g, xi, row);
+    if (k < KO) {
+#pragma unroll
+      for (int e = 0; e < P; ++e) lds_lane[(k * P + e) * 64] = row[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < P; ++e) bv[k - KO][e] = row[e];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < M; ++c) acc[c] = F(0);
+  owalk<D, L, M, KO, KU, 0, F>(g, w, L, 0, F(1), acc, bv, lds_lane);
+}
+
 // F = double: the FP64 path.  F = float: the FP32 path (surplus, states and
 // outputs in FP32; the map to the unit cube in FP64, then rounded).
+// (The body is fast_point's, written out: through the shared routine the
+// compiler allocated this kernel's registers differently and it ran slower.)
 template <int D, int L, int M, typename F = double>
 __global__ __launch_bounds__(64) void k_eval_fast(GridArgs g, const F* __restrict__ w, int64_t nq,
                                                   const F* __restrict__ xq, F* __restrict__ uq) {
@@ -311,6 +343,55 @@ __global__ __launch_bounds__(64) void k_eval_fast(GridArgs g, const F* __restric
   }
 }
 
+// ---- surplus build with the unrolled walk (d = 6, m <= 3) --------------------
+//
+// The surplus of a node of total excess lv is f - I^{lv-1}(f) at the node
+// (eq. interpo), where I^{lv-1} is the interpolant of the level-(lv - 1) grid:
+// its nodes are the nodes of excess < lv, with the same surpluses (the grids
+// are nested).  One level is then a gather of the lower levels' surpluses
+// into that grid's canonical order, and the unrolled evaluation of that grid
+// at the level-lv nodes with f - I^{lv-1}(f) stored as their surpluses.
+
+// Excess 0 and 1: the center node's surplus is its value; I^0 is that
+// constant.  nodes: the center, then the n - 1 nodes of excess 1.
+__global__ __launch_bounds__(64) void k_surplus_low(const int32_t* __restrict__ nodes, int64_t n, int m,
+                                                    const double* __restrict__ f, double* __restrict__ w) {
+  const int64_t q = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (q >= n * m) return;
+  const int64_t i = q / m;
+  const int c = (int)(q - i * m);
+  const int64_t c0 = nodes[0], ni = nodes[i];
+  w[ni * m + c] = i == 0 ? f[c0 * m + c] : f[ni * m + c] - f[c0 * m + c];
+}
+
+// out[i][c] = w[map[i]][c], i < n
+__global__ __launch_bounds__(256) void k_gather_rows(const int32_t* __restrict__ map, int64_t n, int m,
+                                                     const double* __restrict__ w, double* __restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= n * m) return;
+  const int64_t i = q / m;
+  const int c = (int)(q - i * m);
+  out[q] = w[(int64_t)map[i] * m + c];
+}
+
+// Surpluses of the n nodes nodes[0 .. n) (node coordinates node_xi of the
+// full grid) from the level-L grid g with surpluses wsub.
+template <int D, int L, int M>
+__global__ __launch_bounds__(64) void k_surplus_fast(GridArgs g, const double* __restrict__ wsub, int64_t n,
+                                                     const int32_t* __restrict__ nodes,
+                                                     const double* __restrict__ node_xi,
+                                                     const double* __restrict__ f, double* __restrict__ w) {
+  const int64_t q = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const bool active = q < n;
+  const int64_t node = active ? nodes[q] : 0;
+  double acc[M];
+  fast_point<D, L, M, double>(g, wsub, [&](int k) { return active ? node_xi[node * D + k] : 0.5; }, acc);
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < M; ++c) w[node * M + c] = f[node * M + c] - acc[c];
+  }
+}
+
 // ---- host side -------------------------------------------------------------
 
 int ensure_device_tables(Grid& G, int dev) {
@@ -325,12 +406,17 @@ int ensure_device_tables(Grid& G, int dev) {
   bool ok = up((void**)&gd.node_xi, G.xi.data(), G.xi.size() * sizeof(double)) &&
             up((void**)&gd.by_level, G.by_level.data(), G.by_level.size() * sizeof(int32_t)) &&
             up((void**)&gd.tables, G.itab.data(), G.itab.size() * sizeof(int32_t)) &&
-            up((void**)&gd.dtab, G.dtab.data(), G.dtab.size() * sizeof(double));
+            up((void**)&gd.dtab, G.dtab.data(), G.dtab.size() * sizeof(double)) &&
+            up((void**)&gd.sub_map, G.sub_map.data(), G.sub_map.size() * sizeof(int32_t)) &&
+            up((void**)&gd.scratch, nullptr, (size_t)G.M * 3 * sizeof(double));
+  for (auto& sg : G.sub) ok = ok && ensure_device_tables(*sg, dev) == SGCM_OK;
   if (!ok) {
     (void)hipFree(gd.node_xi);
     (void)hipFree(gd.by_level);
     (void)hipFree(gd.tables);
     (void)hipFree(gd.dtab);
+    (void)hipFree(gd.sub_map);
+    (void)hipFree(gd.scratch);
     gd = GridDevice();
     return SGCM_ENOMEM;
   }
@@ -467,6 +553,59 @@ hipError_t eval_fast(const Grid& G, int m, const GridArgs& a, int64_t nq, const 
   }
 }
 
+template <int L, int M>
+hipError_t launch_surplus_fast(const GridArgs& a, const double* wsub, int64_t n, const int32_t* nodes,
+                               const double* node_xi, const double* f, double* w, hipStream_t s) {
+  constexpr int D = 6;
+  const size_t lds = (size_t)(D - 4) * upto(L) * 64 * sizeof(double);
+  const int64_t blocks = (n + 63) / 64;
+  hipLaunchKernelGGL((k_surplus_fast<D, L, M>), dim3((unsigned)blocks), dim3(64), lds, s, a, wsub, n, nodes,
+                     node_xi, f, w);
+  return hipGetLastError();
+}
+
+template <int L>
+hipError_t surplus_fast_m(int m, const GridArgs& a, const double* wsub, int64_t n, const int32_t* nodes,
+                          const double* node_xi, const double* f, double* w, hipStream_t s) {
+  switch (m) {
+    case 1: return launch_surplus_fast<L, 1>(a, wsub, n, nodes, node_xi, f, w, s);
+    case 2: return launch_surplus_fast<L, 2>(a, wsub, n, nodes, node_xi, f, w, s);
+    default: return launch_surplus_fast<L, 3>(a, wsub, n, nodes, node_xi, f, w, s);
+  }
+}
+
+// The unrolled build covers d = 6, levels 0..5, m <= 3 (the lower-level grids
+// it evaluates have levels 1..4).
+bool fast_build_applies(const Grid& G, int m) {
+  return G.d == 6 && G.level <= 5 && m <= 3 && (int)G.sub.size() == G.level;
+}
+
+hipError_t build_fast(Grid& G, int dev, int m, const double* f, double* w, hipStream_t s) {
+  const GridDevice& gd = G.dev[dev];
+  const int64_t n01 = G.level >= 1 ? G.level_start[2] : 1;
+  hipLaunchKernelGGL(k_surplus_low, dim3((unsigned)((n01 * m + 63) / 64)), dim3(64), 0, s, gd.by_level, n01, m, f,
+                     w);
+  hipError_t e = hipGetLastError();
+  for (int lv = 2; lv <= G.level && e == hipSuccess; ++lv) {
+    const Grid& S = *G.sub[lv - 1];
+    const int64_t ms = S.M, start = G.level_start[lv], count = G.level_start[lv + 1] - start;
+    const int32_t* map = gd.sub_map + G.sub_map_off[lv - 1];
+    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((ms * m + 255) / 256)), dim3(256), 0, s, map, ms, m, w,
+                       gd.scratch);
+    e = hipGetLastError();
+    if (e != hipSuccess || count == 0) continue;
+    const GridArgs sa = make_args(S, S.dev[dev]);
+    const int32_t* nodes = gd.by_level + start;
+    switch (lv - 1) {
+      case 1: e = surplus_fast_m<1>(m, sa, gd.scratch, count, nodes, gd.node_xi, f, w, s); break;
+      case 2: e = surplus_fast_m<2>(m, sa, gd.scratch, count, nodes, gd.node_xi, f, w, s); break;
+      case 3: e = surplus_fast_m<3>(m, sa, gd.scratch, count, nodes, gd.node_xi, f, w, s); break;
+      default: e = surplus_fast_m<4>(m, sa, gd.scratch, count, nodes, gd.node_xi, f, w, s); break;
+    }
+  }
+  return e;
+}
+
 int current_device(int* dev) {
   if (hipGetDevice(dev) != hipSuccess) return SGCM_EDEVICE;
   if (*dev < 0 || *dev >= kMaxDevices) return SGCM_EUNSUPPORTED;
@@ -486,10 +625,13 @@ void free_device_tables(Grid& G) {
       (void)hipFree(gd.by_level);
       (void)hipFree(gd.tables);
       (void)hipFree(gd.dtab);
+      (void)hipFree(gd.sub_map);
+      (void)hipFree(gd.scratch);
     }
     gd = GridDevice();
   }
   if (cur >= 0) (void)hipSetDevice(cur);
+  for (auto& sg : G.sub) free_device_tables(*sg);
 }
 
 }  // namespace sgcm
@@ -506,9 +648,10 @@ extern "C" int sgcm_build_interpolant(const sgcm_grid* gh, int32_t m, const doub
   rc = ensure_device_tables(G, dev);
   if (rc != SGCM_OK) return rc;
   const GridDevice& gd = G.dev[dev];
+  hipStream_t s = (hipStream_t)stream;
+  if (fast_build_applies(G, m)) return build_fast(G, dev, m, values, surplus, s) == hipSuccess ? SGCM_OK : SGCM_EDEVICE;
   GridArgs a = make_args(G, gd);
   const size_t lds = lds_bytes(G);
-  hipStream_t s = (hipStream_t)stream;
   for (int lv = 0; lv <= G.level; ++lv) {
     const int64_t start = G.level_start[lv], count = G.level_start[lv + 1] - start;
     if (count == 0) continue;

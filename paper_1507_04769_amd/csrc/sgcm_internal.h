@@ -3,6 +3,7 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -41,6 +42,8 @@ struct GridDevice {
   int32_t* by_level = nullptr;   // node indices grouped by total excess
   int32_t* tables = nullptr;     // int tables (see Grid::itab)
   double* dtab = nullptr;        // double tables (see Grid::dtab)
+  int32_t* sub_map = nullptr;    // Grid::sub_map
+  double* scratch = nullptr;     // M x 3 doubles: lower-level surpluses during a build
 };
 
 struct Grid {
@@ -62,12 +65,19 @@ struct Grid {
   //   [0, P)            the points of the finest set X^{level+1}, increasing
   //   [P, 2P)           scale[e] = 1 / prod_{s != t(e)} (x_t - x_s) over X^i
   std::vector<double> dtab;
+  // The grids of the lower levels (sub[l] of level l < level, without grids
+  // of their own) and, for each, the index in this grid of each of its nodes:
+  // sub_map[sub_map_off[l] + i] for node i of sub[l] (the grids are nested).
+  std::vector<std::unique_ptr<Grid>> sub;
+  std::vector<int64_t> sub_map_off;
+  std::vector<int32_t> sub_map;
   std::mutex mu;
   GridDevice dev[kMaxDevices];
 };
 
-// Host grid construction (grid.cpp).
-int build_grid(int d, int level, const double* lo, const double* hi, Grid* g);
+// Host grid construction (grid.cpp); with_sub also builds the lower-level
+// grids and their node maps.
+int build_grid(int d, int level, const double* lo, const double* hi, Grid* g, bool with_sub = true);
 
 // Coordinate in [0,1] of offset t in X^i (i >= 2), t = 0..2^{i-1}.
 double cgl_coordinate(int i, int t);
