@@ -214,7 +214,9 @@ void sgcm_grid_destroy(sgcm_grid* g);
  * X^{i_1} x .. x X^{i_d}.
  *   values   device, M x m node values f (canonical order), read only
  *   surplus  device, M x m (canonical order); may not alias values
- * 1 <= m <= 64. */
+ * 1 <= m <= 64.  For d = 6 and m <= 3 the lower levels' surpluses are staged
+ * in a device buffer that the grid owns, so calls with the same grid on one
+ * device must not overlap (use one stream, or order them). */
 int sgcm_build_interpolant(const sgcm_grid* g, int32_t m, const double* values,
                            double* surplus, void* stream);
 
