@@ -11,29 +11,32 @@
 //   Phi' = [[A, -S], [W, -A^T]],  S = (1/r_w) Bt Bt^T,  W = -q_w I - sum_i lambda_i f_i''.
 //
 // Linear solve: a backward Riccati sweep dlambda_k = P_k dx_k + c_k from
-// P_N = p_w I, c_N = -F_N.  The controls act on the body rates only, so S has
-// rank <= 3 and lives in the rate block; eliminating dlambda_{k-1} with
-// D^{-1} = (I - a A_{k-1}^T)^{-1} and dx_k with L_k = (I - a A_k)^{-1} leaves,
-// on the serial path, one 3 x 3 system per interval (a Woodbury-type step):
-//   EM1 = F P_k - H,  Psi = P_k + EM1,
-//   Z3  = I + S_w Psi_w B_k,   [M | m] = Z3^{-1} S_w [Psi_w R_k - Gam_w | Psi_w rho + phi_w],
-//   P_{k-1} = (EM1 R_k - Gam) - (EM1 B_k) M,   c_{k-1} = EM1 rho - (EM1 B_k) m + F c_k + D^{-1} r^l,
-//   G_k = R_k - B_k M,  g_k = rho - B_k m   (dx_k = G_k dx_{k-1} + g_k),
-// with F = D^{-1}(I + a A_k^T), H = a D^{-1} W_k, Gam = a D^{-1} W_{k-1},
-// R_k = L_k (I + a A_{k-1}), B_k = a L_k[:, rates], rho = -L_k r^x,
-// phi = (I + F) c_k + D^{-1} r^l.  D and I - a A_k are block triangular (the
-// rates do not depend on the angles), so L_k comes from two 3 x 3 inverses and
-// D^{-1} = L_{k-1}^T.
-//
-// Per-point blocks (A, W, L) are derived in batches of 8 points into an LDS
-// ring ahead of the sweep (the trigonometric factors come from the residual
-// pass); each interval is four LDS-synchronised stages (interval products,
-// then three chain stages), each of which issues all of its LDS reads before
-// its first product.  The interval solutions [G_k g_k ; P_{k-1} c_{k-1}] go
-// to global memory and come back, staged through LDS 8 intervals at a time
-// with a register prefetch, for the forward pass dx_0 = -F_0,
+// P_N = p_w I, c_N = -F_N, and a forward pass dx_0 = -F_0,
 // dx_k = G_k dx_{k-1} + g_k, dlambda_{k-1} = P_{k-1} dx_{k-1} + c_{k-1}.
-// Mesh-point work and the residual are lane-parallel over k.
+// With L = (I - a A)^{-1} at each point (two 3 x 3 inverses: the rates do not
+// depend on the angles) and, per interval k,
+//   K = L_k [I + a A_{k-1} | a e_rates | -r^x_k]   (6 x 10),
+//   F = L_{k-1}^T (I + a A_k^T),  H = a L_{k-1}^T W_k,
+//   C = H K + [a L_{k-1}^T W_{k-1} | 0 | -L_{k-1}^T r^l_k],
+// one sweep step is
+//   Q = [P_k | c_k] [K ; e_9],  E = F Q - C,  T = Q + E on the rate rows,
+//   (S_w^{-1} + T[:, 6..8]) M = T   (or (I + S_w T[:, 6..8]) M = S_w T),
+//   [P_{k-1} | c_{k-1}] = E[:, state] - E[:, 6..8] M,
+//   [G_k | g_k] = K[:, state] - K[:, 6..8] M:
+// the elimination of dlambda_{k-1} and dx_k from the interval equations.  The
+// controls act on the rates only (S has rank <= 3), so the only inverse on the
+// serial path is 3 x 3.
+//
+// Per Newton iteration: (1) the residual pass, one lane per mesh point:
+// Phi, the residual and its norm, and the point blocks (nonzeros of A and W,
+// L, r_k) stored entry-major in the workspace; (2) the sweep in batches of 8
+// intervals from k = N down: the batch's window of point blocks comes to LDS
+// by direct global-to-LDS loads (issued a batch ahead), the interval
+// constants K, F, H, Gam' are formed lane-parallel, and the serial chain runs
+// one lane per entry of the 6 x 10 step with three LDS exchanges per interval;
+// the interval solutions [G_k g_k ; P_{k-1} c_{k-1}] go to the workspace;
+// (3) the forward pass, 12 rows per 16-lane row with dx broadcast by DPP,
+// the interval solutions staged through LDS 12 at a time.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
