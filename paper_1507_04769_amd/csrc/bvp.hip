@@ -430,7 +430,21 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
     double lmax = 0.0;
     int bad = 0;
     bool regular = true;
-    for (int base = 0; base < NP; base += 64) {
+    // In the first (linearised) step Y = 0, and the sweep forms its interval
+    // constants from the first batch alone (every interval has the same
+    // ones).  The pass then covers only the last 64 points, which hold that
+    // batch's window of point blocks, and sets F_0 = 0 - xbar and
+    // F_N = 0 - p_w 0 directly (the values the pass would compute); nothing
+    // is tested in that step.
+    int base0 = 0;
+    if (it < 0 && NP > 64) {
+      base0 = NP - 64;
+      if (lane < 6) {
+        R[lane] = 0.0 - sh.xb[lane];
+        R[6 + lane] = 0.0 - P.pw * 0.0;
+      }
+    }
+    for (int base = base0; base < NP; base += 64) {
       const int lane = opaque_lane(lane0);
       const int k = base + lane;
       const bool valid = k < NP;
