@@ -273,8 +273,9 @@ constexpr int kFwdBuf = kFwd * kZI + kFwdY;
 // Structural zeros of A = df/dx and W at a mesh point (both models): the
 // rates do not depend on the angles, yaw does not enter the kinematics, and
 // the gyroscopic terms couple distinct rates only.  A point block stores the
-// structurally nonzero entries of A and W (row-major order), all of L and the
-// interval residual r.
+// structurally nonzero entries of A (row-major), those of the symmetric W on
+// and above the diagonal, L without its zero block L[3..5][0..2] (rows 0..2,
+// then columns 3..5 of rows 3..5) and the interval residual r.
 __host__ __device__ constexpr bool a_nz(int r, int c) {
   return (r == 0 && c != 2) || (r == 1 && (c == 0 || c >= 4)) || (r == 2 && c != 3 && c != 2) ||
          (r >= 3 && c >= 3 && c != r);
@@ -288,16 +289,19 @@ __host__ __device__ constexpr int a_idx(int r, int c) {
   for (int e = 0; e < r * 6 + c; ++e) n += a_nz(e / 6, e % 6) ? 1 : 0;
   return n;
 }
+// slot of W[r][c], r <= c, among the stored entries of W
 __host__ __device__ constexpr int w_idx(int r, int c) {
   int n = 0;
-  for (int e = 0; e < r * 6 + c; ++e) n += w_nz(e / 6, e % 6) ? 1 : 0;
+  for (int e = 0; e < r * 6 + c; ++e) n += (w_nz(e / 6, e % 6) && e / 6 <= e % 6) ? 1 : 0;
   return n;
 }
 constexpr int kPbW = a_idx(6, 0);        // W entries start after the 18 of A
-constexpr int kPbL = kPbW + w_idx(6, 0);  // L (36) after the 22 of W
-constexpr int kPbR = kPbL + 36;           // r (12)
+constexpr int kPbL = kPbW + w_idx(6, 0);  // L (27) after the 14 of W
+constexpr int kPbR = kPbL + 27;           // r (12)
 constexpr int kPB = kPbR + 12;            // entries per point block
-static_assert(kPbW == 18 && kPbL == 40 && kPB == 88, "point-block layout");
+static_assert(kPbW == 18 && kPbL == 32 && kPB == 71, "point-block layout");
+// slot of L[r][c] (r < 3, or r >= 3 and c >= 3) relative to kPbL
+__host__ __device__ constexpr int l_slot(int r, int c) { return r < 3 ? r * 6 + c : 18 + (r - 3) * 3 + (c - 3); }
 // Entry of A[r][c] and of W[r][c] in a point block (-1: structural zero), as
 // tables so that an index known at compile time folds to a constant.
 struct PbIndex {
@@ -306,8 +310,9 @@ struct PbIndex {
 __host__ __device__ constexpr PbIndex make_pb_index() {
   PbIndex t{};
   for (int e = 0; e < 36; ++e) {
-    t.a[e] = a_nz(e / 6, e % 6) ? a_idx(e / 6, e % 6) : -1;
-    t.w[e] = w_nz(e / 6, e % 6) ? kPbW + w_idx(e / 6, e % 6) : -1;
+    const int r = e / 6, c = e % 6;
+    t.a[e] = a_nz(r, c) ? a_idx(r, c) : -1;
+    t.w[e] = w_nz(r, c) ? kPbW + (r <= c ? w_idx(r, c) : w_idx(c, r)) : -1;
   }
   return t;
 }
@@ -355,8 +360,9 @@ struct __align__(16) SweepShared {
 
 
 // L = (I - a A)^{-1} of one mesh point from its A (row-major 6 x 6), and
-// the nonzeros of A and W and all of L stored as entries 0 .. kPbR - 1 of the
-// point's column of a point-block array (entry e at dst[e * stride]).  I - a A is block upper triangular (the
+// the stored entries of A, W and L (see the point-block layout) as entries
+// 0 .. kPbR - 1 of the point's column of a point-block array (entry e at
+// dst[e * stride]).  I - a A is block upper triangular (the
 // rates do not depend on the angles) with an angle block that has a zero
 // column, so L = [[X, X (a E) Y], [0, Y]] from two 3 x 3 inverses, X of the
 // angle block and Y of the rate block, E = A[0:3, 3:6].  Returns false when
@@ -378,7 +384,7 @@ __device__ __forceinline__ bool point_block_store(const double a, const double (
 #pragma unroll
   for (int e = 0; e < 36; ++e) {
     if (kPbIdx.a[e] >= 0) dst[kPbIdx.a[e] * stride] = (T)A[e];
-    if (kPbIdx.w[e] >= 0) dst[kPbIdx.w[e] * stride] = (T)W[e];
+    if (kPbIdx.w[e] >= 0 && e / 6 <= e % 6) dst[kPbIdx.w[e] * stride] = (T)W[e];
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -388,10 +394,9 @@ __device__ __forceinline__ bool point_block_store(const double a, const double (
       xe[j] = a * (Xb[i * 3 + 0] * E[0 * 3 + j] + Xb[i * 3 + 1] * E[1 * 3 + j] + Xb[i * 3 + 2] * E[2 * 3 + j]);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      dst[(kPbL + i * 6 + j) * stride] = (T)Xb[i * 3 + j];
-      dst[(kPbL + i * 6 + 3 + j) * stride] = (T)(xe[0] * Yb[0 * 3 + j] + xe[1] * Yb[1 * 3 + j] + xe[2] * Yb[2 * 3 + j]);
-      dst[(kPbL + (3 + i) * 6 + j) * stride] = T(0);
-      dst[(kPbL + (3 + i) * 6 + 3 + j) * stride] = (T)Yb[i * 3 + j];
+      dst[(kPbL + l_slot(i, j)) * stride] = (T)Xb[i * 3 + j];
+      dst[(kPbL + l_slot(i, 3 + j)) * stride] = (T)(xe[0] * Yb[0 * 3 + j] + xe[1] * Yb[1 * 3 + j] + xe[2] * Yb[2 * 3 + j]);
+      dst[(kPbL + l_slot(3 + i, 3 + j)) * stride] = (T)Yb[i * 3 + j];
     }
   }
   return d1 != 0.0 && d2 != 0.0;
@@ -586,8 +591,14 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
             for (int h = 0; h < 2; ++h)
 #pragma unroll
               for (int m = 0; m < 6; ++m) {
-                lb[h][m] = (h == 1 && m < 3) ? T(0) : pb[(kPbL + (ip + 3 * h) * 6 + m) * kSP];
-                la[h][m] = (h == 0 && m >= 3) ? T(0) : pa[(kPbL + m * 6 + ip + 3 * h) * kSP];
+                // L_k[ip + 3h][m] and L_{k-1}[m][ip + 3h]; the slot is linear
+                // in ip (row ip: ip * 6 + m; row 3 + ip: 18 + ip * 3 + m - 3;
+                // column ip + 3h of row m < 3: m * 6 + 3h + ip; of row m >= 3:
+                // 18 + (m - 3) * 3 + ip)
+                lb[h][m] = (h == 1 && m < 3) ? T(0)
+                           : pb[(kPbL + (h == 0 ? ip * 6 + m : 18 + ip * 3 + m - 3)) * kSP];
+                la[h][m] = (h == 0 && m >= 3) ? T(0)
+                           : pa[(kPbL + (m < 3 ? m * 6 + 3 * h + ip : 18 + (m - 3) * 3 + ip)) * kSP];
               }
             T* kc = cst + ip;              // K[i][o] at kc[o * 6 + 3 h]
             T* fh = cst + kKc + ip * kFHr;  // row i of [F | H | Gam'] at fh[3 h kFHr + j]
