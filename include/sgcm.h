@@ -121,7 +121,10 @@ int sgcm_solve_bvps_workspace(const sgcm_problem* p, int64_t n_bvps, size_t* byt
  *            sgcm_solve_bvps_workspace() bytes, 256-byte aligned; its
  *            contents on entry are ignored.
  * n_bvps == 0 is a valid no-op.  Outputs of a non-converged BVP are those of
- * the last iterate.  The call is stream-ordered on `stream`. */
+ * the last iterate.  The call is stream-ordered on `stream`.  For
+ * n_bvps <= 4096 the BVPs are handed to workgroups in decreasing order of
+ * |x0|_1 (a predictor of their Newton iterations, so that the longest start
+ * first); each BVP's outputs do not depend on that order. */
 int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const double* x0,
                     double* lambda0, double* u0, double* V, double* traj,
                     int32_t* status, int32_t* iters, void* workspace,

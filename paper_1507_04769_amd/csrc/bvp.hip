@@ -990,11 +990,64 @@ template <typename T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_newton(
     BvpArgs P, const double* __restrict__ x0, double* __restrict__ lam0, double* __restrict__ u0,
     double* __restrict__ Vout, double* __restrict__ traj, int32_t* __restrict__ status,
-    int32_t* __restrict__ iters, double* __restrict__ ws) {
+    int32_t* __restrict__ iters, double* __restrict__ ws, const int32_t* __restrict__ order) {
   __shared__ SweepShared<T> sh;
-  const int64_t b = blockIdx.x;
-  newton_bvp(P, P.N, P.h, b, ws + b * P.per_bvp, x0, lam0, u0, Vout, traj, status, iters, sh);
+  // the workspace is scratch: workgroup g uses slot g whatever BVP it takes,
+  // so that consecutive workgroups keep consecutive memory
+  const int64_t b = order ? order[blockIdx.x] : blockIdx.x;
+  newton_bvp(P, P.N, P.h, b, ws + (int64_t)blockIdx.x * P.per_bvp, x0, lam0, u0, Vout, traj, status, iters, sh);
 }
+
+// The order in which the workgroups of one launch take the BVPs: decreasing
+// |x0|_1.  The Newton iterations a BVP needs grow with the size of its
+// initial state (the nonlinear terms grow with it), and the launch ends with
+// its longest BVPs, so those start first and the short ones fill the compute
+// units behind them (the longest-first rule of the batch plans).  Any order
+// gives the same results, so an approximate one does: a one-pass bucket sort
+// of the keys into 256 buckets of equal width below the largest key (LDS
+// atomics; the order inside a bucket is arbitrary).  A non-finite key counts
+// as 0 (such a BVP stops at its first residual test).  n <= kOrderMax.
+constexpr int kOrderMax = 4096;
+__global__ __launch_bounds__(1024) void k_order(const double* __restrict__ x0, int n, int32_t* __restrict__ order) {
+  __shared__ float key[kOrderMax];
+  __shared__ float wmax[16];
+  __shared__ int32_t cnt[256];
+  const int t = threadIdx.x;
+  float m = 0.0f;
+  for (int i = t; i < n; i += 1024) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) s += fabs(x0[(int64_t)i * 6 + j]);
+    const float f = (float)s;
+    key[i] = isfinite(f) ? f : 0.0f;
+    m = fmaxf(m, key[i]);
+  }
+  if (t < 256) cnt[t] = 0;
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d));
+  if ((t & 63) == 0) wmax[t >> 6] = m;
+  __syncthreads();
+  float kmax = 0.0f;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) kmax = fmaxf(kmax, wmax[w]);
+  const float scale = kmax > 0.0f ? 255.5f / kmax : 0.0f;
+  auto bucket = [&](int i) { return 255 - min(255, (int)(key[i] * scale)); };  // largest keys in bucket 0
+  for (int i = t; i < n; i += 1024) atomicAdd(&cnt[bucket(i)], 1);
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int b = 0; b < 256; ++b) {
+      const int c = cnt[b];
+      cnt[b] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < n; i += 1024) order[atomicAdd(&cnt[bucket(i)], 1)] = i;
+}
+
+// Bytes of the launch order behind the BVP workspaces.
+size_t order_bytes(int64_t n_bvps) { return n_bvps <= kOrderMax ? ((size_t)n_bvps * 4 + 255) / 256 * 256 : 0; }
 
 // A batch of BVPs with per-BVP mesh size and horizon.  Plain mode: workgroup
 // g solves BVP order[g].  Persistent mode: each workgroup takes the next
@@ -1144,7 +1197,7 @@ extern "C" int sgcm_solve_bvps_workspace(const sgcm_problem* p, int64_t n_bvps, 
   if (!bytes || n_bvps < 0) return SGCM_EINVAL;
   int rc = make_bvp_args(p, &a);
   if (rc != SGCM_OK) return rc;
-  *bytes = (size_t)a.per_bvp * sizeof(double) * (size_t)n_bvps;
+  *bytes = (size_t)a.per_bvp * sizeof(double) * (size_t)n_bvps + order_bytes(n_bvps);
   return SGCM_OK;
 }
 
@@ -1159,13 +1212,20 @@ extern "C" int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const doub
   if (n_bvps > 0x7fffffffLL) return SGCM_EUNSUPPORTED;
   if (!x0 || !lambda0 || !u0 || !status || !iters || !workspace) return SGCM_EINVAL;
   if (((uintptr_t)workspace & 255u) != 0) return SGCM_EINVAL;
-  if (ws_bytes < (size_t)a.per_bvp * sizeof(double) * (size_t)n_bvps) return SGCM_EINVAL;
+  const size_t bvp_bytes = (size_t)a.per_bvp * sizeof(double) * (size_t)n_bvps;
+  if (ws_bytes < bvp_bytes + order_bytes(n_bvps)) return SGCM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  int32_t* order = nullptr;
+  if (n_bvps > 1 && n_bvps <= kOrderMax) {
+    order = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(workspace) + bvp_bytes);
+    hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, s, x0, (int)n_bvps, order);
+  }
   if (a.fp32)
-    hipLaunchKernelGGL(k_newton<float>, dim3((unsigned)n_bvps), dim3(64), 0, (hipStream_t)stream, a, x0,
-                       lambda0, u0, V, traj, status, iters, (double*)workspace);
+    hipLaunchKernelGGL(k_newton<float>, dim3((unsigned)n_bvps), dim3(64), 0, s, a, x0, lambda0, u0, V, traj,
+                       status, iters, (double*)workspace, order);
   else
-    hipLaunchKernelGGL(k_newton<double>, dim3((unsigned)n_bvps), dim3(64), 0, (hipStream_t)stream, a, x0,
-                       lambda0, u0, V, traj, status, iters, (double*)workspace);
+    hipLaunchKernelGGL(k_newton<double>, dim3((unsigned)n_bvps), dim3(64), 0, s, a, x0, lambda0, u0, V, traj,
+                       status, iters, (double*)workspace, order);
   return hipGetLastError() == hipSuccess ? SGCM_OK : SGCM_EDEVICE;
 }
 

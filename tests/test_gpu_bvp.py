@@ -170,3 +170,15 @@ def test_deterministic_and_workspace_reuse():
     torch.cuda.synchronize()
     for k in ("lambda0", "u0", "V", "traj", "status", "iters"):
         assert torch.equal(getattr(a, k), getattr(b, k)), k
+
+
+def test_results_do_not_depend_on_input_order():
+    # the launch hands BVPs to workgroups in decreasing |x0|_1; a BVP's
+    # outputs must be bitwise the same whatever the order of the inputs
+    gp, _ = problems(N=48, T=10.0)
+    x0 = W.uniform_in_box(300, seed=116)
+    perm = np.random.default_rng(117).permutation(len(x0))
+    a = gpu_solve(gp, x0)
+    b = gpu_solve(gp, x0[perm])
+    for k in ("lambda0", "u0", "V", "traj", "status", "iters"):
+        assert np.array_equal(a[k][perm], b[k]), k
