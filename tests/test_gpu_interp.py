@@ -33,7 +33,7 @@ def dev(a):
 
 # d = 6 with levels 1..5 and m <= 3 takes the kernel whose inner trie is
 # unrolled at compile time; everything else takes the generic trie walk.
-CASES = [(1, 0), (1, 5), (2, 3), (3, 4), (4, 1), (6, 1), (6, 2), (6, 3), (6, 4), (6, 5), (8, 2)]
+CASES = [(1, 0), (1, 5), (2, 3), (3, 4), (4, 1), (6, 0), (6, 1), (6, 2), (6, 3), (6, 4), (6, 5), (8, 2)]
 
 
 @pytest.mark.parametrize("d,level", CASES)
