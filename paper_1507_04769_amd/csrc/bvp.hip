@@ -218,14 +218,25 @@ __device__ __forceinline__ void lds_handoff() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// s_waitcnt lgkmcnt(n), the other counters left alone (gfx9 encoding: vmcnt
+// in bits 3:0 and 15:14, expcnt in 6:4, lgkmcnt in 11:8): with only LDS
+// operations in flight, which complete in order, every one but the n most
+// recent has completed.  The compiler's own wait insertion takes this wait
+// into account and still adds whatever a later use needs, so n sets how long
+// the wave waits, never what it reads.
+template <int n>
+__device__ __forceinline__ void lds_wait_all_but() {
+  static_assert(n >= 0 && n < 16, "lgkmcnt has 4 bits");
+  __builtin_amdgcn_s_waitcnt(0xC07F | (n << 8));
+}
+
 // Value of v in lane J of each 16-lane row, to every lane of that row (DPP
-// row_newbcast): no SGPR round trip, the result lands in VGPRs.
+// row_newbcast): no SGPR round trip, the result lands in VGPRs.  gfx950 moves
+// a 64-bit value with one row_newbcast (v_mov_b64_dpp).
 template <int J>
 __device__ __forceinline__ double row_bcast(double v) {
-  const long long bits = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)bits, 0x150 + J, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(bits >> 32), 0x150 + J, 0xf, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  const long long bits = __builtin_amdgcn_mov_dpp(__double_as_longlong(v), 0x150 + J, 0xf, 0xf, false);
+  return __longlong_as_double(bits);
 }
 
 template <int J>
@@ -717,13 +728,14 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
 #pragma unroll
         for (int a = 0; a < 3; ++a) kb[a] = cst[(6 + a) * 6 + ci];
       };
-      // S_w^{-1} in VGPRs: it is added to T1, which arrives in SGPRs
-      T siv[9];
+      // Z = S_w^{-1} + T[3..5][6..8] is formed before exchange 3 by the lanes
+      // that hold those entries of T (lane (3 + a, 6 + c) adds S_w^{-1}[a][c]),
+      // so that it arrives ready; no other lane reads those entries
+      T zadd = T(0);
 #pragma unroll
-      for (int e = 0; e < 9; ++e) {
-        siv[e] = (T)P.Si[e];
-        asm volatile("" : "+v"(siv[e]));
-      }
+      for (int e2 = 0; e2 < 9; ++e2)
+        if (P.sinv && ci == 3 + e2 / 3 && co == 6 + e2 % 3) zadd = (T)P.Si[e2];
+      asm volatile("" : "+v"(zadd));
       // this lane's entries of the interval solutions, (G_k | g_k) row ci and
       // (P_{k-1} | c_{k-1}) row 6 + ci, column cs, from k = khi down
       T* zrow = Zg + (int64_t)(khi - 1) * kZI + ci * 7 + cs;
@@ -762,8 +774,9 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
         const T tv = q + e;  // T = Psi_w [K ; e_9] on the rate rows
         const T kio_t = kio, kb0 = kb[0], kb1 = kb[1], kb2 = kb[2];
         // exchange 3: column o of T's rate rows, row i of E[:, 6..8], and
-        // T[3..5][6..8] (the same for every lane)
-        sh.TL[lane0] = tv;
+        // T[3..5][6..8] (the same for every lane; it arrives as
+        // S_w^{-1} + T[3..5][6..8] when S_w is invertible)
+        sh.TL[lane0] = tv + zadd;
         sh.EL[lane0] = e;
         lds_handoff();
         T tc[3], er[3], t1[9];
@@ -774,13 +787,22 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
 #pragma unroll
           for (int c = 0; c < 3; ++c) t1[a * 3 + c] = sh.TL[(3 + a) * 10 + 6 + c];
         }
-        // the 3 x 3 system Z M = W: Z = S_w^{-1} + T[:, 6..8], W = T when S_w
-        // is invertible, else Z = I + S_w T[:, 6..8], W = S_w T; M by the
-        // adjugate of Z
+        // the next interval's constants (this interval's are all in registers
+        // by now), issued behind the exchange reads; the wait below covers
+        // only the exchange, so they arrive during the 3 x 3 solve.  The
+        // constants take 13 LDS reads in FP64 and 9 in FP32 as compiled; the
+        // last interval of a batch reads its own again, so that the reads are
+        // not under a branch
+        __builtin_amdgcn_sched_barrier(0);
+        load_consts(t + 1 < nb ? t + 1 : t);
+        lds_wait_all_but<sizeof(T) == 8 ? 13 : 9>();
+        // the 3 x 3 system Z M = W: Z = S_w^{-1} + T[:, 6..8] (as exchanged),
+        // W = T when S_w is invertible, else Z = I + S_w T[:, 6..8],
+        // W = S_w T; M by the adjugate of Z
         T z[9], w[3];
         if (P.sinv) {
 #pragma unroll
-          for (int e2 = 0; e2 < 9; ++e2) z[e2] = siv[e2] + t1[e2];
+          for (int e2 = 0; e2 < 9; ++e2) z[e2] = t1[e2];
 #pragma unroll
           for (int a = 0; a < 3; ++a) w[a] = tc[a];
         } else {
@@ -802,12 +824,6 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
         const T j20 = z[3] * z[7] - z[4] * z[6], j21 = z[1] * z[6] - z[0] * z[7], j22 = z[0] * z[4] - z[1] * z[3];
         const T det = z[0] * j00 + z[1] * j10 + z[2] * j20;
         if (det == 0.0) singular = true;
-        // the next interval's constants, issued once this interval's exchange
-        // reads have been consumed (a wait covers every LDS read in flight, so
-        // issued earlier they would lengthen it); the last interval of a
-        // batch reads its own again, so that the reads are not under a branch
-        lds_handoff();
-        load_consts(t + 1 < nb ? t + 1 : t);
         // 1/det: the hardware reciprocal (relative error below 5e-8 for FP64
         // on gfx950) refined by one Newton step (about 2e-15); det is O(1)
         // here, so no scaling is needed
