@@ -228,17 +228,25 @@ __device__ __forceinline__ void uwalk(const F (&bv)[KU][P], const F* __restrict_
 #pragma unroll
       for (int c = 0; c < M; ++c) acc[c] = fma(pe, w[off * M + c], acc[c]);
     } else if constexpr (R == 2) {
+      // the sum over the last dimension starts from its first point, whose
+      // basis value is the constant 1: the term is the surplus itself, and
+      // where it is the only term (no budget left) it goes straight into acc
       constexpr int n = upto(B - ex);
-      F t[M];
-#pragma unroll
-      for (int c = 0; c < M; ++c) t[c] = F(0);
-#pragma unroll
-      for (int q = 0; q < n; ++q)
-#pragma unroll
-        for (int c = 0; c < M; ++c) t[c] = fma(bv[KU - 1][q], w[(off + q) * M + c], t[c]);
       const F pe = p * bv[KU - 2][E];
+      if constexpr (n == 1) {
 #pragma unroll
-      for (int c = 0; c < M; ++c) acc[c] = fma(pe, t[c], acc[c]);
+        for (int c = 0; c < M; ++c) acc[c] = fma(pe, w[off * M + c], acc[c]);
+      } else {
+        F t[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) t[c] = w[off * M + c];
+#pragma unroll
+        for (int q = 1; q < n; ++q)
+#pragma unroll
+          for (int c = 0; c < M; ++c) t[c] = fma(bv[KU - 1][q], w[(off + q) * M + c], t[c]);
+#pragma unroll
+        for (int c = 0; c < M; ++c) acc[c] = fma(pe, t[c], acc[c]);
+      }
     } else {
       uwalk<KU, P, M, R - 1, B - ex, off, 0, F>(bv, w, p * bv[KU - R][E], acc);
     }
