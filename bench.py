@@ -158,7 +158,8 @@ def batched_leg(dev, reps: int) -> dict:
     bms, ubms = float(np.median(ms)), float(np.median(ums))
     flops = newton_flops(N, it.cpu().numpy())
     return {"workload": "mixed batch: " + A.W.BATCH.name, "n_bvps": n, "converged": converged,
-            "roofline": alu_roofline("k_newton_batch<double>", flops, bms, PEAK_FP64_TFLOPS),
+            "roofline": alu_roofline("k_newton_batch_grid<double>" if slots == 0 else "k_newton_batch<double>",
+                                     flops, bms, PEAK_FP64_TFLOPS),
             "schedule": {"order": "larger N*T first" if order == S.ORDER_LONGEST_FIRST else "as given",
                          "slots_per_cu": slots, "source": os.path.relpath(src, ROOT) if src else "default"},
             "graph": True, "ms": bms, "bvps_per_s": converged / (bms / 1e3),

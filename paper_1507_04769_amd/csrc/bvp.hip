@@ -1099,6 +1099,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   }
 }
 
+// One workgroup per BVP in plan order (the form without a slot loop, which
+// keeps the registers of the loop out of the Newton solve).
+template <typename T>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_newton_batch_grid(
+    BvpArgs P, BatchArgs B, const double* __restrict__ x0, double* __restrict__ lam0, double* __restrict__ u0,
+    double* __restrict__ Vout, int32_t* __restrict__ status, int32_t* __restrict__ iters,
+    double* __restrict__ ws) {
+  __shared__ SweepShared<T> sh;
+  const int64_t j = B.order[blockIdx.x];
+  newton_bvp(P, B.N[j], B.h[j], j, ws + B.off[j], x0, lam0, u0, Vout, nullptr, status, iters, sh);
+}
+
 __global__ void k_reset_counter(int32_t* counter) {
   if (threadIdx.x == 0) *counter = 0;
 }
@@ -1360,7 +1372,14 @@ extern "C" int sgcm_solve_bvps_batch(const sgcm_batch* b, const double* x0, doub
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b->counter);
   }
   const unsigned g = (unsigned)(B.persistent ? (b->slots < b->n ? b->slots : b->n) : b->n);
-  if (b->args.fp32)
+  if (!B.persistent) {
+    if (b->args.fp32)
+      hipLaunchKernelGGL(k_newton_batch_grid<float>, dim3(g), dim3(64), 0, s, b->args, B, x0, lambda0, u0, V,
+                         status, iters, (double*)workspace);
+    else
+      hipLaunchKernelGGL(k_newton_batch_grid<double>, dim3(g), dim3(64), 0, s, b->args, B, x0, lambda0, u0, V,
+                         status, iters, (double*)workspace);
+  } else if (b->args.fp32)
     hipLaunchKernelGGL(k_newton_batch<float>, dim3(g), dim3(64), 0, s, b->args, B, x0, lambda0, u0, V, status,
                        iters, (double*)workspace);
   else
