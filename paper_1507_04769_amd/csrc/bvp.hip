@@ -1139,7 +1139,7 @@ __global__ __launch_bounds__(256) void k_rhs(BvpArgs P, int64_t n, const double*
 
 // Workspace of one BVP in doubles, a multiple of 256 bytes: Y (N + 1) x 12,
 // F_0 and F_N (16), the interval solutions N x 84 (in the solve's type) and
-// the point blocks 120 x pb_stride(N) (in the solve's type).
+// the point blocks kPB x pb_stride(N) (71 entries per point, in the solve's type).
 int64_t bvp_doubles(int64_t N, int fp32) {
   const int64_t esize = fp32 ? 4 : 8;
   const int64_t d = 12 * (N + 1) + 16 + kZI * N + (kPB * pb_stride(N) * esize + 7) / 8;

@@ -182,3 +182,18 @@ def test_results_do_not_depend_on_input_order():
     b = gpu_solve(gp, x0[perm])
     for k in ("lambda0", "u0", "V", "traj", "status", "iters"):
         assert np.array_equal(a[k][perm], b[k]), k
+
+
+def test_launch_above_the_ordered_size():
+    # a launch of more than 4096 BVPs takes them in input order (no launch
+    # order is formed); each BVP's outputs must equal those of the same BVP
+    # in ordered launches of at most 4096, and the oracle's on a sample
+    gp, op = problems(N=8, T=2.0)
+    x0 = W.uniform_in_box(4100, seed=118)
+    a = gpu_solve(gp, x0)
+    b0, b1 = gpu_solve(gp, x0[:4096]), gpu_solve(gp, x0[4096:])
+    for k in ("lambda0", "u0", "V", "traj", "status", "iters"):
+        assert np.array_equal(a[k], np.concatenate([b0[k], b1[k]])), k
+    pick = np.r_[0:8, 4090:4100]
+    o = O.solve_bvps(op, x0[pick])
+    assert_parity({k: a[k][pick] for k in a}, o)
