@@ -75,6 +75,21 @@ def newton_flops(N, iters: np.ndarray) -> float:
     return float(np.sum(solves + (it + 2) * (N + 1) * FLOPS_PER_POINT_EVAL))
 
 
+# the first Newton step formed from a solve plan: a combination of six
+# trajectories per mesh point and unknown (12 x 6 multiply-adds)
+FLOPS_PER_POINT_PLAN_STEP = 12 * 6 * 2
+
+
+def newton_flops_plan(N, iters: np.ndarray) -> float:
+    """Flops of the same solves with a plan: the first step is formed from the
+    plan (FLOPS_PER_POINT_PLAN_STEP per point) instead of solved, so there
+    remain iters linear solves and (iters + 1) evaluations per BVP."""
+    it = iters.astype(np.float64)
+    N = np.asarray(N, dtype=np.float64) + 0 * it
+    return float(np.sum(it * N * FLOPS_PER_INTERVAL_SOLVE + (it + 1) * (N + 1) * FLOPS_PER_POINT_EVAL
+                        + (N + 1) * FLOPS_PER_POINT_PLAN_STEP))
+
+
 def alu_roofline(kernel: str, flops: float, ms: float, peak: float) -> dict:
     achieved = flops / (ms / 1e3) / 1e12
     return {"kernel": kernel, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
@@ -294,11 +309,17 @@ def main():
     surplus = torch.empty((M, wl.m), dtype=torch.float64, device=dev)
     uq = torch.empty((len(xq_host), wl.m), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+    # the problem's solve plan (first Newton steps of the six unit initial
+    # states), made once like the grid, before the timed steps
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter()
+    plan = S.Plan(prob, stream)
+    plan_ms = (time.perf_counter() - t_plan) * 1e3
 
     def step(ev=None):
         if ev is not None:
             ev[0].record(stream)
-        S.sgcm_solve_bvps(prob, x0, lam, u0, V, traj, st, it, ws, stream)
+        S.sgcm_solve_bvps_plan(plan, x0, lam, u0, V, traj, st, it, ws, stream)
         if ev is not None:
             ev[1].record(stream)
         S.sgcm_build_interpolant(grid, u0, surplus, stream)
@@ -328,8 +349,17 @@ def main():
     converged = int(np.sum(status == S.CONVERGED))
     total_s = float(np.sum(step_ms)) / 1e3
     value = converged * args.steps / total_s
-    flops = newton_flops(wl.n_intervals, iters)
+    flops = newton_flops_plan(wl.n_intervals, iters)
     achieved = flops / (float(np.mean(solve_ms)) / 1e3) / 1e12
+    # the same solve without the plan (each BVP solving its first step), for
+    # comparison, on outputs of its own
+    from paper_1507_04769_amd import autotune as A
+    lam_n, u0_n, V_n, traj_n = torch.empty_like(lam), torch.empty_like(u0), torch.empty_like(V), torch.empty_like(traj)
+    st_n, it_n = torch.empty_like(st), torch.empty_like(it)
+    noplan_ms = A.time_ms(lambda: S.sgcm_solve_bvps(prob, x0, lam_n, u0_n, V_n, traj_n, st_n, it_n, ws), 5)
+    same_status = bool(torch.equal(st, st_n) and torch.equal(it, it_n))
+    lam_dev = float(((lam - lam_n).abs().amax(dim=1) / lam_n.abs().amax(dim=1).clamp_min(1e-8)).max().item())
+    del lam_n, u0_n, V_n, traj_n, st_n, it_n
     eval_flops_q = eval_flops_per_query(grid.keys(), wl.level, wl.m)
 
     batched = None if args.no_batched or args.workload != "full" else batched_leg(dev, 5)
@@ -367,10 +397,16 @@ def main():
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
         "phases_ms": {"solve_bvps": float(np.mean(solve_ms)), "build_interpolant": float(np.mean(build_ms)),
                       "eval_feedback": float(np.mean(eval_ms))},
+        "solve_plan": {"create_ms": plan_ms,
+                       "note": "first Newton step of each BVP formed from the problem's plan (made once, "
+                               "outside the timed steps, like the grid)",
+                       "solve_without_plan_ms": float(np.median(noplan_ms)),
+                       "same_status_and_iters_without_plan": same_status,
+                       "lambda0_max_rel_diff_without_plan": lam_dev},
         "converged": converged,
         "newton_iters_hist": np.bincount(iters).tolist(),
         "wall_s_timed": wall,
-        "roofline": {"kernel": "k_newton (sgcm_solve_bvps)", "bound": "alu", "achieved": achieved,
+        "roofline": {"kernel": "k_newton (sgcm_solve_bvps_plan)", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": measured_traffic() if wl.name == W.FULL.name else None,
                      "algorithmic_flops_per_launch": flops},

@@ -138,6 +138,40 @@ int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const double* x0,
 int sgcm_characteristic_rhs(const sgcm_problem* p, int64_t n_points, const double* y,
                             double* phi, double* dphi, void* stream);
 
+/* ---- solve plans: the first Newton step by superposition --------------- */
+
+/* Newton's iteration starts with one step from Y = 0: the collocation
+ * solution of the BVP of eq. hamchar linearised about the origin (the initial
+ * guess).  For both models the right-hand side vanishes at the origin, so at
+ * Y = 0 the residual is [-x0; 0; 0] and the Jacobian does not depend on x0:
+ * that step is linear in x0, Y1(x0) = sum_j x0_j Y1(e_j).  A plan holds the
+ * problem and the steps Y1(e_j) of the six unit initial states, and
+ * sgcm_solve_bvps_plan forms each BVP's first step from them instead of
+ * solving it: the same iterates as sgcm_solve_bvps up to rounding, with one
+ * serial linear solve fewer per BVP. */
+typedef struct sgcm_plan sgcm_plan;
+
+/* Create a plan for problem p (copied).  The six steps are solved on `stream`
+ * in FP64 whatever p->precision (which applies to the solves with the plan),
+ * and the call synchronizes the stream.  On success *out owns 6 x (N+1) x 12
+ * doubles of device memory on the current device.  Returns SGCM_EINVAL for an
+ * invalid problem or out == NULL, SGCM_ENOMEM, SGCM_EDEVICE, and
+ * SGCM_EUNSUPPORTED when the linearised step is singular or not finite (then
+ * sgcm_solve_bvps reports that per BVP). */
+int sgcm_plan_create(const sgcm_problem* p, void* stream, sgcm_plan** out);
+
+/* sgcm_solve_bvps for the plan's problem, each BVP's first Newton step formed
+ * from the plan.  Arguments, workspace (sgcm_solve_bvps_workspace of the
+ * plan's problem), outputs and errors as for sgcm_solve_bvps.  The plan is
+ * only read: calls with one plan may run concurrently, with the plan's device
+ * current. */
+int sgcm_solve_bvps_plan(const sgcm_plan* plan, int64_t n_bvps, const double* x0,
+                         double* lambda0, double* u0, double* V, double* traj,
+                         int32_t* status, int32_t* iters, void* workspace,
+                         size_t ws_bytes, void* stream);
+
+void sgcm_plan_destroy(sgcm_plan* plan);
+
 /* ---- batches of BVPs with mixed meshes and horizons --------------------- */
 
 /* Plan for n_bvps BVPs of one problem whose mesh size N and horizon T differ

@@ -28,7 +28,8 @@ FP64, FP32 = 0, 1
 
 # every extern "C" symbol declared in include/sgcm.h
 EXPORTS = ("sgcm_strerror", "sgcm_version", "sgcm_solve_bvps_workspace", "sgcm_solve_bvps",
-           "sgcm_characteristic_rhs", "sgcm_batch_create", "sgcm_batch_workspace", "sgcm_solve_bvps_batch",
+           "sgcm_characteristic_rhs", "sgcm_plan_create", "sgcm_solve_bvps_plan", "sgcm_plan_destroy",
+           "sgcm_batch_create", "sgcm_batch_workspace", "sgcm_solve_bvps_batch",
            "sgcm_batch_destroy", "sgcm_grid_create", "sgcm_grid_size", "sgcm_grid_nodes",
            "sgcm_grid_keys", "sgcm_grid_destroy", "sgcm_build_interpolant", "sgcm_eval_feedback",
            "sgcm_eval_feedback_f32")
@@ -105,6 +106,9 @@ def lib() -> ctypes.CDLL:
         "sgcm_solve_bvps_workspace": (ctypes.c_int, [P, i64, ctypes.POINTER(ctypes.c_size_t)]),
         "sgcm_solve_bvps": (ctypes.c_int, [P, i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
         "sgcm_characteristic_rhs": (ctypes.c_int, [P, i64, vp, vp, vp, vp]),
+        "sgcm_plan_create": (ctypes.c_int, [P, vp, ctypes.POINTER(vp)]),
+        "sgcm_solve_bvps_plan": (ctypes.c_int, [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
+        "sgcm_plan_destroy": (None, [vp]),
         "sgcm_batch_create": (ctypes.c_int, [P, i64, vp, vp, ctypes.POINTER(_CSchedule), ctypes.POINTER(vp)]),
         "sgcm_batch_workspace": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_size_t)]),
         "sgcm_solve_bvps_batch": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
@@ -177,7 +181,7 @@ def sgcm_solve_bvps_workspace(problem: Problem, n_bvps: int) -> int:
     return int(out.value)
 
 
-def sgcm_solve_bvps(problem: Problem, x0, lambda0, u0, V, traj, status, iters, workspace, stream=None):
+def _solve_args(problem: Problem, x0, lambda0, u0, V, traj, status, iters, workspace, stream):
     import torch
     f64, i32 = torch.float64, torch.int32
     n = x0.shape[0] if x0 is not None else 0
@@ -185,13 +189,43 @@ def sgcm_solve_bvps(problem: Problem, x0, lambda0, u0, V, traj, status, iters, w
         raise ValueError("x0 must be n x 6")
     ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
     m, NP = int(problem.m), int(problem.N) + 1
-    rc = lib().sgcm_solve_bvps(ctypes.byref(problem.c()), int(n), _ptr(x0, f64, "x0"),
-                               _ptr(lambda0, f64, "lambda0", 6 * n), _ptr(u0, f64, "u0", m * n),
-                               _ptr(V, f64, "V", n), _ptr(traj, f64, "traj", 12 * NP * n),
-                               _ptr(status, i32, "status", n), _ptr(iters, i32, "iters", n),
-                               _ptr(workspace, None, "workspace"), ctypes.c_size_t(ws_bytes),
-                               _stream(stream))
-    _check(rc, "sgcm_solve_bvps")
+    return (int(n), _ptr(x0, f64, "x0"), _ptr(lambda0, f64, "lambda0", 6 * n), _ptr(u0, f64, "u0", m * n),
+            _ptr(V, f64, "V", n), _ptr(traj, f64, "traj", 12 * NP * n), _ptr(status, i32, "status", n),
+            _ptr(iters, i32, "iters", n), _ptr(workspace, None, "workspace"), ctypes.c_size_t(ws_bytes),
+            _stream(stream))
+
+
+def sgcm_solve_bvps(problem: Problem, x0, lambda0, u0, V, traj, status, iters, workspace, stream=None):
+    args = _solve_args(problem, x0, lambda0, u0, V, traj, status, iters, workspace, stream)
+    _check(lib().sgcm_solve_bvps(ctypes.byref(problem.c()), *args), "sgcm_solve_bvps")
+
+
+class Plan:
+    """sgcm_plan: a problem with the first Newton steps of the six unit
+    initial states (the step is linear in the initial state), owned by
+    libsgcm; creating it runs one small solve and synchronizes the stream."""
+
+    def __init__(self, problem: Problem, stream=None):
+        self.problem = problem
+        h = ctypes.c_void_p()
+        _check(lib().sgcm_plan_create(ctypes.byref(problem.c()), _stream(stream), ctypes.byref(h)),
+               "sgcm_plan_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.sgcm_plan_destroy(h)
+            self._h = None
+
+
+def sgcm_solve_bvps_plan(plan: Plan, x0, lambda0, u0, V, traj, status, iters, workspace, stream=None):
+    args = _solve_args(plan.problem, x0, lambda0, u0, V, traj, status, iters, workspace, stream)
+    _check(lib().sgcm_solve_bvps_plan(plan.handle, *args), "sgcm_solve_bvps_plan")
 
 
 def sgcm_characteristic_rhs(problem: Problem, y, phi, dphi=None, stream=None):
@@ -346,8 +380,13 @@ class BVPSolution:
 
 
 def solve_bvps(problem: Problem, x0, want_traj: bool = False, want_V: bool = True, workspace=None,
-               stream=None) -> BVPSolution:
+               stream=None, plan: "Plan | None" = None) -> BVPSolution:
+    """Solve the BVPs from the initial states x0 (n x 6, device); with a plan
+    (whose problem is then the one solved) each first Newton step is formed
+    from the plan."""
     import torch
+    if plan is not None:
+        problem = plan.problem
     dev = x0.device
     n = x0.shape[0]
     lam = torch.empty((n, 6), dtype=torch.float64, device=dev)
@@ -359,7 +398,10 @@ def solve_bvps(problem: Problem, x0, want_traj: bool = False, want_V: bool = Tru
     if workspace is None:
         nbytes = sgcm_solve_bvps_workspace(problem, n)
         workspace = torch.empty((max(nbytes, 256) + 255) // 256 * 32, dtype=torch.float64, device=dev)
-    sgcm_solve_bvps(problem, x0, lam, u0, V, traj, st, it, workspace, stream)
+    if plan is not None:
+        sgcm_solve_bvps_plan(plan, x0, lam, u0, V, traj, st, it, workspace, stream)
+    else:
+        sgcm_solve_bvps(problem, x0, lam, u0, V, traj, st, it, workspace, stream)
     return BVPSolution(lam, u0, V, traj, st, it)
 
 

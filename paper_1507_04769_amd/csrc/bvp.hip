@@ -57,6 +57,9 @@ struct BvpArgs {
   double U[9];   // u* = U lambda_w, U[j][i] = -B[i][j] / (r_w J_i), row-major m x 3
   double q, r, pw, T, h, alpha, tol;
   int64_t per_bvp;  // doubles of workspace per BVP
+  // A solve plan's first Newton steps for the six unit initial states, 6 x
+  // (N + 1) x 12 (device), or null: then each BVP takes its own first step.
+  const double* y1;
   int sinv;         // 1: S_w is invertible and Si holds its inverse
   int fp32;         // 1: Newton linear solve in FP32 (inexact Newton)
   double Si[9];
@@ -437,10 +440,30 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
 
   if (lane < 6) sh.xb[lane] = x0[b * 6 + lane];
   if (lane < 8) sh.zero[lane] = 0.0;
-  for (int i = lane; i < 12 * NP; i += 64) Y[i] = 0.0;
+  // it = -1: the first Newton step from Y = 0 (the discrete LQR guess) is
+  // still to be taken.  At Y = 0 the residual is [-xbar; 0; 0] and the
+  // Jacobian does not depend on xbar, so that step is linear in xbar; with a
+  // plan it is the combination of the plan's steps for the unit initial
+  // states, and the loop starts with its test (it = 0).
+  int it = -1, st = SGCM_BVP_MAXITER;
+  if (P.y1) {
+    double xb[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) xb[j] = x0[b * 6 + j];
+    const int64_t n12 = 12 * (int64_t)NP;
+#pragma unroll 4
+    for (int64_t i = lane; i < n12; i += 64) {
+      double y = xb[0] * P.y1[i];
+#pragma unroll
+      for (int j = 1; j < 6; ++j) y = fma(xb[j], P.y1[j * n12 + i], y);
+      Y[i] = y;
+    }
+    it = 0;
+  } else {
+    for (int i = lane; i < 12 * NP; i += 64) Y[i] = 0.0;
+  }
   wave_mem_sync();
 
-  int it = -1, st = SGCM_BVP_MAXITER;
   while (true) {
     // ---- residual F(Y) and its max norm (lane-parallel over mesh points) ----
     double lmax = 0.0;
@@ -1212,6 +1235,7 @@ int make_bvp_args(const sgcm_problem* p, BvpArgs* a) {
   if (!a->sinv)
     for (int e = 0; e < 9; ++e) a->Si[e] = 0.0;
   a->per_bvp = bvp_doubles(p->N, a->fp32);
+  a->y1 = nullptr;
   return SGCM_OK;
 }
 
@@ -1229,13 +1253,15 @@ extern "C" int sgcm_solve_bvps_workspace(const sgcm_problem* p, int64_t n_bvps, 
   return SGCM_OK;
 }
 
-extern "C" int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const double* x0, double* lambda0,
-                               double* u0, double* V, double* traj, int32_t* status, int32_t* iters,
-                               void* workspace, size_t ws_bytes, void* stream) {
+// sgcm_solve_bvps, with the first Newton steps of a plan (y1) or without (null).
+static int solve_bvps(const sgcm_problem* p, const double* y1, int64_t n_bvps, const double* x0, double* lambda0,
+               double* u0, double* V, double* traj, int32_t* status, int32_t* iters, void* workspace,
+               size_t ws_bytes, void* stream) {
   BvpArgs a;
   if (n_bvps < 0) return SGCM_EINVAL;
   int rc = make_bvp_args(p, &a);
   if (rc != SGCM_OK) return rc;
+  a.y1 = y1;
   if (n_bvps == 0) return SGCM_OK;
   if (n_bvps > 0x7fffffffLL) return SGCM_EUNSUPPORTED;
   if (!x0 || !lambda0 || !u0 || !status || !iters || !workspace) return SGCM_EINVAL;
@@ -1255,6 +1281,94 @@ extern "C" int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const doub
     hipLaunchKernelGGL(k_newton<double>, dim3((unsigned)n_bvps), dim3(64), 0, s, a, x0, lambda0, u0, V, traj,
                        status, iters, (double*)workspace, order);
   return hipGetLastError() == hipSuccess ? SGCM_OK : SGCM_EDEVICE;
+}
+
+extern "C" int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const double* x0, double* lambda0,
+                               double* u0, double* V, double* traj, int32_t* status, int32_t* iters,
+                               void* workspace, size_t ws_bytes, void* stream) {
+  return solve_bvps(p, nullptr, n_bvps, x0, lambda0, u0, V, traj, status, iters, workspace, ws_bytes, stream);
+}
+
+struct sgcm_plan {
+  sgcm_problem p;
+  double* y1;  // device, 6 x (N + 1) x 12
+};
+
+// The first Newton step of the six unit initial states, solved by the same
+// kernel with max_iter = 0 (in FP64 whatever the plan's precision): the
+// trajectory output is that step.  Synchronous.
+extern "C" int sgcm_plan_create(const sgcm_problem* p, void* stream, sgcm_plan** out) {
+  if (!out) return SGCM_EINVAL;
+  *out = nullptr;
+  BvpArgs a;
+  int rc = make_bvp_args(p, &a);
+  if (rc != SGCM_OK) return rc;
+  sgcm_problem q = *p;
+  q.precision = SGCM_FP64;
+  q.max_iter = 0;
+  size_t ws_bytes = 0;
+  rc = sgcm_solve_bvps_workspace(&q, 6, &ws_bytes);
+  if (rc != SGCM_OK) return rc;
+  const int64_t NP = (int64_t)p->N + 1;
+  const size_t y1_bytes = (size_t)6 * 12 * NP * sizeof(double);
+  // scratch: workspace (256-byte aligned first), identity x0, lambda0, u0, status, iters
+  const size_t tmp_bytes = ws_bytes + 256 + 36 * sizeof(double) + 36 * sizeof(double) + 18 * sizeof(double) +
+                           12 * sizeof(int32_t);
+  sgcm_plan* plan = new (std::nothrow) sgcm_plan();
+  if (!plan) return SGCM_ENOMEM;
+  plan->p = *p;
+  plan->y1 = nullptr;
+  char* tmp = nullptr;
+  if (hipMalloc((void**)&plan->y1, y1_bytes) != hipSuccess || hipMalloc((void**)&tmp, tmp_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    if (plan->y1) (void)hipFree(plan->y1);
+    delete plan;
+    return SGCM_ENOMEM;
+  }
+  double* ws = reinterpret_cast<double*>(tmp);
+  double* x0 = reinterpret_cast<double*>(tmp + (ws_bytes + 255) / 256 * 256);
+  double* lam = x0 + 36;
+  double* u0 = lam + 36;
+  int32_t* st = reinterpret_cast<int32_t*>(u0 + 18);
+  int32_t* its = st + 6;
+  double eye[36] = {};
+  for (int j = 0; j < 6; ++j) eye[j * 6 + j] = 1.0;
+  int32_t hst[12];
+  hipStream_t s = (hipStream_t)stream;
+  rc = SGCM_OK;
+  if (hipMemcpyAsync(x0, eye, sizeof(eye), hipMemcpyHostToDevice, s) != hipSuccess) rc = SGCM_EDEVICE;
+  if (rc == SGCM_OK)
+    rc = solve_bvps(&q, nullptr, 6, x0, lam, u0, nullptr, plan->y1, st, its, ws, ws_bytes, stream);
+  if (rc == SGCM_OK && hipMemcpyAsync(hst, st, sizeof(hst), hipMemcpyDeviceToHost, s) != hipSuccess)
+    rc = SGCM_EDEVICE;
+  if (rc == SGCM_OK && hipStreamSynchronize(s) != hipSuccess) rc = SGCM_EDEVICE;
+  (void)hipFree(tmp);
+  // a singular or non-finite linearised step has no plan (the solve without
+  // one reports it per BVP)
+  for (int j = 0; rc == SGCM_OK && j < 6; ++j)
+    if ((hst[j] != SGCM_BVP_CONVERGED && hst[j] != SGCM_BVP_MAXITER) || hst[6 + j] != 0) rc = SGCM_EUNSUPPORTED;
+  if (rc != SGCM_OK) {
+    (void)hipGetLastError();
+    (void)hipFree(plan->y1);
+    delete plan;
+    return rc;
+  }
+  *out = plan;
+  return SGCM_OK;
+}
+
+extern "C" int sgcm_solve_bvps_plan(const sgcm_plan* plan, int64_t n_bvps, const double* x0, double* lambda0,
+                                    double* u0, double* V, double* traj, int32_t* status, int32_t* iters,
+                                    void* workspace, size_t ws_bytes, void* stream) {
+  if (!plan) return SGCM_EINVAL;
+  return solve_bvps(&plan->p, plan->y1, n_bvps, x0, lambda0, u0, V, traj, status, iters, workspace, ws_bytes,
+                    stream);
+}
+
+extern "C" void sgcm_plan_destroy(sgcm_plan* plan) {
+  if (!plan) return;
+  (void)hipFree(plan->y1);
+  delete plan;
 }
 
 extern "C" int sgcm_characteristic_rhs(const sgcm_problem* p, int64_t n_points, const double* y, double* phi,

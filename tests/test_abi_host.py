@@ -123,6 +123,20 @@ def test_entry_points_validate_before_device_work():
     assert L.sgcm_build_interpolant(g.handle, 0, fake, vp(8192), None) == S.SGCM_EINVAL
 
 
+def test_plan_entry_points_validate_before_device_work():
+    L = S.lib()
+    vp = ctypes.c_void_p
+    out = vp(1234)
+    assert L.sgcm_plan_create(ctypes.byref(S.Problem(N=0).c()), None, ctypes.byref(out)) == S.SGCM_EINVAL
+    assert out.value is None  # cleared on failure
+    assert L.sgcm_plan_create(ctypes.byref(S.Problem(model=7).c()), None, ctypes.byref(out)) == S.SGCM_EINVAL
+    assert L.sgcm_plan_create(ctypes.byref(S.Problem().c()), None, None) == S.SGCM_EINVAL
+    assert L.sgcm_plan_create(None, None, ctypes.byref(out)) == S.SGCM_EINVAL
+    assert L.sgcm_solve_bvps_plan(None, 1, None, None, None, None, None, None, None, None, 0,
+                                  None) == S.SGCM_EINVAL
+    L.sgcm_plan_destroy(None)
+
+
 def test_batch_create_validates_before_device_work():
     # every rejected argument is caught on the host, before any HIP call
     L = S.lib()

@@ -1,0 +1,157 @@
+"""GPU parity of the solve with a plan (sgcm_solve_bvps_plan): each BVP's
+first Newton step from Y = 0 (the collocation solution of the problem
+linearised about the origin, Sec. 3.1) is formed from the plan's first steps
+of the six unit initial states, the step being linear in the initial state.
+
+Bar: the same as for sgcm_solve_bvps against the oracle (status and iteration
+count bit-exact; lambda(0), u(0), V and the trajectory within 1e-8 relative
+per BVP); against the solve without a plan the same statuses and iteration
+counts and values equal to 1e-9 relative (the two differ only by the rounding
+of the first step).
+"""
+import numpy as np
+import pytest
+
+import paper_1507_04769_amd as S
+from oracle import oracle as O
+from paper_1507_04769_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+REL = 1e-8
+REL_PLAN = 1e-9
+REL_FP32 = 1e-7  # the FP32 inexact Newton's bar, as for the solve without a plan
+KEYS = ("lambda0", "u0", "V", "traj", "status", "iters")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def rel_err(a, b):
+    a = np.asarray(a).reshape(len(a), -1)
+    b = np.asarray(b).reshape(len(b), -1)
+    return np.max(np.abs(a - b), axis=1) / np.maximum(np.max(np.abs(b), axis=1), 1e-8)
+
+
+def problems(model=S.MODEL_RIGID_BODY, m=3, N=64, T=20.0, tol=W.TOL, max_iter=W.MAX_ITER, precision=S.FP64):
+    B = W.input_matrix(m)
+    g = S.Problem(model=model, m=m, J=W.J_DIAG, B=B, q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W, T=T, N=N,
+                  tol=tol, max_iter=max_iter, precision=precision)
+    o = O.Problem(model={S.MODEL_RIGID_BODY: O.RIGID_BODY, S.MODEL_LINEARISED: O.LINEARISED}[model],
+                  n=6, m=m, J=W.J_DIAG, B=B, q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W, T=T, N=N, tol=tol,
+                  max_iter=max_iter)
+    return g, o
+
+
+def solve(prob, x0, plan=None, stream=None):
+    torch = _torch()
+    xd = torch.tensor(np.asarray(x0, dtype=np.float64), device="cuda")
+    r = S.solve_bvps(prob, xd, want_traj=True, plan=plan, stream=stream)
+    torch.cuda.synchronize()
+    return {k: getattr(r, k).cpu().numpy() for k in KEYS}
+
+
+def assert_parity(g, o):
+    assert np.array_equal(g["status"], o.status), (g["status"], o.status)
+    assert np.array_equal(g["iters"], o.iters), (g["iters"], o.iters)
+    ok = o.status == O.CONVERGED
+    for k, ov in (("lambda0", o.lambda0), ("u0", o.u0), ("V", o.V[:, None]), ("traj", o.traj)):
+        gv = g[k][:, None] if k == "V" else g[k]
+        assert np.all(rel_err(gv[ok], ov[ok]) <= REL), k
+
+
+def assert_same_as_unplanned(a, b):
+    assert np.array_equal(a["status"], b["status"]) and np.array_equal(a["iters"], b["iters"])
+    for k in ("lambda0", "u0", "traj"):
+        assert np.all(rel_err(a[k], b[k]) <= REL_PLAN), k
+    assert np.all(rel_err(a["V"][:, None], b["V"][:, None]) <= REL_PLAN)
+
+
+def test_plan_small_workload_parity():
+    w = W.SMALL
+    gp, op = problems(N=w.n_intervals, T=w.horizon)
+    x0 = O.grid(6, w.level, W.BOX_LO, W.BOX_HI).nodes
+    g = solve(gp, x0, plan=S.Plan(gp))
+    o = O.solve_bvps(op, x0, want_traj=True)
+    assert np.all(o.status == O.CONVERGED)
+    assert_parity(g, o)
+    assert_same_as_unplanned(g, solve(gp, x0))
+
+
+def test_plan_full_workload():
+    # level-4 grid (1457 nodes), N = 256: every node against the solve without
+    # a plan, a seeded sample against the oracle, and the oracle's residual of
+    # every trajectory
+    w = W.FULL
+    gp, op = problems(N=w.n_intervals, T=w.horizon)
+    x0 = O.grid(6, w.level, W.BOX_LO, W.BOX_HI).nodes
+    g = solve(gp, x0, plan=S.Plan(gp))
+    assert np.all(g["status"] == S.CONVERGED)
+    assert_same_as_unplanned(g, solve(gp, x0))
+    idx = np.unique(np.concatenate([[0, len(x0) - 1], W.sample_indices(len(x0), 10, seed=130)]))
+    o = O.solve_bvps(op, x0[idx], want_traj=True)
+    assert_parity({k: v[idx] for k, v in g.items()}, o)
+    F = O.residual(op, x0, g["traj"])
+    assert np.max(np.abs(F)) <= W.TOL + 1e-12
+
+
+def test_plan_linear_model_and_underactuated_region():
+    # the linearised model: the first step is the solution (0 iterations)
+    gp, op = problems(S.MODEL_LINEARISED, N=64)
+    x0 = W.uniform_in_box(40, seed=131)
+    g = solve(gp, x0, plan=S.Plan(gp))
+    assert np.all(g["status"] == S.CONVERGED) and np.all(g["iters"] == 0)
+    assert_parity(g, O.solve_bvps(op, x0, want_traj=True))
+    # two wheels where the oracle converges everywhere (0.3 x box, T = 2)
+    gp, op = problems(m=2, N=40, T=2.0)
+    x0 = 0.3 * W.uniform_in_box(64, seed=132)
+    g = solve(gp, x0, plan=S.Plan(gp))
+    o = O.solve_bvps(op, x0, want_traj=True)
+    assert np.all(o.status == O.CONVERGED)
+    assert_parity(g, o)
+
+
+def test_plan_status_rules_and_meshes():
+    for N, T in [(1, 0.5), (7, 2.0), (32, 4.0), (300, 20.0)]:
+        gp, op = problems(N=N, T=T)
+        x0 = np.vstack([np.zeros(6), W.uniform_in_box(6, seed=133 + N)])
+        x0[3, 2] = np.nan
+        plan = S.Plan(gp)
+        g = solve(gp, x0, plan=plan)
+        assert g["status"][0] == S.CONVERGED and g["iters"][0] == 0 and not np.any(g["traj"][0])
+        assert g["status"][3] == S.NONFINITE and g["iters"][3] == 0
+        assert_parity(g, O.solve_bvps(op, x0, want_traj=True))
+    for tol, max_iter in [(W.TOL, 0), (0.0, 2)]:
+        gp, op = problems(N=32, T=4.0, tol=tol, max_iter=max_iter)
+        x0 = W.uniform_in_box(5, seed=134)
+        g = solve(gp, x0, plan=S.Plan(gp))
+        o = O.solve_bvps(op, x0, want_traj=True)
+        assert np.array_equal(g["status"], o.status) and np.array_equal(g["iters"], o.iters)
+
+
+def test_plan_fp32_newton():
+    # an FP32 problem: its first steps are still solved in FP64; the FP32
+    # inexact Newton then converges to the FP64 test as without a plan
+    w = W.SMALL
+    gp, op = problems(N=w.n_intervals, T=w.horizon, precision=S.FP32)
+    x0 = O.grid(6, w.level, W.BOX_LO, W.BOX_HI).nodes
+    g = solve(gp, x0, plan=S.Plan(gp))
+    o = O.solve_bvps(op, x0)
+    assert np.all(g["status"] == S.CONVERGED)
+    assert np.all(rel_err(g["lambda0"], o.lambda0) <= REL_FP32)
+    assert np.all(rel_err(g["u0"], o.u0) <= REL_FP32)
+    extra = g["iters"].astype(int) - o.iters.astype(int)
+    assert extra.min() >= -1 and extra.max() <= 2
+
+
+def test_plan_reuse_streams_and_determinism():
+    torch = _torch()
+    gp, _ = problems(N=48, T=10.0)
+    plan = S.Plan(gp)
+    xa, xb = W.uniform_in_box(50, seed=135), W.uniform_in_box(30, seed=136)
+    ref_a, ref_b = solve(gp, xa, plan=plan), solve(gp, xb, plan=plan)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a, b = solve(gp, xa, plan=plan, stream=s1), solve(gp, xb, plan=plan, stream=s2)
+    for k in KEYS:
+        assert np.array_equal(a[k], ref_a[k]) and np.array_equal(b[k], ref_b[k]), k
