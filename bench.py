@@ -276,6 +276,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-rate", type=float, default=2000.0, help="requests per second")
+    ap.add_argument("--no-plan-compare", action="store_true",
+                    help="skip timing the solve without the plan (profiling runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -354,12 +356,17 @@ def main():
     # the same solve without the plan (each BVP solving its first step), for
     # comparison, on outputs of its own
     from paper_1507_04769_amd import autotune as A
-    lam_n, u0_n, V_n, traj_n = torch.empty_like(lam), torch.empty_like(u0), torch.empty_like(V), torch.empty_like(traj)
-    st_n, it_n = torch.empty_like(st), torch.empty_like(it)
-    noplan_ms = A.time_ms(lambda: S.sgcm_solve_bvps(prob, x0, lam_n, u0_n, V_n, traj_n, st_n, it_n, ws), 5)
-    same_status = bool(torch.equal(st, st_n) and torch.equal(it, it_n))
-    lam_dev = float(((lam - lam_n).abs().amax(dim=1) / lam_n.abs().amax(dim=1).clamp_min(1e-8)).max().item())
-    del lam_n, u0_n, V_n, traj_n, st_n, it_n
+    compare = {}
+    if not args.no_plan_compare:
+        lam_n, u0_n, V_n, traj_n = (torch.empty_like(lam), torch.empty_like(u0), torch.empty_like(V),
+                                    torch.empty_like(traj))
+        st_n, it_n = torch.empty_like(st), torch.empty_like(it)
+        noplan_ms = A.time_ms(lambda: S.sgcm_solve_bvps(prob, x0, lam_n, u0_n, V_n, traj_n, st_n, it_n, ws), 5)
+        compare = {"solve_without_plan_ms": float(np.median(noplan_ms)),
+                   "same_status_and_iters_without_plan": bool(torch.equal(st, st_n) and torch.equal(it, it_n)),
+                   "lambda0_max_rel_diff_without_plan":
+                       float(((lam - lam_n).abs().amax(dim=1) / lam_n.abs().amax(dim=1).clamp_min(1e-8)).max().item())}
+        del lam_n, u0_n, V_n, traj_n, st_n, it_n
     eval_flops_q = eval_flops_per_query(grid.keys(), wl.level, wl.m)
 
     batched = None if args.no_batched or args.workload != "full" else batched_leg(dev, 5)
@@ -397,12 +404,9 @@ def main():
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
         "phases_ms": {"solve_bvps": float(np.mean(solve_ms)), "build_interpolant": float(np.mean(build_ms)),
                       "eval_feedback": float(np.mean(eval_ms))},
-        "solve_plan": {"create_ms": plan_ms,
-                       "note": "first Newton step of each BVP formed from the problem's plan (made once, "
-                               "outside the timed steps, like the grid)",
-                       "solve_without_plan_ms": float(np.median(noplan_ms)),
-                       "same_status_and_iters_without_plan": same_status,
-                       "lambda0_max_rel_diff_without_plan": lam_dev},
+        "solve_plan": dict({"create_ms": plan_ms,
+                            "note": "first Newton step of each BVP formed from the problem's plan (made once, "
+                                    "outside the timed steps, like the grid)"}, **compare),
         "converged": converged,
         "newton_iters_hist": np.bincount(iters).tolist(),
         "wall_s_timed": wall,
