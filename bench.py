@@ -36,8 +36,9 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak
 #   = 1152 + 2016 for n = 12, k = 7) and the forward pass with the update (156);
 #   per mesh point and evaluation: Phi, A = df/dx and W (172) and the interval
 #   residual (48).  Transcendentals (two sincos per point) are not counted.
-#   In the first (linearised) step every interval has the same system, so its
-#   assembly is counted once per BVP, not once per interval.
+#   The first (linearised) Newton step is formed from a solve plan, so a BVP
+#   that takes iters Newton iterations does iters linear solves and iters + 1
+#   evaluations (newton_flops_plan).
 FLOPS_ASSEMBLY = 1098
 FLOPS_PER_INTERVAL_SOLVE = FLOPS_ASSEMBLY + 1152 + 2016 + 156
 FLOPS_PER_POINT_EVAL = 172 + 48
@@ -63,16 +64,6 @@ def measured_traffic() -> float | None:
     if not h or not t or h.group(1) != src:
         return None
     return float(t.group(1))
-
-
-def newton_flops(N, iters: np.ndarray) -> float:
-    """Algorithmic flops of solving BVPs with N intervals (a number, or one per
-    BVP) in the given iteration counts: (iters + 1) linear solves (the first is
-    the linearised step) and (iters + 2) evaluations per BVP."""
-    it = iters.astype(np.float64)
-    N = np.asarray(N, dtype=np.float64) + 0 * it
-    solves = (it + 1) * N * FLOPS_PER_INTERVAL_SOLVE - (N - 1) * FLOPS_ASSEMBLY
-    return float(np.sum(solves + (it + 2) * (N + 1) * FLOPS_PER_POINT_EVAL))
 
 
 # the first Newton step formed from a solve plan: a combination of six
@@ -171,7 +162,7 @@ def batched_leg(dev, reps: int) -> dict:
     run, ngroups = A.unbatched_runner(problem, x0, N, T)
     ums = A.time_ms(run, reps)
     bms, ubms = float(np.median(ms)), float(np.median(ums))
-    flops = newton_flops(N, it.cpu().numpy())
+    flops = newton_flops_plan(N, it.cpu().numpy())  # first steps from the batch's per-(N, T) steps
     return {"workload": "mixed batch: " + A.W.BATCH.name, "n_bvps": n, "converged": converged,
             "roofline": alu_roofline("k_newton_batch_grid<double>" if slots == 0 else "k_newton_batch<double>",
                                      flops, bms, PEAK_FP64_TFLOPS),
@@ -184,8 +175,9 @@ def batched_leg(dev, reps: int) -> dict:
 
 def precision_leg(dev, prob, grid, x0, lam64, u064, it64, surplus, eval_flops_q: float, reps: int) -> dict:
     """FP32 variants beside the FP64 path on the same MI355X: the FP32 inexact
-    Newton solve of the full workload (errors against the FP64 GPU solve, which
-    matches the oracle to ~1e-13) and FP32 feedback evaluation at 1e7 uniform
+    Newton solve of the full workload with its plan, against the FP64 solve
+    with its plan (errors against the FP64 GPU solve, which matches the oracle
+    to ~1e-13) and FP32 feedback evaluation at 1e7 uniform
     states (errors against the FP64 GPU evaluation of the same interpolant)."""
     import dataclasses
     import torch
@@ -204,15 +196,16 @@ def precision_leg(dev, prob, grid, x0, lam64, u064, it64, surplus, eval_flops_q:
     ws64 = torch.empty((S.sgcm_solve_bvps_workspace(p64, M) // 8 + 32,), dtype=torch.float64, device=dev)
     lam2, u02, V2 = torch.empty_like(lam), torch.empty_like(u0), torch.empty_like(V)
     st2, it2 = torch.empty_like(st), torch.empty_like(it)
-    ms32 = A.time_ms(lambda: S.sgcm_solve_bvps(p32, x0, lam, u0, V, None, st, it, ws), reps)
-    ms64 = A.time_ms(lambda: S.sgcm_solve_bvps(p64, x0, lam2, u02, V2, None, st2, it2, ws64), reps)
+    plan32, plan64 = S.Plan(p32), S.Plan(p64)  # as in the timed step: first steps from the plans
+    ms32 = A.time_ms(lambda: S.sgcm_solve_bvps_plan(plan32, x0, lam, u0, V, None, st, it, ws), reps)
+    ms64 = A.time_ms(lambda: S.sgcm_solve_bvps_plan(plan64, x0, lam2, u02, V2, None, st2, it2, ws64), reps)
     conv = int((st == S.CONVERGED).sum().item())
     el = ((lam - lam64).abs().amax(dim=1) / lam64.abs().amax(dim=1).clamp_min(1e-8)).cpu().numpy()
     eu = ((u0 - u064).abs().amax(dim=1) / u064.abs().amax(dim=1).clamp_min(1e-8)).cpu().numpy()
     i32, i64 = it.cpu().numpy(), it64
     # the same algorithmic flops as the FP64 solve; the linear solve (95 % of
     # them) runs in FP32, so the fraction is given against both peaks
-    f32 = newton_flops(prob.N, i32)
+    f32 = newton_flops_plan(prob.N, i32)
     rf = alu_roofline("k_newton<float>", f32, float(np.median(ms32)), PEAK_FP32_TFLOPS)
     rf["frac_of_fp64_peak"] = rf["achieved"] / PEAK_FP64_TFLOPS
     solve = {"ms": float(np.median(ms32)), "fp64_ms": float(np.median(ms64)), "roofline": rf,

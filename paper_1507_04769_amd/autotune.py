@@ -56,8 +56,9 @@ def time_ms(fn, reps: int) -> list:
 
 
 def unbatched_runner(problem: S.Problem, x0_dev, N, T):
-    """One sgcm_solve_bvps launch per (N, T) group, in sequence; buffers made
-    up front so that the timed region only launches."""
+    """One sgcm_solve_bvps_plan launch per (N, T) group, in sequence (each
+    group with its solve plan, as the batch forms its first Newton steps);
+    plans and buffers made up front so that the timed region only launches."""
     import torch
     groups = []
     for NN, TT in sorted(set(zip(N.tolist(), T.tolist()))):
@@ -72,11 +73,11 @@ def unbatched_runner(problem: S.Problem, x0_dev, N, T):
                 torch.empty((n,), dtype=torch.float64, device=x0_dev.device),
                 torch.empty((n,), dtype=torch.int32, device=x0_dev.device),
                 torch.empty((n,), dtype=torch.int32, device=x0_dev.device))
-        groups.append((p, xi, ws, outs))
+        groups.append((S.Plan(p), xi, ws, outs))
 
     def run():
-        for p, xi, ws, (lam, u0, V, st, it) in groups:
-            S.sgcm_solve_bvps(p, xi, lam, u0, V, None, st, it, ws)
+        for plan, xi, ws, (lam, u0, V, st, it) in groups:
+            S.sgcm_solve_bvps_plan(plan, xi, lam, u0, V, None, st, it, ws)
     return run, len(groups)
 
 

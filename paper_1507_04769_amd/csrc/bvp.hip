@@ -420,7 +420,8 @@ __device__ __forceinline__ bool point_block_store(const double a, const double (
 // workspace ws_b) by one 64-lane workgroup.
 template <typename T>
 __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const double h, const int64_t b,
-                                           double* ws_b, const double* __restrict__ x0, double* __restrict__ lam0,
+                                           const double* __restrict__ y1, double* ws_b,
+                                           const double* __restrict__ x0, double* __restrict__ lam0,
                                            double* __restrict__ u0, double* __restrict__ Vout,
                                            double* __restrict__ traj, int32_t* __restrict__ status,
                                            int32_t* __restrict__ iters, SweepShared<T>& sh) {
@@ -446,16 +447,16 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
   // plan it is the combination of the plan's steps for the unit initial
   // states, and the loop starts with its test (it = 0).
   int it = -1, st = SGCM_BVP_MAXITER;
-  if (P.y1) {
+  if (y1) {
     double xb[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) xb[j] = x0[b * 6 + j];
     const int64_t n12 = 12 * (int64_t)NP;
 #pragma unroll 4
     for (int64_t i = lane; i < n12; i += 64) {
-      double y = xb[0] * P.y1[i];
+      double y = xb[0] * y1[i];
 #pragma unroll
-      for (int j = 1; j < 6; ++j) y = fma(xb[j], P.y1[j * n12 + i], y);
+      for (int j = 1; j < 6; ++j) y = fma(xb[j], y1[j * n12 + i], y);
       Y[i] = y;
     }
     it = 0;
@@ -1034,7 +1035,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   // the workspace is scratch: workgroup g uses slot g whatever BVP it takes,
   // so that consecutive workgroups keep consecutive memory
   const int64_t b = order ? order[blockIdx.x] : blockIdx.x;
-  newton_bvp(P, P.N, P.h, b, ws + (int64_t)blockIdx.x * P.per_bvp, x0, lam0, u0, Vout, traj, status, iters, sh);
+  newton_bvp(P, P.N, P.h, b, P.y1, ws + (int64_t)blockIdx.x * P.per_bvp, x0, lam0, u0, Vout, traj, status, iters,
+             sh);
 }
 
 // The order in which the workgroups of one launch take the BVPs: decreasing
@@ -1095,6 +1097,8 @@ struct BatchArgs {
   const int32_t* N;      // per BVP: mesh intervals
   const double* h;       // per BVP: mesh width T / N
   const int64_t* off;    // per BVP: workspace offset in doubles
+  const double* y1;      // first Newton steps of the unit initial states of each (N, T) group
+  const int64_t* y1off;  // per BVP: offset of its group's steps in y1, or -1 (no plan)
   const int32_t* order;  // schedule: BVP index at each position
   int32_t* counter;      // persistent mode: next schedule position
   int64_t n;
@@ -1116,7 +1120,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   int64_t pos = B.persistent ? next_position(B.counter) : (int64_t)blockIdx.x;
   while (pos < B.n) {
     const int64_t j = B.order[pos];
-    newton_bvp(P, B.N[j], B.h[j], j, ws + B.off[j], x0, lam0, u0, Vout, nullptr, status, iters, sh);
+    const int64_t yo = B.y1off[j];
+    newton_bvp(P, B.N[j], B.h[j], j, yo >= 0 ? B.y1 + yo : nullptr, ws + B.off[j], x0, lam0, u0, Vout, nullptr,
+               status, iters, sh);
     if (!B.persistent) break;
     pos = next_position(B.counter);
   }
@@ -1131,7 +1137,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     double* __restrict__ ws) {
   __shared__ SweepShared<T> sh;
   const int64_t j = B.order[blockIdx.x];
-  newton_bvp(P, B.N[j], B.h[j], j, ws + B.off[j], x0, lam0, u0, Vout, nullptr, status, iters, sh);
+  const int64_t yo = B.y1off[j];
+  newton_bvp(P, B.N[j], B.h[j], j, yo >= 0 ? B.y1 + yo : nullptr, ws + B.off[j], x0, lam0, u0, Vout, nullptr,
+             status, iters, sh);
 }
 
 __global__ void k_reset_counter(int32_t* counter) {
@@ -1294,35 +1302,22 @@ struct sgcm_plan {
   double* y1;  // device, 6 x (N + 1) x 12
 };
 
-// The first Newton step of the six unit initial states, solved by the same
-// kernel with max_iter = 0 (in FP64 whatever the plan's precision): the
-// trajectory output is that step.  Synchronous.
-extern "C" int sgcm_plan_create(const sgcm_problem* p, void* stream, sgcm_plan** out) {
-  if (!out) return SGCM_EINVAL;
-  *out = nullptr;
-  BvpArgs a;
-  int rc = make_bvp_args(p, &a);
-  if (rc != SGCM_OK) return rc;
+// The first Newton step of the six unit initial states of problem p into y1
+// (device, 6 x (N + 1) x 12), solved by the same kernel with max_iter = 0 in
+// FP64 (the trajectory output is that step), on stream s, which is then
+// synchronized.  SGCM_EUNSUPPORTED when the step is singular or not finite.
+static int first_steps(const sgcm_problem* p, double* y1, hipStream_t s) {
   sgcm_problem q = *p;
   q.precision = SGCM_FP64;
   q.max_iter = 0;
   size_t ws_bytes = 0;
-  rc = sgcm_solve_bvps_workspace(&q, 6, &ws_bytes);
+  int rc = sgcm_solve_bvps_workspace(&q, 6, &ws_bytes);
   if (rc != SGCM_OK) return rc;
-  const int64_t NP = (int64_t)p->N + 1;
-  const size_t y1_bytes = (size_t)6 * 12 * NP * sizeof(double);
   // scratch: workspace (256-byte aligned first), identity x0, lambda0, u0, status, iters
-  const size_t tmp_bytes = ws_bytes + 256 + 36 * sizeof(double) + 36 * sizeof(double) + 18 * sizeof(double) +
-                           12 * sizeof(int32_t);
-  sgcm_plan* plan = new (std::nothrow) sgcm_plan();
-  if (!plan) return SGCM_ENOMEM;
-  plan->p = *p;
-  plan->y1 = nullptr;
+  const size_t tmp_bytes = ws_bytes + 256 + (36 + 36 + 18) * sizeof(double) + 12 * sizeof(int32_t);
   char* tmp = nullptr;
-  if (hipMalloc((void**)&plan->y1, y1_bytes) != hipSuccess || hipMalloc((void**)&tmp, tmp_bytes) != hipSuccess) {
+  if (hipMalloc((void**)&tmp, tmp_bytes) != hipSuccess) {
     (void)hipGetLastError();
-    if (plan->y1) (void)hipFree(plan->y1);
-    delete plan;
     return SGCM_ENOMEM;
   }
   double* ws = reinterpret_cast<double*>(tmp);
@@ -1334,21 +1329,38 @@ extern "C" int sgcm_plan_create(const sgcm_problem* p, void* stream, sgcm_plan**
   double eye[36] = {};
   for (int j = 0; j < 6; ++j) eye[j * 6 + j] = 1.0;
   int32_t hst[12];
-  hipStream_t s = (hipStream_t)stream;
-  rc = SGCM_OK;
   if (hipMemcpyAsync(x0, eye, sizeof(eye), hipMemcpyHostToDevice, s) != hipSuccess) rc = SGCM_EDEVICE;
-  if (rc == SGCM_OK)
-    rc = solve_bvps(&q, nullptr, 6, x0, lam, u0, nullptr, plan->y1, st, its, ws, ws_bytes, stream);
+  if (rc == SGCM_OK) rc = solve_bvps(&q, nullptr, 6, x0, lam, u0, nullptr, y1, st, its, ws, ws_bytes, s);
   if (rc == SGCM_OK && hipMemcpyAsync(hst, st, sizeof(hst), hipMemcpyDeviceToHost, s) != hipSuccess)
     rc = SGCM_EDEVICE;
   if (rc == SGCM_OK && hipStreamSynchronize(s) != hipSuccess) rc = SGCM_EDEVICE;
-  (void)hipFree(tmp);
-  // a singular or non-finite linearised step has no plan (the solve without
-  // one reports it per BVP)
+  (void)hipFree(tmp);  // waits for the device
   for (int j = 0; rc == SGCM_OK && j < 6; ++j)
     if ((hst[j] != SGCM_BVP_CONVERGED && hst[j] != SGCM_BVP_MAXITER) || hst[6 + j] != 0) rc = SGCM_EUNSUPPORTED;
-  if (rc != SGCM_OK) {
+  if (rc != SGCM_OK) (void)hipGetLastError();
+  return rc;
+}
+
+extern "C" int sgcm_plan_create(const sgcm_problem* p, void* stream, sgcm_plan** out) {
+  if (!out) return SGCM_EINVAL;
+  *out = nullptr;
+  BvpArgs a;
+  int rc = make_bvp_args(p, &a);
+  if (rc != SGCM_OK) return rc;
+  sgcm_plan* plan = new (std::nothrow) sgcm_plan();
+  if (!plan) return SGCM_ENOMEM;
+  plan->p = *p;
+  plan->y1 = nullptr;
+  const size_t y1_bytes = (size_t)6 * 12 * ((size_t)p->N + 1) * sizeof(double);
+  if (hipMalloc((void**)&plan->y1, y1_bytes) != hipSuccess) {
     (void)hipGetLastError();
+    delete plan;
+    return SGCM_ENOMEM;
+  }
+  // a singular or non-finite linearised step has no plan (the solve without
+  // one reports it per BVP)
+  rc = first_steps(p, plan->y1, (hipStream_t)stream);
+  if (rc != SGCM_OK) {
     (void)hipFree(plan->y1);
     delete plan;
     return rc;
@@ -1397,6 +1409,8 @@ struct sgcm_batch {
   int64_t* off = nullptr;
   int32_t* order = nullptr;
   int32_t* counter = nullptr;
+  double* y1 = nullptr;       // first Newton steps of the unit initial states, per (N, T) group
+  int64_t* y1off = nullptr;   // per BVP: its group's steps in y1, or -1
   size_t ws_doubles = 0;
   sgcm_schedule sched{1, 0};
   int64_t slots = 0;  // persistent workgroups (0: one workgroup per BVP)
@@ -1446,12 +1460,47 @@ extern "C" int sgcm_batch_create(const sgcm_problem* p, int64_t n_bvps, const in
     return src == nullptr || hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
   };
   const int32_t zero = 0;
-  const bool ok = up((void**)&b->N, hN.data(), n_bvps * sizeof(int32_t)) &&
-                  up((void**)&b->h, hh.data(), n_bvps * sizeof(double)) &&
-                  up((void**)&b->off, hoff.data(), n_bvps * sizeof(int64_t)) &&
-                  up((void**)&b->order, horder.data(), n_bvps * sizeof(int32_t)) &&
-                  up((void**)&b->counter, &zero, sizeof(int32_t));
+  // one set of first Newton steps per distinct (N, T), as for a solve plan
+  std::vector<std::pair<int32_t, double>> keys(n_bvps);
+  for (int64_t i = 0; i < n_bvps; ++i) keys[i] = {N[i], T[i]};
+  std::vector<std::pair<int32_t, double>> groups(keys);
+  std::sort(groups.begin(), groups.end());
+  groups.erase(std::unique(groups.begin(), groups.end()), groups.end());
+  std::vector<int64_t> goff(groups.size());
+  int64_t y1_total = 0;
+  for (size_t g = 0; g < groups.size(); ++g) {
+    goff[g] = y1_total;
+    y1_total += (int64_t)6 * 12 * (groups[g].first + 1);
+  }
+  std::vector<int64_t> hy1off(n_bvps);
+  for (int64_t i = 0; i < n_bvps; ++i)
+    hy1off[i] = goff[std::lower_bound(groups.begin(), groups.end(), keys[i]) - groups.begin()];
+  bool ok = up((void**)&b->N, hN.data(), n_bvps * sizeof(int32_t)) &&
+            up((void**)&b->h, hh.data(), n_bvps * sizeof(double)) &&
+            up((void**)&b->off, hoff.data(), n_bvps * sizeof(int64_t)) &&
+            up((void**)&b->order, horder.data(), n_bvps * sizeof(int32_t)) &&
+            up((void**)&b->counter, &zero, sizeof(int32_t)) &&
+            up((void**)&b->y1, nullptr, (size_t)y1_total * sizeof(double));
   if (!ok) {
+    (void)hipGetLastError();
+    sgcm_batch_destroy(b);
+    return SGCM_ENOMEM;
+  }
+  for (size_t g = 0; g < groups.size(); ++g) {
+    sgcm_problem qg = *p;
+    qg.N = groups[g].first;
+    qg.T = groups[g].second;
+    rc = first_steps(&qg, b->y1 + goff[g], nullptr);
+    if (rc == SGCM_EUNSUPPORTED) {  // that group's BVPs take their own first step
+      for (int64_t i = 0; i < n_bvps; ++i)
+        if (keys[i] == groups[g]) hy1off[i] = -1;
+    } else if (rc != SGCM_OK) {
+      sgcm_batch_destroy(b);
+      return rc;
+    }
+  }
+  if (!up((void**)&b->y1off, hy1off.data(), n_bvps * sizeof(int64_t))) {
+    (void)hipGetLastError();
     sgcm_batch_destroy(b);
     return SGCM_ENOMEM;
   }
@@ -1479,6 +1528,8 @@ extern "C" int sgcm_solve_bvps_batch(const sgcm_batch* b, const double* x0, doub
   B.off = b->off;
   B.order = b->order;
   B.counter = b->counter;
+  B.y1 = b->y1;
+  B.y1off = b->y1off;
   B.n = b->n;
   B.persistent = b->slots > 0;
   hipStream_t s = (hipStream_t)stream;
@@ -1509,5 +1560,7 @@ extern "C" void sgcm_batch_destroy(sgcm_batch* b) {
   (void)hipFree(b->off);
   (void)hipFree(b->order);
   (void)hipFree(b->counter);
+  (void)hipFree(b->y1);
+  (void)hipFree(b->y1off);
   delete b;
 }

@@ -98,19 +98,20 @@ def test_schedule_does_not_change_results():
 
 
 def test_batch_equals_uniform_solver():
-    # every BVP with N = 64, T = 20: the batch path and sgcm_solve_bvps run the
-    # same per-BVP code, so the results agree bitwise
+    # every BVP with N = 64, T = 20: the batch path and sgcm_solve_bvps_plan
+    # run the same per-BVP code (each first Newton step formed from the steps
+    # of the unit initial states of its (N, T)), so the results agree bitwise
     torch = _torch()
     x0 = W.uniform_in_box(50, seed=140)
     n = len(x0)
-    b = S.Batch(problem(), np.full(n, 64), np.full(n, 20.0), slots_per_cu=2)
-    g = gpu_batch(b, x0)
     p = problem()
     p.N, p.T = 64, 20.0
-    r = S.solve_bvps(p, torch.tensor(x0, device="cuda"))
+    r = S.solve_bvps(p, torch.tensor(x0, device="cuda"), plan=S.Plan(p))
     torch.cuda.synchronize()
-    for k in ("lambda0", "u0", "V", "status", "iters"):
-        assert np.array_equal(g[k], getattr(r, k).cpu().numpy()), k
+    for slots in (0, 2):
+        g = gpu_batch(S.Batch(problem(), np.full(n, 64), np.full(n, 20.0), slots_per_cu=slots), x0)
+        for k in ("lambda0", "u0", "V", "status", "iters"):
+            assert np.array_equal(g[k], getattr(r, k).cpu().numpy()), (slots, k)
 
 
 def test_underactuated_mixed_batch():

@@ -138,7 +138,12 @@ def test_fp32_batch_matches_fp32_solver():
     torch = _torch()
     x0 = W.uniform_in_box(30, seed=450)
     gp, _ = problems(N=64, T=20.0)
-    a = solve(gp, x0)
+    # a batch forms each first Newton step from its (N, T) group's steps, as
+    # the solver does with a plan
+    xd = torch.tensor(x0, device="cuda")
+    ra = S.solve_bvps(gp, xd, plan=S.Plan(gp))
+    torch.cuda.synchronize()
+    a = {k: getattr(ra, k).cpu().numpy() for k in ("lambda0", "u0", "V", "status", "iters")}
     b = S.Batch(gp, np.full(30, 64), np.full(30, 20.0), slots_per_cu=2)
     r = S.solve_bvps_batch(b, torch.tensor(x0, device="cuda"))
     torch.cuda.synchronize()
