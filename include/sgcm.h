@@ -162,9 +162,9 @@ int sgcm_plan_create(const sgcm_problem* p, void* stream, sgcm_plan** out);
 
 /* sgcm_solve_bvps for the plan's problem, each BVP's first Newton step formed
  * from the plan.  Arguments, workspace (sgcm_solve_bvps_workspace of the
- * plan's problem), outputs and errors as for sgcm_solve_bvps.  The plan is
- * only read: calls with one plan may run concurrently, with the plan's device
- * current. */
+ * plan's problem), outputs and errors as for sgcm_solve_bvps; SGCM_EINVAL
+ * also when the current device is not the plan's.  The plan is only read:
+ * calls with one plan may run concurrently. */
 int sgcm_solve_bvps_plan(const sgcm_plan* plan, int64_t n_bvps, const double* x0,
                          double* lambda0, double* u0, double* V, double* traj,
                          int32_t* status, int32_t* iters, void* workspace,

@@ -1299,6 +1299,7 @@ extern "C" int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const doub
 
 struct sgcm_plan {
   sgcm_problem p;
+  int dev;     // the device current at creation, which holds y1
   double* y1;  // device, 6 x (N + 1) x 12
 };
 
@@ -1347,9 +1348,12 @@ extern "C" int sgcm_plan_create(const sgcm_problem* p, void* stream, sgcm_plan**
   BvpArgs a;
   int rc = make_bvp_args(p, &a);
   if (rc != SGCM_OK) return rc;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return SGCM_EDEVICE;
   sgcm_plan* plan = new (std::nothrow) sgcm_plan();
   if (!plan) return SGCM_ENOMEM;
   plan->p = *p;
+  plan->dev = dev;
   plan->y1 = nullptr;
   const size_t y1_bytes = (size_t)6 * 12 * ((size_t)p->N + 1) * sizeof(double);
   if (hipMalloc((void**)&plan->y1, y1_bytes) != hipSuccess) {
@@ -1373,6 +1377,11 @@ extern "C" int sgcm_solve_bvps_plan(const sgcm_plan* plan, int64_t n_bvps, const
                                     double* u0, double* V, double* traj, int32_t* status, int32_t* iters,
                                     void* workspace, size_t ws_bytes, void* stream) {
   if (!plan) return SGCM_EINVAL;
+  if (n_bvps > 0) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return SGCM_EDEVICE;
+    if (dev != plan->dev) return SGCM_EINVAL;  // the plan's steps live on its own device
+  }
   return solve_bvps(&plan->p, plan->y1, n_bvps, x0, lambda0, u0, V, traj, status, iters, workspace, ws_bytes,
                     stream);
 }
