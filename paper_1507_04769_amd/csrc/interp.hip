@@ -68,6 +68,42 @@ __device__ __forceinline__ void level_basis(const GridArgs& g, F xi, F (&out)[kM
   }
 }
 
+__host__ __device__ constexpr int bit_length(int v) { return v == 0 ? 0 : 1 + bit_length(v >> 1); }
+
+// The basis value of point E of the nested 1-D sets at xi, alone: the
+// Lagrange polynomial on X^I (I the level of E) that is 1 at the point, with
+// the factors of level_basis in the same order (the prefix, then the suffix
+// from the right, then the scale), so the same bits as level_basis.
+template <int L, int E, typename F>
+__device__ __forceinline__ F basis_point(const GridArgs& g, F xi) {
+  if constexpr (E == 0) {
+    return F(1);
+  } else {
+    constexpr int I = E <= 2 ? 2 : bit_length(E - 1) + 1;
+    constexpr int n = (1 << (I - 1)) + 1;
+    constexpr int stride = 1 << (L + 1 - I);
+    constexpr int s = I == 2 ? 2 * (E - 1) : 2 * (E - ((1 << (I - 2)) + 1)) + 1;
+    F suf = F(1);
+#pragma unroll
+    for (int t = n - 1; t > s; --t) suf = suf * (xi - (F)g.X[t * stride]);
+    F pre = F(1);
+#pragma unroll
+    for (int t = 0; t < s; ++t) pre *= xi - (F)g.X[t * stride];
+    return pre * suf * (F)g.scale[E];
+  }
+}
+
+// basis_point for a run-time point e < N (a wave-uniform value)
+template <int L, int E, int N, typename F>
+__device__ __forceinline__ F basis_point_rt(const GridArgs& g, F xi, int e) {
+  if constexpr (E + 1 < N) {
+    if (e == E) return basis_point<L, E, F>(g, xi);
+    return basis_point_rt<L, E + 1, N, F>(g, xi, e);
+  } else {
+    return basis_point<L, E, F>(g, xi);
+  }
+}
+
 template <int L, typename F = double>
 __device__ __forceinline__ void basis_row_l(const GridArgs& g, F xi, F (&out)[kMaxPoints]) {
   out[0] = F(1);
@@ -264,9 +300,15 @@ __device__ __forceinline__ void uwalk_budget(int b, const F (&bv)[KU][P], const 
   }
 }
 
-template <int D, int L, int M, int KO, int KU, int K, typename F>
+// The outer (run-time) dimensions of the trie walk, their basis values in LDS
+// at lds_lane[(K * P + e) * 64].  With LOW0, dimension 0 keeps only its
+// values of the finest level there, after the other outer dimensions' (at
+// [((KO - 1) * P + e - upto(L - 1)) * 64]), and its lower-level values are
+// formed from xi0 when the walk reaches them (each once per query): half the
+// LDS per lane, so more waves per compute unit.
+template <int D, int L, int M, int KO, int KU, int K, bool LOW0, typename F>
 __device__ __forceinline__ void owalk(const GridArgs& g, const F* __restrict__ w, int bL, int64_t base, F p,
-                                      F (&acc)[M], const F (&bv)[KU][upto(L)], const F* lds_lane) {
+                                      F (&acc)[M], const F (&bv)[KU][upto(L)], const F* lds_lane, F xi0) {
   constexpr int P = upto(L);
   if constexpr (K == KO) {
     uwalk_budget<KU, P, M, L, F>(bL, bv, w + base * M, p, acc);
@@ -275,8 +317,16 @@ __device__ __forceinline__ void owalk(const GridArgs& g, const F* __restrict__ w
     const int32_t* offrow = g.off + ((D - K - 1) * (L + 1) + bL) * P;
     for (int e = 0; e < cE; ++e) {
       const int ex = g.excess[e];
-      const F pk = (K == 0) ? lds_lane[(K * P + e) * 64] : p * lds_lane[(K * P + e) * 64];
-      owalk<D, L, M, KO, KU, K + 1, F>(g, w, bL - ex, base + offrow[e], pk, acc, bv, lds_lane);
+      F pk;
+      if constexpr (K == 0 && LOW0) {
+        constexpr int PL = upto(L - 1);
+        pk = e < PL ? basis_point_rt<L, 0, PL, F>(g, xi0, e) : lds_lane[((KO - 1) * P + e - PL) * 64];
+      } else if constexpr (K == 0) {
+        pk = lds_lane[e * 64];
+      } else {
+        pk = p * lds_lane[((LOW0 ? K - 1 : K) * P + e) * 64];
+      }
+      owalk<D, L, M, KO, KU, K + 1, LOW0, F>(g, w, bL - ex, base + offrow[e], pk, acc, bv, lds_lane, xi0);
     }
   }
 }
@@ -308,7 +358,17 @@ __device__ __forceinline__ void fast_point(const GridArgs& g, const F* __restric
   }
 #pragma unroll
   for (int c = 0; c < M; ++c) acc[c] = F(0);
-  owalk<D, L, M, KO, KU, 0, F>(g, w, L, 0, F(1), acc, bv, lds_lane);
+  owalk<D, L, M, KO, KU, 0, false, F>(g, w, L, 0, F(1), acc, bv, lds_lane, F(0));
+}
+
+// Whether the evaluation kernel forms dimension 0's lower-level basis values
+// when reached instead of keeping them in LDS: in FP64 up to level 4, where the
+// LDS bounds the waves per compute unit (at level 4: 9 workgroups of 17 KB,
+// 12 of 13 KB), not at level 5 (bound by registers) or in FP32 (by registers
+// after the first halving).
+template <int L, typename F>
+__host__ __device__ constexpr bool eval_low0() {
+  return sizeof(F) == 8 && L <= 4;
 }
 
 // F = double: the FP64 path.  F = float: the FP32 path (surplus, states and
@@ -328,14 +388,21 @@ __global__ __launch_bounds__(64) void k_eval_fast(GridArgs g, const F* __restric
   const bool active = q < nq;
   F* lds_lane = lds + lane;
   F bv[KU][P];
+  F xi0 = F(0);
+  constexpr bool LOW0 = eval_low0<L, F>();
+  constexpr int PL = upto(L - 1);  // dimension 0's points below the finest level
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     const F xi = active ? (F)(((double)xq[q * D + k] - g.lo[k]) * g.inv_width[k]) : F(0.5);
     F row[kMaxPoints];
     basis_row_l<L, F>(g, xi, row);
-    if (k < KO) {
+    if (k == 0 && LOW0) {
+      xi0 = xi;
 #pragma unroll
-      for (int e = 0; e < P; ++e) lds_lane[(k * P + e) * 64] = row[e];
+      for (int e = PL; e < P; ++e) lds_lane[((KO - 1) * P + e - PL) * 64] = row[e];
+    } else if (k < KO) {
+#pragma unroll
+      for (int e = 0; e < P; ++e) lds_lane[((LOW0 ? k - 1 : k) * P + e) * 64] = row[e];
     } else {
 #pragma unroll
       for (int e = 0; e < P; ++e) bv[k - KO][e] = row[e];
@@ -344,7 +411,7 @@ __global__ __launch_bounds__(64) void k_eval_fast(GridArgs g, const F* __restric
   F acc[M];
 #pragma unroll
   for (int c = 0; c < M; ++c) acc[c] = F(0);
-  owalk<D, L, M, KO, KU, 0, F>(g, w, L, 0, F(1), acc, bv, lds_lane);
+  owalk<D, L, M, KO, KU, 0, LOW0, F>(g, w, L, 0, F(1), acc, bv, lds_lane, xi0);
   if (active) {
 #pragma unroll
     for (int c = 0; c < M; ++c) uq[q * M + c] = acc[c];
@@ -531,7 +598,10 @@ hipError_t level_chunk(int d, int mc, const GridArgs& a, size_t lds, const doubl
 template <int L, int M, typename F>
 hipError_t launch_fast(const GridArgs& a, int64_t nq, const F* w, const F* xq, F* uq, hipStream_t s) {
   constexpr int D = 6;
-  const size_t lds = (size_t)(D - 4) * upto(L) * 64 * sizeof(F);
+  // the outer dimensions' basis values; with LOW0, dimension 0's of the
+  // finest level only (see owalk)
+  const size_t lds = (eval_low0<L, F>() ? (size_t)((D - 5) * upto(L) + upto(L) - upto(L - 1))
+                                        : (size_t)(D - 4) * upto(L)) * 64 * sizeof(F);
   const int64_t blocks = (nq + 63) / 64;
   hipLaunchKernelGGL((k_eval_fast<D, L, M, F>), dim3((unsigned)blocks), dim3(64), lds, s, a, w, nq, xq, uq);
   return hipGetLastError();
