@@ -196,11 +196,12 @@ typedef struct sgcm_schedule {
 /* N, T: host arrays of n_bvps (>= 1) mesh sizes (1..65536) and horizons
  * (finite, > 0); sched: NULL for {order 1, slots_per_cu 0}.  Like a solve
  * plan, the batch forms each BVP's first Newton step from the first steps of
- * the six unit initial states of its (N, T): creation solves those (FP64, one
- * small launch per distinct (N, T) on the null stream, synchronized); a group
- * whose linearised step is singular or not finite solves its own first steps.
- * On success *out owns device memory of about 32 bytes per BVP and
- * 6 x (N+1) x 12 doubles per distinct (N, T), on the current device. */
+ * the six unit initial states of its (N, T), for every (N, T) shared by at
+ * least 8 BVPs: creation solves those (FP64, one small launch per such
+ * (N, T) on the null stream, synchronized); the other BVPs, and a group
+ * whose linearised step is singular or not finite, solve their own first
+ * steps.  On success *out owns device memory of about 32 bytes per BVP and
+ * 6 x (N+1) x 12 doubles per such (N, T), on the current device. */
 int sgcm_batch_create(const sgcm_problem* p, int64_t n_bvps, const int32_t* N, const double* T,
                       const sgcm_schedule* sched, sgcm_batch** out);
 

@@ -1409,6 +1409,10 @@ extern "C" int sgcm_characteristic_rhs(const sgcm_problem* p, int64_t n_points, 
 
 // ---- batches with per-BVP mesh size and horizon ----------------------------
 
+// The least number of BVPs of one (N, T) for which a batch solves the first
+// Newton steps of the unit initial states once (see sgcm_batch_create).
+constexpr int kMinGroupSteps = 8;
+
 struct sgcm_batch {
   BvpArgs args;  // the problem; args.N, args.h, args.per_bvp are unused
   int64_t n = 0;
@@ -1469,27 +1473,37 @@ extern "C" int sgcm_batch_create(const sgcm_problem* p, int64_t n_bvps, const in
     return src == nullptr || hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
   };
   const int32_t zero = 0;
-  // one set of first Newton steps per distinct (N, T), as for a solve plan
+  // one set of first Newton steps per distinct (N, T) of at least
+  // kMinGroupSteps BVPs, as for a solve plan (a smaller group would pay a
+  // launch and its steps' memory for a few BVPs; its BVPs solve their own)
   std::vector<std::pair<int32_t, double>> keys(n_bvps);
   for (int64_t i = 0; i < n_bvps; ++i) keys[i] = {N[i], T[i]};
-  std::vector<std::pair<int32_t, double>> groups(keys);
-  std::sort(groups.begin(), groups.end());
-  groups.erase(std::unique(groups.begin(), groups.end()), groups.end());
+  std::vector<std::pair<int32_t, double>> sorted_keys(keys);
+  std::sort(sorted_keys.begin(), sorted_keys.end());
+  std::vector<std::pair<int32_t, double>> groups;
+  for (size_t i = 0; i < sorted_keys.size();) {
+    size_t j = i;
+    while (j < sorted_keys.size() && sorted_keys[j] == sorted_keys[i]) ++j;
+    if (j - i >= (size_t)kMinGroupSteps) groups.push_back(sorted_keys[i]);
+    i = j;
+  }
   std::vector<int64_t> goff(groups.size());
   int64_t y1_total = 0;
   for (size_t g = 0; g < groups.size(); ++g) {
     goff[g] = y1_total;
     y1_total += (int64_t)6 * 12 * (groups[g].first + 1);
   }
-  std::vector<int64_t> hy1off(n_bvps);
-  for (int64_t i = 0; i < n_bvps; ++i)
-    hy1off[i] = goff[std::lower_bound(groups.begin(), groups.end(), keys[i]) - groups.begin()];
+  std::vector<int64_t> hy1off(n_bvps, -1);
+  for (int64_t i = 0; i < n_bvps; ++i) {
+    const auto it = std::lower_bound(groups.begin(), groups.end(), keys[i]);
+    if (it != groups.end() && *it == keys[i]) hy1off[i] = goff[it - groups.begin()];
+  }
   bool ok = up((void**)&b->N, hN.data(), n_bvps * sizeof(int32_t)) &&
             up((void**)&b->h, hh.data(), n_bvps * sizeof(double)) &&
             up((void**)&b->off, hoff.data(), n_bvps * sizeof(int64_t)) &&
             up((void**)&b->order, horder.data(), n_bvps * sizeof(int32_t)) &&
             up((void**)&b->counter, &zero, sizeof(int32_t)) &&
-            up((void**)&b->y1, nullptr, (size_t)y1_total * sizeof(double));
+            (y1_total == 0 || up((void**)&b->y1, nullptr, (size_t)y1_total * sizeof(double)));
   if (!ok) {
     (void)hipGetLastError();
     sgcm_batch_destroy(b);

@@ -181,3 +181,26 @@ def test_full_mixed_batch():
     o = oracle_groups(x0, N, T, idx=idx)
     sub = {k: v[idx] for k, v in r.items()}
     assert_parity(sub, o)
+
+
+def test_batch_with_and_without_group_first_steps():
+    # (N, T) groups of at least 8 BVPs take their first Newton steps from the
+    # group's unit-state steps, smaller groups solve their own: against the
+    # oracle, and bitwise against the solver with and without a plan
+    torch = _torch()
+    sizes = {(16, 2.0): 20, (8, 0.5): 5, (24, 6.0): 10, (4, 1.0): 3}
+    N = np.concatenate([np.full(c, k[0]) for k, c in sizes.items()]).astype(np.int32)
+    T = np.concatenate([np.full(c, k[1]) for k, c in sizes.items()])
+    perm = np.random.default_rng(150).permutation(len(N))
+    N, T = N[perm], T[perm]
+    x0 = W.uniform_in_box(len(N), seed=151)
+    g = gpu_batch(S.Batch(problem(), N, T), x0)
+    assert_parity(g, oracle_groups(x0, N, T))
+    for (NN, TT), c in sizes.items():
+        sel = np.nonzero((N == NN) & (T == TT))[0]
+        p = problem()
+        p.N, p.T = int(NN), float(TT)
+        r = S.solve_bvps(p, torch.tensor(x0[sel], device="cuda"), plan=S.Plan(p) if c >= 8 else None)
+        torch.cuda.synchronize()
+        for k in ("lambda0", "u0", "V", "status", "iters"):
+            assert np.array_equal(g[k][sel], getattr(r, k).cpu().numpy()), ((NN, TT), k)
