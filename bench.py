@@ -235,6 +235,32 @@ def precision_leg(dev, prob, grid, x0, lam64, u064, it64, surplus, eval_flops_q:
             "note": "errors against the FP64 GPU results, which match the FP64 oracle to ~1e-13"}
 
 
+def validation_leg(dev, prob, grid, u0, V, surplus, n_nodes_intervals: int, reps: int) -> dict:
+    """Monte Carlo total-error estimate of the interpolant (Sec. 4.3): 1280
+    uniform states, reference from 2x and 4x the nodes' intervals (Richardson
+    extrapolation), for the feedback u(0, x) (the step's interpolant) and the
+    value V(0, x) (an interpolant of the node values of V)."""
+    import torch
+    import paper_1507_04769_amd as S
+    from paper_1507_04769_amd import autotune as A
+    from paper_1507_04769_amd import validation as VA
+    from paper_1507_04769_amd import workloads as W
+    w_V = S.build_interpolant(grid, V.view(-1, 1).contiguous())
+    xs = torch.tensor(W.uniform_in_box(VA.N_SAMPLES, seed=VA.SAMPLE_SEED), device=dev)
+    n_ref = 2 * n_nodes_intervals
+    est = VA.Estimator(prob, n_ref)
+    r = est(grid, surplus, xs, w_V)
+    ms = A.time_ms(lambda: est(grid, surplus, xs, w_V), reps)
+    su, sV = r.stats_u.cpu().numpy(), r.stats_V.cpu().numpy()
+    st = r.status.cpu().numpy()
+    return {"samples": VA.N_SAMPLES, "seed": VA.SAMPLE_SEED, "node_intervals": n_nodes_intervals,
+            "reference_intervals": [n_ref, 2 * n_ref],
+            "reference_converged": [int(np.sum(st[0] == S.CONVERGED)), int(np.sum(st[1] == S.CONVERGED))],
+            "u_error": {"max": float(su[0]), "rms": float(su[1]), "reference_correction_max": float(su[2])},
+            "V_error": {"max": float(sV[0]), "rms": float(sV[1]), "reference_correction_max": float(sV[2])},
+            "ms": float(np.median(ms)), "samples_per_s": VA.N_SAMPLES / (float(np.median(ms)) / 1e3)}
+
+
 def serving_leg(n_requests: int, rate: float) -> dict:
     """The serving loop on a seeded Poisson stream of mixed requests: solves of
     1..512 states (meshes 64..512, three- or two-wheel model) and queries of
@@ -269,6 +295,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-batch leg")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32 leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-validation", action="store_true", help="skip the total-error estimate leg")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-rate", type=float, default=2000.0, help="requests per second")
     ap.add_argument("--no-plan-compare", action="store_true",
@@ -368,6 +395,9 @@ def main():
     precision = None
     if not args.no_precision and args.workload == "full":
         precision = precision_leg(dev, prob, grid, x0, lam, u0, iters, surplus, eval_flops_q, 5)
+    validation = None
+    if not args.no_validation and args.workload == "full":
+        validation = validation_leg(dev, prob, grid, u0, V, surplus, wl.n_intervals, 3)
     serving = None
     if not args.no_serving and args.workload == "full":
         serving = serving_leg(args.serving_requests, args.serving_rate)
@@ -416,6 +446,8 @@ def main():
         out["batched"] = batched
     if precision is not None:
         out["precision"] = precision
+    if validation is not None:
+        out["validation"] = validation
     if serving is not None:
         out["serving"] = serving
     if not args.no_cpu_baseline:

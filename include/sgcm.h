@@ -286,6 +286,28 @@ int sgcm_eval_feedback(const sgcm_grid* g, int32_t m, const double* surplus, int
 int sgcm_eval_feedback_f32(const sgcm_grid* g, int32_t m, const float* surplus, int64_t n_q,
                            const float* xq, float* uq, void* stream);
 
+/* ---- total-error estimate (Sec. 4.3) ---------------------------------------- */
+
+/* The error of the interpolant at n sample states against BVP solutions more
+ * accurate than those at the grid nodes (the Monte Carlo estimate of
+ * e_interp + e_bvp of Sec. 4.3).  The reference at a sample is the Richardson
+ * extrapolation of two trapezoidal solutions, on N and 2N intervals of the
+ * same horizon: ref = (4 fine - coarse) / 3, which removes the h^2 term of
+ * the trapezoid's error (its expansion has even powers of h only).
+ *   interp  device, n x m: the interpolant at the samples (sgcm_eval_feedback)
+ *   coarse  device, n x m: the same quantity solved on N intervals
+ *   fine    device, n x m: solved on 2N intervals
+ *   ref     device, n x m out: the extrapolated reference
+ *   err     device, n out: max over the m components of |interp - ref|
+ *   stats   device, 3 out: [0] max of err, [1] RMS of err, [2] max over
+ *           samples and components of |fine - ref| (the extrapolation's
+ *           correction to the fine solution, an estimate of its error)
+ * Row-major arrays; no output may overlap an input.  A NaN in any input
+ * propagates to its err entry and to stats[0..2].  n == 0 writes zeros to
+ * stats.  1 <= m <= 64.  One workgroup does the whole call, in stream order. */
+int sgcm_total_error(int64_t n, int32_t m, const double* interp, const double* coarse,
+                     const double* fine, double* ref, double* err, double* stats, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

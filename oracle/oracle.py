@@ -9,7 +9,8 @@ Every function follows a passage of Kang & Wilcox (see ``sgcm_oracle.cpp``):
 the CGL sparse grid (Sec. 3.2, eq. CGL), hierarchical surpluses (Sec. 3.3,
 eq. interpo), the combination formula (eq. interpolation2), and the
 characteristic BVP (Sec. 3.1, eq. hamchar / optuv) by trapezoidal collocation
-and Newton's method.
+and Newton's method; the Monte Carlo total-error estimate (Sec. 4.3) is plain
+numpy here (``total_error``).
 """
 from __future__ import annotations
 
@@ -269,3 +270,27 @@ def eval_comb(d: int, level: int, values, xq, lo=None, hi=None, nthreads: int | 
     lib().oracle_eval_comb(d, level, m, _dp(lo), _dp(hi), _dp(values), xq.shape[0], _dp(xq),
                            _dp(out), nthreads or default_threads())
     return out
+
+
+def total_error(interp, coarse, fine):
+    """Monte Carlo estimate of e_interp + e_bvp (Sec. 4.3): the interpolant's
+    values at sample states (``interp``, n x m) against a reference solution
+    that is more accurate than the solutions at the grid nodes.  The paper takes
+    the reference from an error-controlled solver; here it is the Richardson
+    extrapolation of trapezoidal solutions on N (``coarse``) and 2N (``fine``)
+    intervals of the same horizon, whose global errors are c h^2 + O(h^4):
+    ref = fine + (fine - coarse) / 3 = (4 fine - coarse) / 3.
+
+    Returns (ref, err, stats): err[i] = max_c |interp[i, c] - ref[i, c]|
+    (NaN if any term is NaN) and stats = [max err, RMS err,
+    max |fine - ref|], with zeros for an empty sample."""
+    interp, coarse, fine = (np.asarray(a, dtype=np.float64) for a in (interp, coarse, fine))
+    ref = (4.0 * fine - coarse) / 3.0
+    n = interp.shape[0]
+    if n == 0:
+        return ref, np.zeros(0), np.zeros(3)
+    err = np.max(np.abs(interp - ref), axis=1)
+    corr = np.max(np.abs(fine - ref))
+    stats = np.array([np.max(err), np.sqrt(np.mean(err * err)), corr])
+    return ref, err, stats
+

@@ -32,7 +32,7 @@ EXPORTS = ("sgcm_strerror", "sgcm_version", "sgcm_solve_bvps_workspace", "sgcm_s
            "sgcm_batch_create", "sgcm_batch_workspace", "sgcm_solve_bvps_batch",
            "sgcm_batch_destroy", "sgcm_grid_create", "sgcm_grid_size", "sgcm_grid_nodes",
            "sgcm_grid_keys", "sgcm_grid_destroy", "sgcm_build_interpolant", "sgcm_eval_feedback",
-           "sgcm_eval_feedback_f32")
+           "sgcm_eval_feedback_f32", "sgcm_total_error")
 
 
 class SgcmError(RuntimeError):
@@ -121,6 +121,7 @@ def lib() -> ctypes.CDLL:
         "sgcm_build_interpolant": (ctypes.c_int, [vp, i32, vp, vp, vp]),
         "sgcm_eval_feedback": (ctypes.c_int, [vp, i32, vp, i64, vp, vp, i32, vp]),
         "sgcm_eval_feedback_f32": (ctypes.c_int, [vp, i32, vp, i64, vp, vp, vp]),
+        "sgcm_total_error": (ctypes.c_int, [i64, i32, vp, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -365,6 +366,21 @@ def sgcm_eval_feedback(grid: Grid, surplus, xq, uq, precision: int = FP64, strea
     _check(rc, "sgcm_eval_feedback")
 
 
+def sgcm_total_error(interp, coarse, fine, ref, err, stats, stream=None):
+    import torch
+    if interp.dim() != 2:
+        raise ValueError("interp must be n x m")
+    n, m = interp.shape
+    for name, t in (("coarse", coarse), ("fine", fine)):
+        if tuple(t.shape) != (n, m):
+            raise ValueError("%s must be %d x %d" % (name, n, m))
+    f64 = torch.float64
+    rc = lib().sgcm_total_error(int(n), int(m), _ptr(interp, f64, "interp"), _ptr(coarse, f64, "coarse"),
+                                _ptr(fine, f64, "fine"), _ptr(ref, f64, "ref", n * m), _ptr(err, f64, "err", n),
+                                _ptr(stats, f64, "stats", 3), _stream(stream))
+    _check(rc, "sgcm_total_error")
+
+
 # ---------------------------------------------------------------------------
 # allocation helpers (outputs allocated with torch; compute in libsgcm)
 # ---------------------------------------------------------------------------
@@ -469,3 +485,17 @@ def eval_feedback(grid: Grid, surplus, xq, precision: int = FP64, stream=None):
     uq = torch.empty((xq.shape[0], surplus.shape[1]), dtype=torch.float64, device=xq.device)
     sgcm_eval_feedback(grid, surplus, xq, uq, precision, stream)
     return uq
+
+
+def total_error(interp, coarse, fine, stream=None):
+    """The total-error estimate of the interpolant at sample states: returns
+    (ref, err, stats) with ref = (4 fine - coarse) / 3 (n x m), err the
+    per-sample max error (n) and stats = [max err, RMS err, max |fine - ref|]
+    (device tensors)."""
+    import torch
+    n, m = interp.shape
+    ref = torch.empty((n, m), dtype=torch.float64, device=interp.device)
+    err = torch.empty((n,), dtype=torch.float64, device=interp.device)
+    stats = torch.empty((3,), dtype=torch.float64, device=interp.device)
+    sgcm_total_error(interp, coarse, fine, ref, err, stats, stream)
+    return ref, err, stats

@@ -171,3 +171,17 @@ def test_batch_create_validates_before_device_work():
     assert L.sgcm_batch_workspace(None, ctypes.byref(nb)) == S.SGCM_EINVAL
     assert L.sgcm_solve_bvps_batch(None, None, None, None, None, None, None, None, 0, None) == S.SGCM_EINVAL
     L.sgcm_batch_destroy(None)
+
+
+def test_total_error_argument_validation():
+    # every rejection happens before any device work; fake non-null pointers
+    # are never dereferenced on these paths
+    L = S.lib()
+    p = ctypes.c_void_p(256)
+    assert L.sgcm_total_error(-1, 3, p, p, p, p, p, p, None) == S.SGCM_EINVAL   # n < 0
+    assert L.sgcm_total_error(10, 0, p, p, p, p, p, p, None) == S.SGCM_EINVAL   # m < 1
+    assert L.sgcm_total_error(10, 65, p, p, p, p, p, p, None) == S.SGCM_EINVAL  # m > 64
+    assert L.sgcm_total_error(10, 3, p, p, p, p, p, None, None) == S.SGCM_EINVAL  # no stats
+    assert L.sgcm_total_error(10, 3, None, p, p, p, p, p, None) == S.SGCM_EINVAL  # no interp
+    assert L.sgcm_total_error(10, 3, p, p, p, p, None, p, None) == S.SGCM_EINVAL  # no err
+    assert L.sgcm_total_error(2**62, 3, p, p, p, p, p, p, None) == S.SGCM_EINVAL  # n * m overflows

@@ -1,0 +1,128 @@
+"""Monte Carlo total-error estimate (Sec. 4.3) on the GPU against the oracle.
+
+* sgcm_total_error against oracle.total_error on seeded inputs: the reference
+  and the per-sample errors bit for bit (the same correctly rounded
+  operations), the maxima exactly, the RMS to rounding; sizes from empty to
+  several passes of the 1024-thread workgroup with a ragged tail; NaN rows.
+* The whole estimate (reference solves on two meshes, interpolant evaluation,
+  comparison) against the oracle's pipeline on the same inputs: level-2 grid,
+  nodes on 64 intervals, 96 random states, reference meshes 64 and 128.
+* The estimate at full size (level-4 grid from 256-interval node solves, 1280
+  random states, reference meshes 512 and 1024): every reference solve
+  converges, the reference is far more accurate than the error it measures,
+  and a sample of states is checked against the oracle one by one.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1507_04769_amd as S
+from oracle import oracle as O
+from paper_1507_04769_amd import validation as VA
+from paper_1507_04769_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def gpu(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+@pytest.mark.parametrize("n,m", [(0, 3), (1, 1), (1000, 3), (1024, 1), (3001, 3), (5000, 2)])
+def test_total_error_kernel_matches_oracle(n, m):
+    g = np.random.default_rng(700 + n + m)
+    fine = g.standard_normal((n, m))
+    coarse = fine + 1e-3 * g.standard_normal((n, m))
+    interp = fine + 1e-2 * g.standard_normal((n, m))
+    ref, err, stats = S.total_error(gpu(interp), gpu(coarse), gpu(fine))
+    o_ref, o_err, o_stats = O.total_error(interp, coarse, fine)
+    assert np.array_equal(ref.cpu().numpy(), o_ref)
+    assert np.array_equal(err.cpu().numpy(), o_err)
+    st = stats.cpu().numpy()
+    assert st[0] == o_stats[0] and st[2] == o_stats[2]
+    assert abs(st[1] - o_stats[1]) <= 1e-14 * max(o_stats[1], 1e-300)
+
+
+def test_total_error_kernel_nan_rows():
+    g = np.random.default_rng(710)
+    n, m = 2500, 3
+    fine = g.standard_normal((n, m))
+    coarse = fine.copy()
+    interp = fine + 1e-2 * g.standard_normal((n, m))
+    interp[7, 1] = np.nan
+    coarse[2049, 0] = np.nan
+    ref, err, stats = S.total_error(gpu(interp), gpu(coarse), gpu(fine))
+    o_ref, o_err, o_stats = O.total_error(interp, coarse, fine)
+    e = err.cpu().numpy()
+    assert np.array_equal(np.isnan(e), np.isnan(o_err)) and np.isnan(e[7]) and np.isnan(e[2049])
+    assert np.array_equal(e[~np.isnan(e)], o_err[~np.isnan(o_err)])
+    assert np.all(np.isnan(stats.cpu().numpy()))
+
+
+def problem(N, T=20.0, m=3):
+    return S.Problem(m=m, J=W.J_DIAG, B=W.input_matrix(m), q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W, T=T, N=N,
+                     tol=W.TOL, max_iter=W.MAX_ITER)
+
+
+def oracle_problem(N, T=20.0, m=3):
+    return O.Problem(n=6, m=m, J=W.J_DIAG, B=W.input_matrix(m), q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W, T=T, N=N,
+                     tol=W.TOL, max_iter=W.MAX_ITER)
+
+
+def device_interpolants(level, N):
+    grid = S.Grid(6, level, W.BOX_LO, W.BOX_HI)
+    nodes = grid.nodes()
+    sol = S.solve_bvps(problem(N), gpu(nodes))
+    w_u = S.build_interpolant(grid, sol.u0)
+    w_V = S.build_interpolant(grid, sol.V.view(-1, 1).contiguous())
+    return grid, nodes, sol, w_u, w_V
+
+
+def test_estimate_matches_oracle_pipeline():
+    level, N, n_ref = 2, 64, 64
+    grid, nodes, sol, w_u, w_V = device_interpolants(level, N)
+    xs = W.uniform_in_box(96, seed=711)
+    est = VA.Estimator(problem(N), n_ref)
+    r = est(grid, w_u, gpu(xs), w_V)
+    # the oracle's pipeline on the same inputs
+    o_sol = O.solve_bvps(oracle_problem(N), nodes)
+    o_wu = O.build_surplus(6, level, o_sol.u0)
+    o_wV = O.build_surplus(6, level, o_sol.V[:, None])
+    o_uint = O.eval_hier(6, level, o_wu, xs, W.BOX_LO, W.BOX_HI)
+    o_Vint = O.eval_hier(6, level, o_wV, xs, W.BOX_LO, W.BOX_HI)
+    oc = O.solve_bvps(oracle_problem(n_ref), xs)
+    of = O.solve_bvps(oracle_problem(2 * n_ref), xs)
+    assert np.array_equal(r.status.cpu().numpy(), np.stack([oc.status, of.status]))
+    assert np.array_equal(r.iters.cpu().numpy(), np.stack([oc.iters, of.iters]))
+    for (ref, err, stats), (intp, c, f) in (((r.ref_u, r.err_u, r.stats_u), (o_uint, oc.u0, of.u0)),
+                                            ((r.ref_V, r.err_V, r.stats_V), (o_Vint, oc.V[:, None], of.V[:, None]))):
+        o_ref, o_err, o_stats = O.total_error(intp, c, f)
+        scale = np.abs(o_ref).max()
+        assert np.max(np.abs(ref.cpu().numpy() - o_ref)) <= 1e-8 * scale
+        # errors are differences of values that agree to 1e-8 of their scale
+        assert np.max(np.abs(err.cpu().numpy() - o_err)) <= 2e-8 * scale
+        assert np.max(np.abs(stats.cpu().numpy() - o_stats)) <= 2e-8 * scale
+
+
+def test_estimate_at_full_size_with_sampled_oracle_checks():
+    level, N, n_ref = W.FULL.level, W.FULL.n_intervals, 2 * W.FULL.n_intervals
+    grid, nodes, sol, w_u, w_V = device_interpolants(level, N)
+    xs = W.uniform_in_box(VA.N_SAMPLES, seed=VA.SAMPLE_SEED)
+    r = VA.Estimator(problem(N), n_ref)(grid, w_u, gpu(xs), w_V)
+    assert np.all(r.status.cpu().numpy() == S.CONVERGED)
+    su, sV = r.stats_u.cpu().numpy(), r.stats_V.cpu().numpy()
+    assert np.all(np.isfinite(su)) and np.all(np.isfinite(sV))
+    # the reference meshes have 2 and 4 times the nodes' intervals: the
+    # correction to the fine solution is well below the error being measured
+    assert su[2] < su[0] / 10 and sV[2] < sV[0] / 10
+    # sampled states, one by one through the oracle: reference solves and the
+    # interpolant of the device surplus
+    pick = W.sample_indices(VA.N_SAMPLES, 4, seed=713)
+    oc = O.solve_bvps(oracle_problem(n_ref), xs[pick])
+    of = O.solve_bvps(oracle_problem(2 * n_ref), xs[pick])
+    o_uint = O.eval_hier(6, level, w_u.cpu().numpy(), xs[pick], W.BOX_LO, W.BOX_HI)
+    o_ref, o_err, _ = O.total_error(o_uint, oc.u0, of.u0)
+    scale = np.abs(o_ref).max()
+    assert np.max(np.abs(r.ref_u.cpu().numpy()[pick] - o_ref)) <= 1e-8 * scale
+    assert np.max(np.abs(r.err_u.cpu().numpy()[pick] - o_err)) <= 2e-8 * scale
