@@ -1105,10 +1105,13 @@ struct BatchArgs {
   int persistent;
 };
 
+// The next position of the batch order for this workgroup, taken by lane 0
+// with a device-scope atomic and made uniform in a scalar register, so that
+// it costs no vector register across the Newton solve.
 __device__ __forceinline__ int64_t next_position(int32_t* counter) {
   int v = 0;
   if (threadIdx.x == 0) v = atomicAdd(counter, 1);
-  return __shfl(v, 0);
+  return __builtin_amdgcn_readfirstlane(v);
 }
 
 template <typename T>
