@@ -126,3 +126,19 @@ def test_estimate_at_full_size_with_sampled_oracle_checks():
     scale = np.abs(o_ref).max()
     assert np.max(np.abs(r.ref_u.cpu().numpy()[pick] - o_ref)) <= 1e-8 * scale
     assert np.max(np.abs(r.err_u.cpu().numpy()[pick] - o_err)) <= 2e-8 * scale
+
+
+@pytest.mark.parametrize("n", [0, 1])
+def test_estimate_empty_and_single_sample(n):
+    level, N = 2, 64
+    grid, nodes, sol, w_u, w_V = device_interpolants(level, N)
+    xs = W.uniform_in_box(max(n, 1), seed=714)[:n]
+    r = VA.Estimator(problem(N), 32)(grid, w_u, gpu(xs).reshape(n, 6), w_V)
+    assert r.err_u.shape == (n,) and r.ref_u.shape == (n, 3) and r.err_V.shape == (n,)
+    su = r.stats_u.cpu().numpy()
+    if n == 0:
+        assert np.array_equal(su, np.zeros(3)) and np.array_equal(r.stats_V.cpu().numpy(), np.zeros(3))
+    else:
+        # one sample: the max and the RMS are its error
+        e = r.err_u.cpu().numpy()[0]
+        assert su[0] == e and abs(su[1] - e) <= 1e-15 * e
