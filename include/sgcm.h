@@ -8,7 +8,9 @@
  * costate equations, Sec. 3.1, eq. hamchar), builds the hierarchical-surplus
  * polynomial interpolant of the result on the Clenshaw-Curtis ("CGL") sparse
  * grid (Sec. 3.2 eq. CGL, Sec. 3.3 eq. interpo), and evaluates the feedback
- * law at arbitrary states (Sec. 3.3, Steps I-III and the on-line step).
+ * law at arbitrary states (Sec. 3.3, Steps I-III and the on-line step).  It
+ * also estimates the interpolant's total error at sample states against more
+ * accurate BVP solutions (Sec. 4.3).
  *
  * Conventions for every function:
  *   - All functions are extern "C", never throw, and return an int status
@@ -18,8 +20,8 @@
  *     returns SGCM_EDEVICE.
  *   - Pointers documented as "device" must point to device memory of the
  *     current HIP device (or be NULL where allowed).  The caller owns every
- *     device buffer and the stream; the library owns only sgcm_grid and
- *     sgcm_batch objects.
+ *     device buffer and the stream; the library owns only sgcm_grid,
+ *     sgcm_plan and sgcm_batch objects.
  *   - Calls on a stream are stream-ordered and do not synchronise the host.
  *     "stream" is a hipStream_t passed as void*; NULL means the null stream.
  *   - Arrays are row-major and densely packed unless stated otherwise.
