@@ -29,7 +29,7 @@ def gpu(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
 
 
-@pytest.mark.parametrize("n,m", [(0, 3), (1, 1), (1000, 3), (1024, 1), (3001, 3), (5000, 2)])
+@pytest.mark.parametrize("n,m", [(0, 3), (1, 1), (1000, 3), (1024, 1), (3001, 3), (5000, 2), (700, 64)])
 def test_total_error_kernel_matches_oracle(n, m):
     g = np.random.default_rng(700 + n + m)
     fine = g.standard_normal((n, m))
