@@ -304,7 +304,7 @@ def main():
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the per-node BVPs shard with no communication; see the design notes).", file=sys.stderr)
         sys.exit(2)
 

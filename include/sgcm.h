@@ -42,7 +42,7 @@ typedef enum {
   SGCM_EINVAL = -1,       /* invalid argument (nothing was queued)            */
   SGCM_ENOMEM = -2,       /* host or device allocation failed                 */
   SGCM_EDEVICE = -3,      /* HIP launch or runtime failure                    */
-  SGCM_EUNSUPPORTED = -4  /* valid request outside what this build supports   */
+  SGCM_EUNSUPPORTED = -4  /* valid request outside what the library supports */
 } sgcm_err;
 
 /* Per-BVP outcome written to status[] by sgcm_solve_bvps.  A per-BVP failure

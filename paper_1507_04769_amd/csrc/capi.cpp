@@ -12,7 +12,7 @@ extern "C" const char* sgcm_strerror(int code) {
     case SGCM_EINVAL: return "invalid argument";
     case SGCM_ENOMEM: return "out of memory";
     case SGCM_EDEVICE: return "HIP device or launch failure";
-    case SGCM_EUNSUPPORTED: return "not supported by this build";
+    case SGCM_EUNSUPPORTED: return "not supported by this library";
     default: return "unknown status";
   }
 }
