@@ -44,7 +44,8 @@ class _Problem(ctypes.Structure):
                 ("J", ctypes.c_double * 3), ("B", ctypes.c_double * 9),
                 ("q_w", ctypes.c_double), ("r_w", ctypes.c_double), ("p_w", ctypes.c_double),
                 ("T", ctypes.c_double), ("N", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("max_iter", ctypes.c_int32)]
+                ("max_iter", ctypes.c_int32), ("max_halvings", ctypes.c_int32),
+                ("continuation", ctypes.c_int32)]
 
 
 @dataclass
@@ -62,6 +63,8 @@ class Problem:
     N: int = 64
     tol: float = 1e-10
     max_iter: int = 20
+    max_halvings: int = 10   # backtracking cap of each Newton step (0: full steps)
+    continuation: int = 0    # two controls: stages of the virtual-torque continuation
 
     def c(self) -> _Problem:
         p = _Problem()
@@ -76,6 +79,7 @@ class Problem:
             p.B[i] = B[i]
         p.q_w, p.r_w, p.p_w = self.q_w, self.r_w, self.p_w
         p.T, p.N, p.tol, p.max_iter = self.T, self.N, self.tol, self.max_iter
+        p.max_halvings, p.continuation = self.max_halvings, self.continuation
         return p
 
 

@@ -30,7 +30,10 @@
 // short version is: trapezoid (the two-point Lobatto IIIA member) on a uniform
 // mesh; Newton from Y = 0 whose first step (the solve of the problem
 // linearised about the origin) is not counted; stop when the max-norm of the
-// collocation residual is <= tol, tested before every update; full steps.
+// collocation residual is <= tol, tested before every update; each counted
+// step damped by backtracking on that max-norm (the full step whenever it
+// decreases the norm enough); for two controls, optionally a continuation
+// from the three-control problem (see solve_bvp).
 //
 // Parity status: every exported function is pinned by the CPU test-suite
 // (printed grids, polynomial exactness, the discrete and continuous Riccati
@@ -109,6 +112,8 @@ typedef struct {
   int32_t N;         // uniform mesh intervals
   double tol;        // Newton stopping tolerance on max|F|
   int32_t max_iter;  // Newton iterations after the first (linearised) step
+  int32_t max_halvings;  // backtracking cap H of each Newton step (0: full steps)
+  int32_t continuation;  // K > 0 (two controls only): continuation stages, see solve_bvp
 } oracle_problem;
 
 }  // extern "C"
@@ -483,17 +488,32 @@ double max_abs(const double* a, size_t n) {
   return m;
 }
 
-// Newton's method on F(Y) = 0 from Y = 0 (see the file header for the rule).
-// Y must hold dim doubles; returns the status and writes the iteration count.
-int newton_solve(const oracle_problem& p, const double* xbar, double* Y, int* iters_out,
+// Newton's method on F(Y) = 0 (see the file header for the rule).  Y must
+// hold dim doubles; returns the status and writes the iteration count.
+//
+// Globalisation (the paper fixes none; Sec. 2 Assumption 1 only asks for a
+// solution of the characteristic BVP): each counted Newton step d is damped by
+// backtracking on the max-norm of the residual.  The trial points are
+// Y + t d for t = 1, 1/2, ..., 2^-H (H = max_halvings); the first whose
+// residual is finite and satisfies the sufficient-decrease test
+//   max|F(Y + t d)| <= (1 - sigma t) max|F(Y)|,  sigma = 1e-4,
+// is taken; if none does, the last trial (t = 2^-H) is taken.  So the full
+// step is taken whenever it passes the test, and H = 0 is plain Newton.  The
+// first step from Y = 0 (the solve of the linearised problem, the initial
+// guess) is always taken in full.
+constexpr double kArmijoSigma = 1e-4;
+
+// Newton's iteration on F(Y) = 0.  from_zero: start at Y = 0 and take the
+// first (uncounted) step in full; else start at the given Y with its test.
+int newton_solve(const oracle_problem& p, const double* xbar, double* Y, bool from_zero, int* iters_out,
                  double* fnorm_out) {
   Collocation C(p);
   const int dim = C.dim, n = p.n;
   const int kl = 3 * n - 1, ku = 3 * n - 1;
   Band A(dim, kl, ku);
-  std::vector<double> F(dim), d(dim);
-  std::fill(Y, Y + dim, 0.0);
-  auto newton_step = [&]() -> bool {
+  std::vector<double> F(dim), d(dim), Yt(dim), Ft(dim);
+  // the Newton step d = -F'(Y)^{-1} F(Y); false on an exactly zero pivot
+  auto newton_direction = [&]() -> bool {
     C.eval_points(Y, true);
     C.residual(xbar, Y, F.data());
     A.clear();
@@ -501,12 +521,15 @@ int newton_solve(const oracle_problem& p, const double* xbar, double* Y, int* it
     if (!A.factor()) return false;
     for (int i = 0; i < dim; ++i) d[i] = -F[i];
     A.solve(d.data());
-    for (int i = 0; i < dim; ++i) Y[i] += d[i];
     return true;
   };
   *fnorm_out = NAN;
-  // the first step: the solve of the problem linearised about Y = 0
-  if (!newton_step()) { *iters_out = 0; return ORC_SINGULAR; }
+  if (from_zero) {
+    // the first step: the solve of the problem linearised about Y = 0
+    std::fill(Y, Y + dim, 0.0);
+    if (!newton_direction()) { *iters_out = 0; return ORC_SINGULAR; }
+    for (int i = 0; i < dim; ++i) Y[i] += d[i];
+  }
   for (int it = 0;; ++it) {
     C.eval_points(Y, false);
     C.residual(xbar, Y, F.data());
@@ -516,8 +539,53 @@ int newton_solve(const oracle_problem& p, const double* xbar, double* Y, int* it
     *fnorm_out = fn;
     if (fn <= p.tol) return ORC_CONVERGED;
     if (it == p.max_iter) return ORC_MAXITER;
-    if (!newton_step()) return ORC_SINGULAR;
+    if (!newton_direction()) return ORC_SINGULAR;
+    double t = 1.0;
+    for (int j = 0;; ++j) {
+      for (int i = 0; i < dim; ++i) Yt[i] = Y[i] + t * d[i];
+      if (j == p.max_halvings) break;  // the last trial is taken
+      C.eval_points(Yt.data(), false);
+      C.residual(xbar, Yt.data(), Ft.data());
+      if (all_finite(Ft.data(), dim) && max_abs(Ft.data(), dim) <= (1.0 - kArmijoSigma * t) * fn) break;
+      t *= 0.5;
+    }
+    std::copy(Yt.begin(), Yt.end(), Y);
   }
+}
+
+// The characteristic BVP from xbar.  With two controls and continuation K > 0
+// the linearisation about the origin loses a controllable direction (the
+// torques span a plane), the linearised first step drifts along it, and
+// Newton's iteration from there fails over most of the box.  The solution is
+// then reached by continuation in the authority of a third, virtual torque
+// along b3 = B_1 x B_2 / |B_1 x B_2|, the normal of that plane: stage k = 0..K-1
+// solves the three-control problem with B_k = [B_1 B_2 s_k b3],
+// s_k = 1 - k / K, the first from Y = 0 as above and each later one (and the
+// final stage K, the two-control problem itself) from the solution of the one
+// before.  The status is that of the last stage solved (a failed stage ends
+// the continuation) and the iteration count is the total over the stages.
+int solve_bvp(const oracle_problem& p, const double* xbar, double* Y, int* iters_out, double* fnorm_out) {
+  if (p.continuation <= 0 || p.m != 2) return newton_solve(p, xbar, Y, true, iters_out, fnorm_out);
+  const double* B1 = p.B;
+  const double* B2 = p.B + 3;
+  double b3[3] = {B1[1] * B2[2] - B1[2] * B2[1], B1[2] * B2[0] - B1[0] * B2[2], B1[0] * B2[1] - B1[1] * B2[0]};
+  const double nb = std::sqrt(b3[0] * b3[0] + b3[1] * b3[1] + b3[2] * b3[2]);
+  for (double& v : b3) v /= nb;
+  int total = 0, st = ORC_CONVERGED;
+  for (int k = 0; k <= p.continuation; ++k) {
+    oracle_problem q = p;
+    if (k < p.continuation) {
+      const double s = 1.0 - (double)k / p.continuation;
+      q.m = 3;
+      for (int i = 0; i < 3; ++i) q.B[6 + i] = s * b3[i];
+    }
+    int it = 0;
+    st = newton_solve(q, xbar, Y, k == 0, &it, fnorm_out);
+    total += it;
+    if (st != ORC_CONVERGED) break;
+  }
+  *iters_out = total;
+  return st;
 }
 
 // ---------------------------------------------------------------------------
@@ -708,7 +776,7 @@ void oracle_solve_bvps(const oracle_problem* p, int64_t nb, const double* x0, do
     std::vector<double> Y(dim);
     int it = 0;
     double fn = 0.0;
-    int st = newton_solve(*p, x0 + b * n, Y.data(), &it, &fn);
+    int st = solve_bvp(*p, x0 + b * n, Y.data(), &it, &fn);
     if (status) status[b] = st;
     if (iters) iters[b] = it;
     if (fnorm) fnorm[b] = fn;

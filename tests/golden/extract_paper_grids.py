@@ -7,7 +7,7 @@ pgfplots table.  The data are plotted on [-1, 1]^2 although the caption says
 [0, 1]^2; the fixtures keep the printed numbers and the tests map them with
 xi = (x + 1) / 2.
 
-Usage: python tests/golden/extract_paper_grids.py /root/reference/PAPER.md
+Usage: python tests/golden/extract_paper_grids.py <LaTeX source of the paper>
 """
 import os
 import re
@@ -32,4 +32,6 @@ def main(path):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "/root/reference/PAPER.md")
+    if len(sys.argv) != 2:
+        sys.exit("usage: extract_paper_grids.py <LaTeX source of the paper>")
+    main(sys.argv[1])

@@ -291,10 +291,11 @@ def test_example3_closed_form_second_order(T):
 # nonlinear rigid body: same discrete solution by other algorithms
 # ---------------------------------------------------------------------------
 
-def shooting(kind, m, x0, N, T):
-    """Single shooting: unknown lambda(0); each mesh step solves the implicit
-    trapezoid equation with Newton on the sympy right-hand side; a dense
-    Newton (finite-difference Jacobian) drives lambda_N - p_w x_N to zero."""
+def shooting(kind, m, x0, N, T, l0=None):
+    """Single shooting: unknown lambda(0) (from l0, default 0); each mesh step
+    solves the implicit trapezoid equation with Newton on the sympy
+    right-hand side; a dense Newton (finite-difference Jacobian) drives
+    lambda_N - p_w x_N to zero."""
     n = 6
     h = T / N
 
@@ -319,7 +320,7 @@ def shooting(kind, m, x0, N, T):
         ys = march(l0)
         return ys[-1, n:] - W.P_W * ys[-1, :n]
 
-    l0 = np.zeros(n)
+    l0 = np.zeros(n) if l0 is None else np.array(l0, dtype=np.float64)
     for _ in range(30):
         r = mismatch(l0)
         if np.max(np.abs(r)) < 1e-13:
