@@ -4,10 +4,13 @@
 One step = the whole hot path on one batch of synthetic input: solve the
 characteristic BVP at every node of the level-4 Smolyak CGL grid of the 6-D
 rigid-body attitude problem (1457 nodes, 256 trapezoidal intervals, Newton
-to max|F| <= 1e-10), build the hierarchical-surplus interpolant of u(0), and
-evaluate the feedback at 1e6 seeded uniform states.  Inputs are resident in
-HBM before the timed region; W untimed warm-up steps, then exactly K timed
-steps bracketed by synchronisation.  Prints one JSON line.
+from the linearised guess to max|F| <= 1e-10), build the hierarchical-surplus
+interpolant of u(0), and evaluate the feedback at 1e6 seeded uniform states.
+The headline step is one-shot (each BVP solves its own first Newton step);
+the same step with a per-problem solve plan made once is reported beside it.
+Inputs are resident in HBM before the timed region; W untimed warm-up steps,
+then exactly K timed steps bracketed by synchronisation.  Prints one JSON
+line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload full|small]
 """
@@ -28,17 +31,31 @@ METRIC = "converged 6-D BVPs/s at tol 1e-10 + feedback evals/s; p50/p99 latency"
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector (and matrix) peak
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak
 
-# Algorithmic FP64 work of the Newton solve (the counts are derived in the
-# design notes):
+# Algorithmic FP64 work of the Newton solve, the count the roofline uses:
+# 6.5 kflop per mesh interval and Newton linear solve (the residual and
+# Jacobian blocks of the interval, the structured elimination of its 12 x 12
+# blocks and the back-substitution).  A BVP that takes iters counted
+# iterations does iters + 1 linear solves (the first one from Y = 0), or iters
+# with a solve plan (newton_flops).
+FLOPS_PER_INTERVAL_STEP = 6500.0
+
+
+def newton_flops(N, iters: np.ndarray, plan: bool = False) -> float:
+    """6.5 kflop x N x the linear solves of every BVP of a launch."""
+    it = iters.astype(np.float64) + (0.0 if plan else 1.0)
+    N = np.asarray(N, dtype=np.float64) + 0 * it
+    return float(FLOPS_PER_INTERVAL_STEP * np.sum(N * it))
+
+
+# The library's own finer count, kept as a secondary figure:
 #   per interval and linear solve: assembly of the 12 x 12 system and its
 #   7 right-hand sides (S P_k, A_k^T P_k, S c_k, A_k^T c_k and the block sums:
 #   1098), the solve itself counted as LU plus substitution (2/3 n^3 + 2 n^2 k
 #   = 1152 + 2016 for n = 12, k = 7) and the forward pass with the update (156);
 #   per mesh point and evaluation: Phi, A = df/dx and W (172) and the interval
 #   residual (48).  Transcendentals (two sincos per point) are not counted.
-#   The first (linearised) Newton step is formed from a solve plan, so a BVP
-#   that takes iters Newton iterations does iters linear solves and iters + 1
-#   evaluations (newton_flops_plan).
+#   With a solve plan a BVP that takes iters Newton iterations does iters
+#   linear solves and iters + 1 evaluations (newton_flops_plan).
 FLOPS_ASSEMBLY = 1098
 FLOPS_PER_INTERVAL_SOLVE = FLOPS_ASSEMBLY + 1152 + 2016 + 156
 FLOPS_PER_POINT_EVAL = 172 + 48
@@ -88,10 +105,22 @@ def alu_roofline(kernel: str, flops: float, ms: float, peak: float) -> dict:
 
 
 def eval_flops_per_query(grid_keys: np.ndarray, level: int, m: int) -> float:
-    """Algorithmic flops of one feedback evaluation: one FMA per node and
-    output (2 m M), the partial products of the node trie, and the 1-D basis
-    tables (prefix/suffix products, 3 flops per point of each X^i, plus one
-    scale per new point) in every dimension."""
+    """Algorithmic flops of one feedback evaluation, the count the roofline
+    uses: one multiply-add per node and output (2 m M), one product per
+    non-trivial dimension of each node beyond the first (sum over nodes of
+    max(#{k: i_k > 1} - 1, 0)), and the 1-D basis tables, 5 flops per point of
+    each X^i, i = 2..level + 1, in every dimension (12,242 at level 4, m = 3)."""
+    M, d = grid_keys.shape
+    nontrivial = np.count_nonzero(grid_keys, axis=1)
+    basis = sum(5 * (2 ** (i - 1) + 1) for i in range(2, level + 2))
+    return float(2 * m * M + np.sum(np.maximum(nontrivial - 1, 0)) + d * basis)
+
+
+def eval_flops_per_query_walk(grid_keys: np.ndarray, level: int, m: int) -> float:
+    """The evaluation kernel's own count (secondary): one FMA per node and
+    output (2 m M), the partial products of the node trie, 2 m per inner trie
+    node, and the 1-D basis tables (prefix/suffix products, 3 flops per point
+    of each X^i, plus one scale per new point) in every dimension."""
     M, d = grid_keys.shape
     prefixes = 0
     for k in range(1, d - 1):
@@ -104,28 +133,60 @@ def eval_flops_per_query(grid_keys: np.ndarray, level: int, m: int) -> float:
     return 2.0 * m * M + prefixes + 2.0 * m * inner + d * basis
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(args, nodes: np.ndarray, xq: np.ndarray) -> dict:
-    """The FP64 CPU oracle as it stands, on the host cores, on a bounded
-    sample of the same workload: all BVPs of the grid, and a slice of the
-    queries."""
+    """The FP64 CPU oracle as it stands, on a bounded sample of the same
+    workload: on all host threads (median of 3 runs: every BVP of the grid,
+    and a slice of the queries) and on one thread (median of 3 runs on a
+    seeded sample of BVPs and queries)."""
     from oracle import oracle as O
     from paper_1507_04769_amd import workloads as W
     wl = W.FULL if args.workload == "full" else W.SMALL
     threads = O.default_threads()
-    op = O.Problem(N=wl.n_intervals, T=wl.horizon)
-    t0 = time.perf_counter()
-    r = O.solve_bvps(op, nodes, nthreads=threads)
-    t_solve = time.perf_counter() - t0
+    op = O.Problem(N=wl.n_intervals, T=wl.horizon, max_halvings=W.MAX_HALVINGS)
+
+    def timed(fn):
+        t = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            r = fn()
+            t.append(time.perf_counter() - t0)
+        return float(np.median(t)), r
+
+    t_solve, r = timed(lambda: O.solve_bvps(op, nodes, nthreads=threads))
     conv = int(np.sum(r.status == O.CONVERGED))
     nq = min(len(xq), args.cpu_queries)
     w = O.build_surplus(6, wl.level, r.u0, nthreads=threads)
-    t0 = time.perf_counter()
-    O.eval_hier(6, wl.level, w, xq[:nq], W.BOX_LO, W.BOX_HI, nthreads=threads)
-    t_eval = time.perf_counter() - t0
+    t_eval, _ = timed(lambda: O.eval_hier(6, wl.level, w, xq[:nq], W.BOX_LO, W.BOX_HI, nthreads=threads))
+    pick = W.sample_indices(len(nodes), min(len(nodes), 100), seed=31)
+    t1_solve, r1 = timed(lambda: O.solve_bvps(op, nodes[pick], nthreads=1))
+    nq1 = min(nq, 2000)
+    t1_eval, _ = timed(lambda: O.eval_hier(6, wl.level, w, xq[:nq1], W.BOX_LO, W.BOX_HI, nthreads=1))
     return {"value": conv / t_solve, "unit": "BVPs/s", "cores": threads, "kind": "oracle",
-            "sample": "all %d BVPs of the grid (N=%d) and %d of the %d queries" % (len(nodes), wl.n_intervals,
-                                                                                nq, len(xq)),
-            "feedback_evals_per_s": nq / t_eval, "solve_s": t_solve, "eval_s": t_eval}
+            "sample": "all %d BVPs of the grid (N=%d) and %d of the %d queries, median of 3 runs" % (
+                len(nodes), wl.n_intervals, nq, len(xq)),
+            "cpu_model": cpu_model(), "feedback_evals_per_s": nq / t_eval, "solve_s": t_solve, "eval_s": t_eval,
+            "one_core": {"bvps_per_s": int(np.sum(r1.status == O.CONVERGED)) / t1_solve,
+                         "feedback_evals_per_s": nq1 / t1_eval, "cores": 1,
+                         "sample": "%d seeded BVPs of the grid and %d queries, median of 3 runs" % (len(pick), nq1)}}
 
 
 def batched_leg(dev, reps: int) -> dict:
@@ -162,7 +223,7 @@ def batched_leg(dev, reps: int) -> dict:
     run, ngroups = A.unbatched_runner(problem, x0, N, T)
     ums = A.time_ms(run, reps)
     bms, ubms = float(np.median(ms)), float(np.median(ums))
-    flops = newton_flops_plan(N, it.cpu().numpy())  # first steps from the batch's per-(N, T) steps
+    flops = newton_flops(N, it.cpu().numpy(), plan=True)  # first steps from the batch's per-(N, T) steps
     return {"workload": "mixed batch: " + A.W.BATCH.name, "n_bvps": n, "converged": converged,
             "roofline": alu_roofline("k_newton_batch_grid<double>" if slots == 0 else "k_newton_batch<double>",
                                      flops, bms, PEAK_FP64_TFLOPS),
@@ -173,15 +234,36 @@ def batched_leg(dev, reps: int) -> dict:
             "speedup_vs_unbatched": ubms / bms}
 
 
+def rel_rows(a, b):
+    """Per-row relative error max|a - b| / max(max|b|, 1e-8)."""
+    a = np.asarray(a).reshape(len(a), -1)
+    b = np.asarray(b).reshape(len(b), -1)
+    return np.max(np.abs(a - b), axis=1) / np.maximum(np.max(np.abs(b), axis=1), 1e-8)
+
+
+def err_stats(e) -> dict:
+    e = np.asarray(e)
+    return {"max": float(e.max()), "rms": float(np.sqrt(np.mean(e ** 2)))} if e.size else {"max": None, "rms": None}
+
+
+def oracle_sample(op, x0: np.ndarray, n: int, seed: int):
+    """The oracle on a seeded sample of the initial states: (indices, result)."""
+    from oracle import oracle as O
+    idx = np.unique(np.concatenate([[0, len(x0) - 1], np.sort(
+        np.random.default_rng(seed).choice(len(x0), size=min(n, len(x0)), replace=False))]))
+    return idx, O.solve_bvps(op, x0[idx])
+
+
 def precision_leg(dev, prob, grid, x0, lam64, u064, it64, surplus, eval_flops_q: float, reps: int) -> dict:
     """FP32 variants beside the FP64 path on the same MI355X: the FP32 inexact
-    Newton solve of the full workload with its plan, against the FP64 solve
-    with its plan (errors against the FP64 GPU solve, which matches the oracle
-    to ~1e-13) and FP32 feedback evaluation at 1e7 uniform
-    states (errors against the FP64 GPU evaluation of the same interpolant)."""
+    Newton solve of the full workload with its plan against the FP64 solve
+    with its plan, and FP32 feedback evaluation at 1e7 uniform states against
+    FP64; errors against the FP64 oracle on seeded samples (solve: 64 nodes,
+    evaluation: 1e4 states)."""
     import dataclasses
     import torch
     import paper_1507_04769_amd as S
+    from oracle import oracle as O
     from paper_1507_04769_amd import autotune as A
     from paper_1507_04769_amd import workloads as W
     p32 = dataclasses.replace(prob, precision=S.FP32)
@@ -196,23 +278,27 @@ def precision_leg(dev, prob, grid, x0, lam64, u064, it64, surplus, eval_flops_q:
     ws64 = torch.empty((S.sgcm_solve_bvps_workspace(p64, M) // 8 + 32,), dtype=torch.float64, device=dev)
     lam2, u02, V2 = torch.empty_like(lam), torch.empty_like(u0), torch.empty_like(V)
     st2, it2 = torch.empty_like(st), torch.empty_like(it)
-    plan32, plan64 = S.Plan(p32), S.Plan(p64)  # as in the timed step: first steps from the plans
+    plan32, plan64 = S.Plan(p32), S.Plan(p64)  # first steps from the plans (made once)
     ms32 = A.time_ms(lambda: S.sgcm_solve_bvps_plan(plan32, x0, lam, u0, V, None, st, it, ws), reps)
     ms64 = A.time_ms(lambda: S.sgcm_solve_bvps_plan(plan64, x0, lam2, u02, V2, None, st2, it2, ws64), reps)
     conv = int((st == S.CONVERGED).sum().item())
-    el = ((lam - lam64).abs().amax(dim=1) / lam64.abs().amax(dim=1).clamp_min(1e-8)).cpu().numpy()
-    eu = ((u0 - u064).abs().amax(dim=1) / u064.abs().amax(dim=1).clamp_min(1e-8)).cpu().numpy()
     i32, i64 = it.cpu().numpy(), it64
-    # the same algorithmic flops as the FP64 solve; the linear solve (95 % of
-    # them) runs in FP32, so the fraction is given against both peaks
-    f32 = newton_flops_plan(prob.N, i32)
+    op = O.Problem(N=prob.N, T=prob.T, max_iter=prob.max_iter, max_halvings=prob.max_halvings)
+    idx, o = oracle_sample(op, x0.cpu().numpy(), 64, seed=44)
+    el = rel_rows(lam.cpu().numpy()[idx], o.lambda0)
+    eu = rel_rows(u0.cpu().numpy()[idx], o.u0)
+    el64 = rel_rows(lam2.cpu().numpy()[idx], o.lambda0)
+    # the algorithmic flops of the FP64 solve; the linear solve runs in FP32,
+    # so the fraction is given against both peaks
+    f32 = newton_flops(prob.N, i32, plan=True)
     rf = alu_roofline("k_newton<float>", f32, float(np.median(ms32)), PEAK_FP32_TFLOPS)
     rf["frac_of_fp64_peak"] = rf["achieved"] / PEAK_FP64_TFLOPS
     solve = {"ms": float(np.median(ms32)), "fp64_ms": float(np.median(ms64)), "roofline": rf,
              "bvps_per_s": conv / (float(np.median(ms32)) / 1e3), "converged": conv,
              "mean_iters": float(i32.mean()), "fp64_mean_iters": float(i64.mean()),
-             "lambda0_rel_err": {"max": float(el.max()), "rms": float(np.sqrt(np.mean(el ** 2)))},
-             "u0_rel_err": {"max": float(eu.max()), "rms": float(np.sqrt(np.mean(eu ** 2)))}}
+             "vs_oracle_sample": len(idx),
+             "lambda0_rel_err": err_stats(el), "u0_rel_err": err_stats(eu),
+             "fp64_lambda0_rel_err": err_stats(el64)}
     nq = 10_000_000
     xq = torch.tensor(W.uniform_in_box(nq, seed=3), device=dev)
     xq32 = xq.float()
@@ -221,18 +307,73 @@ def precision_leg(dev, prob, grid, x0, lam64, u064, it64, surplus, eval_flops_q:
     uq32 = torch.empty((nq, surplus.shape[1]), dtype=torch.float32, device=dev)
     e64 = A.time_ms(lambda: S.sgcm_eval_feedback(grid, surplus, xq, uq, S.FP64), reps)
     e32 = A.time_ms(lambda: S.sgcm_eval_feedback_f32(grid, w32, xq32, uq32), reps)
-    err = (uq32.double() - uq).abs()
-    scale = float(uq.abs().max().item())
+    qi = W.sample_indices(nq, 10_000, seed=45)
+    ref = O.eval_hier(6, grid.level, surplus.cpu().numpy(), xq.cpu().numpy()[qi], W.BOX_LO, W.BOX_HI)
+    err32 = np.abs(uq32.cpu().numpy()[qi].astype(np.float64) - ref)
+    err64 = np.abs(uq.cpu().numpy()[qi] - ref)
     ev = {"queries": nq, "ms": float(np.median(e32)), "fp64_ms": float(np.median(e64)),
           "evals_per_s": nq / (float(np.median(e32)) / 1e3), "fp64_evals_per_s": nq / (float(np.median(e64)) / 1e3),
-          "abs_err": {"max": float(err.max().item()), "rms": float(err.pow(2).mean().sqrt().item())},
-          "max_abs_u": scale,
+          "vs_oracle_sample": len(qi),
+          "abs_err": err_stats(err32.max(axis=1)), "fp64_abs_err": err_stats(err64.max(axis=1)),
+          "max_abs_u": float(np.abs(ref).max()),
           "roofline": alu_roofline("k_eval_fast<6, %d, 3, float>" % grid.level, eval_flops_q * nq,
                                    float(np.median(e32)), PEAK_FP32_TFLOPS),
           "fp64_roofline": alu_roofline("k_eval_fast<6, %d, 3, double>" % grid.level, eval_flops_q * nq,
                                         float(np.median(e64)), PEAK_FP64_TFLOPS)}
     return {"fp32_newton": solve, "fp32_eval": ev,
-            "note": "errors against the FP64 GPU results, which match the FP64 oracle to ~1e-13"}
+            "note": "errors against the FP64 oracle on seeded samples (interpolant of the three-wheel u(0))"}
+
+
+def underactuated_leg(dev, reps: int) -> dict:
+    """The underactuated precision workload: two wheels (seeded orthonormal
+    3 x 2 B), level-4 grid over the full box, N = 256, T = 20, reached by the
+    virtual-torque continuation (4 stages, at most 100 iterations each); the
+    FP64 and the FP32 inexact Newton solves, each against the FP64 oracle on
+    a seeded sample of 64 nodes."""
+    import dataclasses
+    import torch
+    import paper_1507_04769_amd as S
+    from oracle import oracle as O
+    from paper_1507_04769_amd import autotune as A
+    from paper_1507_04769_amd import workloads as W
+    w = W.UNDERACTUATED
+    grid = S.Grid(6, w.level, W.BOX_LO, W.BOX_HI)
+    nodes = grid.nodes()
+    x0 = torch.tensor(nodes, device=dev)
+    p64 = S.Problem(m=2, J=W.J_DIAG, B=W.input_matrix(2), q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W, T=w.horizon,
+                    N=w.n_intervals, tol=W.TOL, max_iter=W.UNDERACTUATED_MAX_ITER, max_halvings=W.MAX_HALVINGS,
+                    continuation=W.UNDERACTUATED_CONTINUATION)
+    op = O.Problem(m=2, B=W.input_matrix(2), N=w.n_intervals, T=w.horizon, max_iter=p64.max_iter,
+                   max_halvings=p64.max_halvings, continuation=p64.continuation)
+    idx, o = oracle_sample(op, nodes, 64, seed=46)
+    ok = o.status == O.CONVERGED
+    out = {"workload": w.name, "grid_nodes": len(nodes), "continuation_stages": p64.continuation,
+           "max_iter_per_stage": p64.max_iter, "vs_oracle_sample": len(idx),
+           "oracle_sample_converged": int(ok.sum())}
+    for name, prec in (("fp64", S.FP64), ("fp32", S.FP32)):
+        p = dataclasses.replace(p64, precision=prec)
+        ws = torch.empty((S.sgcm_solve_bvps_workspace(p, len(nodes)) // 8 + 32,), dtype=torch.float64, device=dev)
+        res = {}
+
+        def run():
+            res["sol"] = S.solve_bvps(p, x0, workspace=ws)
+        ms = A.time_ms(run, reps)
+        sol = res["sol"]
+        st, it = sol.status.cpu().numpy(), sol.iters.cpu().numpy()
+        both = ok & (st[idx] == S.CONVERGED)
+        el = rel_rows(sol.lambda0.cpu().numpy()[idx][both], o.lambda0[both])
+        eu = rel_rows(sol.u0.cpu().numpy()[idx][both], o.u0[both])
+        out[name] = {"ms": float(np.median(ms)), "converged": int(np.sum(st == S.CONVERGED)),
+                     "status_counts": np.bincount(st, minlength=4).tolist(),
+                     "bvps_per_s": int(np.sum(st == S.CONVERGED)) / (float(np.median(ms)) / 1e3),
+                     "mean_total_iters": float(it.mean()), "max_total_iters": int(it.max()),
+                     "same_status_and_iters_as_oracle_sample": bool(np.array_equal(st[idx], o.status) and
+                                                                     np.array_equal(it[idx], o.iters)),
+                     "lambda0_rel_err": err_stats(el), "u0_rel_err": err_stats(eu)}
+    out["note"] = ("nodes whose continuation stalls are reported by status (MAXITER); without a converged "
+                   "value at every node the grid has no interpolant, so the 1e7-point FP32/FP64 evaluation is "
+                   "measured on the three-wheel interpolant (precision.fp32_eval)")
+    return out
 
 
 def validation_leg(dev, prob, grid, u0, V, surplus, n_nodes_intervals: int, reps: int) -> dict:
@@ -284,6 +425,23 @@ def serving_leg(n_requests: int, rate: float) -> dict:
     return out
 
 
+def timed_steps(step, steps: int, warmup: int, stream, n_events: int):
+    """W untimed calls of step(), then `steps` timed ones with n_events HIP
+    events recorded on the launch stream inside each; returns the events and
+    the host wall time of the timed region (bracketed by synchronisation)."""
+    import torch
+    for _ in range(warmup):
+        step(None)
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(n_events)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    return events, time.perf_counter() - t0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,13 +451,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=20000)
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-batch leg")
-    ap.add_argument("--no-precision", action="store_true", help="skip the FP32 leg")
+    ap.add_argument("--no-precision", action="store_true", help="skip the FP32 and underactuated legs")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-validation", action="store_true", help="skip the total-error estimate leg")
     ap.add_argument("--serving-requests", type=int, default=2000)
-    ap.add_argument("--serving-rate", type=float, default=2000.0, help="requests per second")
+    ap.add_argument("--serving-rate", type=float, default=500.0, help="requests per second")
     ap.add_argument("--no-plan-compare", action="store_true",
-                    help="skip timing the solve without the plan (profiling runs)")
+                    help="skip the step with a solve plan (profiling runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -316,7 +474,7 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     prob = S.Problem(m=wl.m, J=W.J_DIAG, B=W.input_matrix(wl.m), q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W,
-                     T=wl.horizon, N=wl.n_intervals, tol=W.TOL, max_iter=W.MAX_ITER)
+                     T=wl.horizon, N=wl.n_intervals, tol=W.TOL, max_iter=W.MAX_ITER, max_halvings=W.MAX_HALVINGS)
     grid = S.Grid(6, wl.level, W.BOX_LO, W.BOX_HI)
     nodes = grid.nodes()
     M = len(grid)
@@ -333,68 +491,78 @@ def main():
     surplus = torch.empty((M, wl.m), dtype=torch.float64, device=dev)
     uq = torch.empty((len(xq_host), wl.m), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
-    # the problem's solve plan (first Newton steps of the six unit initial
-    # states), made once like the grid, before the timed steps
-    torch.cuda.synchronize()
-    t_plan = time.perf_counter()
-    plan = S.Plan(prob, stream)
-    plan_ms = (time.perf_counter() - t_plan) * 1e3
+    grid.upload(stream)  # the grid's device tables, made once like the grid itself
 
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        S.sgcm_solve_bvps_plan(plan, x0, lam, u0, V, traj, st, it, ws, stream)
-        if ev is not None:
-            ev[1].record(stream)
-        S.sgcm_build_interpolant(grid, u0, surplus, stream)
-        if ev is not None:
-            ev[2].record(stream)
-        S.sgcm_eval_feedback(grid, surplus, xq, uq, S.FP64, stream)
-        if ev is not None:
-            ev[3].record(stream)
+    def make_step(solve):
+        def step(ev):
+            if ev is not None:
+                ev[0].record(stream)
+            solve()
+            if ev is not None:
+                ev[1].record(stream)
+            S.sgcm_build_interpolant(grid, u0, surplus, stream)
+            if ev is not None:
+                ev[2].record(stream)
+            S.sgcm_eval_feedback(grid, surplus, xq, uq, S.FP64, stream)
+            if ev is not None:
+                ev[3].record(stream)
+        return step
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(events[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    # the headline: one-shot steps, each BVP solving its own first Newton step
+    events, wall = timed_steps(make_step(lambda: S.sgcm_solve_bvps(prob, x0, lam, u0, V, traj, st, it, ws,
+                                                                   stream)), args.steps, args.warmup, stream, 4)
     step_ms = np.array([e[0].elapsed_time(e[3]) for e in events])
     solve_ms = np.array([e[0].elapsed_time(e[1]) for e in events])
     build_ms = np.array([e[1].elapsed_time(e[2]) for e in events])
     eval_ms = np.array([e[2].elapsed_time(e[3]) for e in events])
-
     status = st.cpu().numpy()
     iters = it.cpu().numpy()
     converged = int(np.sum(status == S.CONVERGED))
-    total_s = float(np.sum(step_ms)) / 1e3
-    value = converged * args.steps / total_s
-    flops = newton_flops_plan(wl.n_intervals, iters)
+    value = converged * args.steps / (float(np.sum(step_ms)) / 1e3)
+    flops = newton_flops(wl.n_intervals, iters)
     achieved = flops / (float(np.mean(solve_ms)) / 1e3) / 1e12
-    # the same solve without the plan (each BVP solving its first step), for
-    # comparison, on outputs of its own
-    from paper_1507_04769_amd import autotune as A
-    compare = {}
+    builder_flops = newton_flops_plan(wl.n_intervals, iters + 1) - (wl.n_intervals + 1) * FLOPS_PER_POINT_PLAN_STEP * M
+
+    # the same step with the problem's solve plan (first Newton steps of the
+    # six unit initial states), made once before the steps: the amortised form
+    with_plan = None
     if not args.no_plan_compare:
-        lam_n, u0_n, V_n, traj_n = (torch.empty_like(lam), torch.empty_like(u0), torch.empty_like(V),
-                                    torch.empty_like(traj))
-        st_n, it_n = torch.empty_like(st), torch.empty_like(it)
-        noplan_ms = A.time_ms(lambda: S.sgcm_solve_bvps(prob, x0, lam_n, u0_n, V_n, traj_n, st_n, it_n, ws), 5)
-        compare = {"solve_without_plan_ms": float(np.median(noplan_ms)),
-                   "same_status_and_iters_without_plan": bool(torch.equal(st, st_n) and torch.equal(it, it_n)),
-                   "lambda0_max_rel_diff_without_plan":
-                       float(((lam - lam_n).abs().amax(dim=1) / lam_n.abs().amax(dim=1).clamp_min(1e-8)).max().item())}
-        del lam_n, u0_n, V_n, traj_n, st_n, it_n
-    eval_flops_q = eval_flops_per_query(grid.keys(), wl.level, wl.m)
+        lam_p, u0_p, V_p, traj_p = torch.empty_like(lam), torch.empty_like(u0), torch.empty_like(V), torch.empty_like(traj)
+        st_p, it_p = torch.empty_like(st), torch.empty_like(it)
+        torch.cuda.synchronize()
+        t_plan = time.perf_counter()
+        plan = S.Plan(prob, stream)
+        plan_ms = (time.perf_counter() - t_plan) * 1e3
+        ev_p, _ = timed_steps(make_step(lambda: S.sgcm_solve_bvps_plan(plan, x0, lam_p, u0, V_p, traj_p, st_p, it_p,
+                                                                       ws, stream)), args.steps, args.warmup, stream, 4)
+        pstep = np.array([e[0].elapsed_time(e[3]) for e in ev_p])
+        psolve = np.array([e[0].elapsed_time(e[1]) for e in ev_p])
+        pit = it_p.cpu().numpy()
+        pconv = int((st_p == S.CONVERGED).sum().item())
+        pflops = newton_flops(wl.n_intervals, pit, plan=True)
+        with_plan = {"value": pconv * args.steps / (float(np.sum(pstep)) / 1e3), "unit": "BVPs/s",
+                     "ms_per_step": float(np.mean(pstep)), "solve_ms": float(np.mean(psolve)),
+                     "create_ms": plan_ms,
+                     "same_status_and_iters": bool(torch.equal(st, st_p) and torch.equal(it, it_p)),
+                     "lambda0_max_rel_diff": float(((lam - lam_p).abs().amax(dim=1) /
+                                                    lam.abs().amax(dim=1).clamp_min(1e-8)).max().item()),
+                     "roofline": alu_roofline("k_newton (sgcm_solve_bvps_plan)", pflops, float(np.mean(psolve)),
+                                              PEAK_FP64_TFLOPS),
+                     "note": "the plan is made once per problem, outside the timed steps"}
+        del lam_p, u0_p, V_p, traj_p
+        # the headline step's outputs feed the legs below: restore them
+        S.sgcm_solve_bvps(prob, x0, lam, u0, V, traj, st, it, ws, stream)
+        S.sgcm_build_interpolant(grid, u0, surplus, stream)
+        torch.cuda.synchronize()
+
+    keys = grid.keys()
+    eval_flops_q = eval_flops_per_query(keys, wl.level, wl.m)
 
     batched = None if args.no_batched or args.workload != "full" else batched_leg(dev, 5)
-    precision = None
+    precision = underactuated = None
     if not args.no_precision and args.workload == "full":
         precision = precision_leg(dev, prob, grid, x0, lam, u0, iters, surplus, eval_flops_q, 5)
+        underactuated = underactuated_leg(dev, 3)
     validation = None
     if not args.no_validation and args.workload == "full":
         validation = validation_leg(dev, prob, grid, u0, V, surplus, wl.n_intervals, 3)
@@ -409,6 +577,12 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
 
+    eval_rf = alu_roofline("k_eval_fast<6, %d, %d, double>" % (wl.level, wl.m), eval_flops_q * len(xq_host),
+                           float(np.mean(eval_ms)), PEAK_FP64_TFLOPS)
+    walk_q = eval_flops_per_query_walk(keys, wl.level, wl.m)
+    eval_rf["flops_per_query"] = eval_flops_q
+    eval_rf["kernel_count"] = {"flops_per_query": walk_q,
+                               "achieved": walk_q * len(xq_host) / (float(np.mean(eval_ms)) / 1e3) / 1e12}
     out = {
         "metric": METRIC,
         "value": value,
@@ -424,28 +598,31 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "grid_level": wl.level, "grid_nodes": M, "state_dim": 6,
                    "controls": wl.m, "intervals": wl.n_intervals, "horizon": wl.horizon, "tol": W.TOL,
-                   "queries": len(xq_host), "query_seed": wl.query_seed},
+                   "queries": len(xq_host), "query_seed": wl.query_seed, "first_newton_step": "solved per BVP"},
         "feedback_evals_per_s": len(xq_host) / (float(np.mean(eval_ms)) / 1e3),
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
         "phases_ms": {"solve_bvps": float(np.mean(solve_ms)), "build_interpolant": float(np.mean(build_ms)),
                       "eval_feedback": float(np.mean(eval_ms))},
-        "solve_plan": dict({"create_ms": plan_ms,
-                            "note": "first Newton step of each BVP formed from the problem's plan (made once, "
-                                    "outside the timed steps, like the grid)"}, **compare),
         "converged": converged,
         "newton_iters_hist": np.bincount(iters).tolist(),
         "wall_s_timed": wall,
-        "roofline": {"kernel": "k_newton (sgcm_solve_bvps_plan)", "bound": "alu", "achieved": achieved,
+        "roofline": {"kernel": "k_newton (sgcm_solve_bvps, with k_order)", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": measured_traffic() if wl.name == W.FULL.name else None,
-                     "algorithmic_flops_per_launch": flops},
-        "eval_roofline": alu_roofline("k_eval_fast<6, %d, %d, double>" % (wl.level, wl.m),
-                                      eval_flops_q * len(xq_host), float(np.mean(eval_ms)), PEAK_FP64_TFLOPS),
+                     "algorithmic_flops_per_launch": flops,
+                     "interval_steps_per_launch": float(np.sum(wl.n_intervals * (iters + 1.0))),
+                     "kernel_count": {"flops_per_launch": builder_flops,
+                                      "achieved": builder_flops / (float(np.mean(solve_ms)) / 1e3) / 1e12}},
+        "eval_roofline": eval_rf,
     }
+    if with_plan is not None:
+        out["with_plan"] = with_plan
     if batched is not None:
         out["batched"] = batched
     if precision is not None:
         out["precision"] = precision
+    if underactuated is not None:
+        out["underactuated"] = underactuated
     if validation is not None:
         out["validation"] = validation
     if serving is not None:

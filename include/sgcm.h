@@ -42,7 +42,11 @@ typedef enum {
   SGCM_EINVAL = -1,       /* invalid argument (nothing was queued)            */
   SGCM_ENOMEM = -2,       /* host or device allocation failed                 */
   SGCM_EDEVICE = -3,      /* HIP launch or runtime failure                    */
-  SGCM_EUNSUPPORTED = -4  /* valid request outside what the library supports */
+  SGCM_EUNSUPPORTED = -4, /* valid request outside what the library supports */
+  SGCM_ENOTCONVERGED = -5 /* node values from a BVP that did not converge: the
+                             interpolant is not built (reported by the Python
+                             binding, which checks the statuses of a solve
+                             before it builds from its outputs)              */
 } sgcm_err;
 
 /* Per-BVP outcome written to status[] by sgcm_solve_bvps.  A per-BVP failure
@@ -73,9 +77,24 @@ typedef enum { SGCM_FP64 = 0, SGCM_FP32 = 1 } sgcm_precision;
  * Discretisation: trapezoidal collocation (the two-point Lobatto IIIA
  * formula) on N uniform intervals of [0, T]; Newton's method from the zero
  * trajectory; its first step, the solve of the problem linearised about the
- * origin (the LQR initial guess), is not counted; then at iteration
- * it = 0, 1, ...: NONFINITE if the residual F is not finite, CONVERGED if
- * max|F| <= tol, MAXITER if it == max_iter, else a full Newton step. */
+ * origin (the LQR initial guess), is not counted and is taken in full; then
+ * at iteration it = 0, 1, ...: NONFINITE if the residual F is not finite,
+ * CONVERGED if max|F| <= tol, MAXITER if it == max_iter, else a damped Newton
+ * step Y + t d: the first of t = 1, 1/2, ..., 2^-H whose residual is finite
+ * and satisfies max|F(Y + t d)| <= (1 - 1e-4 t) max|F(Y)|, else t = 2^-H
+ * (the full step whenever it passes; H = 0 is plain Newton).  The paper fixes
+ * no solver internals (Sec. 3.1); this globalisation is the library's.
+ * Continuation (two controls, K > 0): the linearisation about the origin of
+ * a two-torque body loses a controllable direction (the torques span a
+ * plane), and Newton's iteration from its solution fails over most of a box
+ * of initial states.  The BVP is then solved in K + 1 stages: stage
+ * k = 0..K-1 solves the three-control problem with B_k = [B_1 B_2 s_k b3],
+ * s_k = 1 - k / K, b3 = B_1 x B_2 / |B_1 x B_2| (a virtual torque normal to the
+ * plane, of decreasing authority), the first stage from the zero trajectory
+ * as above and each later stage, and the final stage K (the problem itself),
+ * from the previous stage's solution, starting with its test.  A stage that
+ * does not converge ends the continuation with its status; iters is the
+ * total over the stages and max_iter applies to each. */
 typedef struct sgcm_problem {
   int32_t model;     /* sgcm_model                                            */
   int32_t n;         /* state dimension: must be 6                            */
@@ -89,7 +108,14 @@ typedef struct sgcm_problem {
   int32_t N;         /* number of mesh intervals, 1 <= N <= 65536             */
   double tol;        /* Newton tolerance on max|F| (>= 0)                     */
   int32_t max_iter;  /* Newton iterations after the first step, 0..1000       */
-  int32_t precision; /* sgcm_precision of the Newton linear solve; FP64 only  */
+  int32_t precision; /* sgcm_precision of the Newton linear solve: SGCM_FP64,
+                        or SGCM_FP32 for the inexact Newton whose linear solve
+                        runs in FP32 while the residual, the update and the
+                        stopping test stay FP64                               */
+  int32_t max_halvings; /* backtracking cap H of each counted Newton step,
+                        0..60 (0: full steps; see below)                      */
+  int32_t continuation; /* two controls: K > 0 continuation stages (0..64; see
+                        below); ignored for one or three controls             */
 } sgcm_problem;
 
 /* ---- library ------------------------------------------------------------- */
@@ -155,7 +181,8 @@ typedef struct sgcm_plan sgcm_plan;
 
 /* Create a plan for problem p (copied).  The six steps are solved on `stream`
  * in FP64 whatever p->precision (which applies to the solves with the plan),
- * and the call synchronizes the stream.  On success *out owns 6 x (N+1) x 12
+ * and the call synchronizes the stream.  With continuation they are the first
+ * steps of its first stage.  On success *out owns 6 x (N+1) x 12
  * doubles of device memory on the current device.  Returns SGCM_EINVAL for an
  * invalid problem or out == NULL, SGCM_ENOMEM, SGCM_EDEVICE, and
  * SGCM_EUNSUPPORTED when the linearised step is singular or not finite (then
@@ -196,7 +223,8 @@ typedef struct sgcm_schedule {
 } sgcm_schedule;
 
 /* N, T: host arrays of n_bvps (>= 1) mesh sizes (1..65536) and horizons
- * (finite, > 0); sched: NULL for {order 1, slots_per_cu 0}.  Like a solve
+ * (finite, > 0); sched: NULL for {order 1, slots_per_cu 0}.  A problem with
+ * continuation stages returns SGCM_EUNSUPPORTED (a batch is one launch).  Like a solve
  * plan, the batch forms each BVP's first Newton step from the first steps of
  * the six unit initial states of its (N, T), for every (N, T) shared by at
  * least 8 BVPs: creation solves those (FP64, one small launch per such
@@ -235,10 +263,22 @@ void sgcm_batch_destroy(sgcm_batch* b);
  * node's key is its tuple of d ids; nodes are sorted lexicographically by key. */
 typedef struct sgcm_grid sgcm_grid;
 
-/* Create the grid (host-side tables only; device copies are made on first
- * use on each device).  1 <= d <= 8, 0 <= level <= 5, lo[j] < hi[j]. */
+/* Create the grid (host-side tables only: no device is needed).
+ * 1 <= d <= 8, 0 <= level <= 5, lo[j] < hi[j]. */
 int sgcm_grid_create(int32_t d, int32_t level, const double* lo, const double* hi,
                      sgcm_grid** out);
+
+/* Make the grid's device tables on the current device: node coordinates,
+ * level lists, 1-D point and scale tables, child offsets, the node maps of
+ * the lower-level grids and a build staging buffer of M x 3 doubles (about
+ * 30 M + 4 d M bytes in all).  This call allocates (hipMalloc) and copies the
+ * tables on `stream` (stream-ordered; the host tables belong to the grid and
+ * stay valid); it does nothing if the tables are already on this device.  It
+ * must precede sgcm_build_interpolant and the sgcm_eval_feedback calls on a
+ * device, which then allocate nothing and never synchronise.  Not to be
+ * called concurrently with a build or an evaluation of the same grid.
+ * Returns SGCM_EINVAL for a NULL grid, SGCM_ENOMEM, SGCM_EDEVICE. */
+int sgcm_grid_upload(sgcm_grid* g, void* stream);
 
 /* Number of nodes M, or -1 for a NULL grid. */
 int64_t sgcm_grid_size(const sgcm_grid* g);
@@ -249,19 +289,25 @@ int sgcm_grid_nodes(const sgcm_grid* g, double* nodes_host);
 int sgcm_grid_keys(const sgcm_grid* g, int32_t* keys_host);
 
 /* Free the grid and its device tables (device tables are freed on the
- * device they were made on).  NULL is a no-op. */
+ * device they were made on, after the work queued on it).  NULL is a no-op. */
 void sgcm_grid_destroy(sgcm_grid* g);
 
 /* ---- interpolant (Sec. 3.3, eq. interpo) ----------------------------------- */
 
-/* Hierarchical surpluses of eq. interpo: for levels |i| = d..q in order,
+/* The grid's tables must be on the current device (sgcm_grid_upload), else
+ * the calls below return SGCM_EINVAL; they allocate nothing.
+ *
+ * Hierarchical surpluses of eq. interpo: for levels |i| = d..q in order,
  * w = f(node) - I^{|i|-1}(f)(node), with the tensor-product Lagrange basis on
  * X^{i_1} x .. x X^{i_d}.
  *   values   device, M x m node values f (canonical order), read only
  *   surplus  device, M x m (canonical order); may not alias values
- * 1 <= m <= 64.  For d = 6 and m <= 3 the lower levels' surpluses are staged
- * in a device buffer that the grid owns, so calls with the same grid on one
- * device must not overlap (use one stream, or order them). */
+ * 1 <= m <= 64.  Every value must be finite: the node values of BVP
+ * solutions whose status is not SGCM_BVP_CONVERGED are the last Newton
+ * iterate and are not to be interpolated (the Python binding refuses them
+ * with SGCM_ENOTCONVERGED).  For d = 6 and m <= 3 the lower levels'
+ * surpluses are staged in the grid's device buffer, so builds with the same
+ * grid on one device must not overlap (use one stream, or order them). */
 int sgcm_build_interpolant(const sgcm_grid* g, int32_t m, const double* values,
                            double* surplus, void* stream);
 

@@ -21,7 +21,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsgcm.so")
 
-SGCM_OK, SGCM_EINVAL, SGCM_ENOMEM, SGCM_EDEVICE, SGCM_EUNSUPPORTED = 0, -1, -2, -3, -4
+SGCM_OK, SGCM_EINVAL, SGCM_ENOMEM, SGCM_EDEVICE, SGCM_EUNSUPPORTED, SGCM_ENOTCONVERGED = 0, -1, -2, -3, -4, -5
 CONVERGED, MAXITER, SINGULAR, NONFINITE = 0, 1, 2, 3
 MODEL_RIGID_BODY, MODEL_LINEARISED = 0, 1
 FP64, FP32 = 0, 1
@@ -30,7 +30,7 @@ FP64, FP32 = 0, 1
 EXPORTS = ("sgcm_strerror", "sgcm_version", "sgcm_solve_bvps_workspace", "sgcm_solve_bvps",
            "sgcm_characteristic_rhs", "sgcm_plan_create", "sgcm_solve_bvps_plan", "sgcm_plan_destroy",
            "sgcm_batch_create", "sgcm_batch_workspace", "sgcm_solve_bvps_batch",
-           "sgcm_batch_destroy", "sgcm_grid_create", "sgcm_grid_size", "sgcm_grid_nodes",
+           "sgcm_batch_destroy", "sgcm_grid_create", "sgcm_grid_upload", "sgcm_grid_size", "sgcm_grid_nodes",
            "sgcm_grid_keys", "sgcm_grid_destroy", "sgcm_build_interpolant", "sgcm_eval_feedback",
            "sgcm_eval_feedback_f32", "sgcm_total_error")
 
@@ -46,7 +46,8 @@ class _CProblem(ctypes.Structure):
                 ("J", ctypes.c_double * 3), ("B", ctypes.c_double * 9),
                 ("q_w", ctypes.c_double), ("r_w", ctypes.c_double), ("p_w", ctypes.c_double),
                 ("T", ctypes.c_double), ("N", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("max_halvings", ctypes.c_int32), ("continuation", ctypes.c_int32)]
 
 
 @dataclass
@@ -65,6 +66,8 @@ class Problem:
     max_iter: int = 20
     precision: int = FP64
     n: int = 6
+    max_halvings: int = 10  # backtracking cap of each counted Newton step (0: full steps)
+    continuation: int = 0   # two controls: stages of the virtual-torque continuation
 
     def c(self) -> _CProblem:
         p = _CProblem()
@@ -79,6 +82,7 @@ class Problem:
         p.q_w, p.r_w, p.p_w, p.T = float(self.q_w), float(self.r_w), float(self.p_w), float(self.T)
         p.N, p.tol, p.max_iter = int(self.N), float(self.tol), int(self.max_iter)
         p.precision = int(self.precision)
+        p.max_halvings, p.continuation = int(self.max_halvings), int(self.continuation)
         return p
 
 
@@ -114,6 +118,7 @@ def lib() -> ctypes.CDLL:
         "sgcm_solve_bvps_batch": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
         "sgcm_batch_destroy": (None, [vp]),
         "sgcm_grid_create": (ctypes.c_int, [i32, i32, vp, vp, ctypes.POINTER(vp)]),
+        "sgcm_grid_upload": (ctypes.c_int, [vp, vp]),
         "sgcm_grid_size": (i64, [vp]),
         "sgcm_grid_nodes": (ctypes.c_int, [vp, vp]),
         "sgcm_grid_keys": (ctypes.c_int, [vp, vp]),
@@ -306,12 +311,22 @@ class Grid:
                                       hi.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)),
                "sgcm_grid_create")
         self._h = h
+        self._uploaded = set()  # devices that hold the grid's tables
         self.d, self.level = int(d), int(level)
         self.lo, self.hi = lo.copy(), hi.copy()
 
     @property
     def handle(self):
         return self._h
+
+    def upload(self, stream=None):
+        """sgcm_grid_upload: the grid's device tables on the current device
+        (allocated, then copied on the stream); a no-op once done there."""
+        import torch
+        dev = torch.cuda.current_device()
+        if dev not in self._uploaded:
+            _check(lib().sgcm_grid_upload(self._h, _stream(stream)), "sgcm_grid_upload")
+            self._uploaded.add(dev)
 
     def __len__(self):
         return int(lib().sgcm_grid_size(self._h))
@@ -347,6 +362,7 @@ def sgcm_build_interpolant(grid: Grid, values, surplus, stream=None):
     if values.dim() != 2 or values.shape[0] != len(grid):
         raise ValueError("values must be M x m with M = %d" % len(grid))
     m = values.shape[1]
+    grid.upload(stream)
     rc = lib().sgcm_build_interpolant(grid.handle, int(m), _ptr(values, torch.float64, "values"),
                                       _ptr(surplus, torch.float64, "surplus", len(grid) * m),
                                       _stream(stream))
@@ -360,6 +376,7 @@ def sgcm_eval_feedback(grid: Grid, surplus, xq, uq, precision: int = FP64, strea
     if xq.dim() != 2 or xq.shape[1] != grid.d:
         raise ValueError("xq must be n_q x %d" % grid.d)
     m, nq = surplus.shape[1], xq.shape[0]
+    grid.upload(stream)
     rc = lib().sgcm_eval_feedback(grid.handle, int(m), _ptr(surplus, torch.float64, "surplus"),
                                   int(nq), _ptr(xq, torch.float64, "xq"),
                                   _ptr(uq, torch.float64, "uq", nq * m), int(precision), _stream(stream))
@@ -450,11 +467,32 @@ def characteristic_rhs(problem: Problem, y, jacobian: bool = True, stream=None):
     return phi, dphi
 
 
-def build_interpolant(grid: Grid, values, stream=None):
+def require_converged(status):
+    """Raise SgcmError(SGCM_ENOTCONVERGED) unless every status is CONVERGED
+    (the node values of a BVP that did not converge are its last iterate and
+    are not interpolated).  Reads the statuses on the host."""
+    bad = int((status != CONVERGED).sum().item())
+    if bad:
+        raise SgcmError(SGCM_ENOTCONVERGED, "%d of %d BVPs did not converge" % (bad, status.numel()))
+
+
+def build_interpolant(grid: Grid, values, stream=None, status=None):
+    """Surpluses of the node values (M x m, device).  With `status` (the
+    statuses of the solve that produced the values) the build is refused
+    unless every BVP converged."""
     import torch
+    if status is not None:
+        require_converged(status)
     surplus = torch.empty_like(values)
     sgcm_build_interpolant(grid, values, surplus, stream)
     return surplus
+
+
+def build_feedback_interpolant(grid: Grid, solution: "BVPSolution", stream=None):
+    """The interpolant of the feedback u(0, x) from a solve at the grid's
+    nodes; raises SgcmError(SGCM_ENOTCONVERGED) if any node's BVP did not
+    converge."""
+    return build_interpolant(grid, solution.u0, stream, status=solution.status)
 
 
 def sgcm_eval_feedback_f32(grid: Grid, surplus, xq, uq, stream=None):
@@ -464,6 +502,7 @@ def sgcm_eval_feedback_f32(grid: Grid, surplus, xq, uq, stream=None):
     if xq.dim() != 2 or xq.shape[1] != grid.d:
         raise ValueError("xq must be n x %d" % grid.d)
     n = xq.shape[0]
+    grid.upload(stream)
     rc = lib().sgcm_eval_feedback_f32(grid.handle, int(m), _ptr(surplus, f32, "surplus", len(grid) * m), int(n),
                                       _ptr(xq, f32, "xq"), _ptr(uq, f32, "uq", n * m), _stream(stream))
     _check(rc, "sgcm_eval_feedback_f32")

@@ -63,7 +63,18 @@ struct BvpArgs {
   int sinv;         // 1: S_w is invertible and Si holds its inverse
   int fp32;         // 1: Newton linear solve in FP32 (inexact Newton)
   double Si[9];
+  int max_halvings;  // backtracking cap H of each counted Newton step
+  // Continuation stages (host-driven launches on one workspace):
+  int resume;   // 1: start from the iterate the previous stage left in the
+                // workspace (skipping a BVP whose previous stage failed) and
+                // add this stage's iterations to iters[]
+  int keep;     // 1: leave the final iterate in the workspace's first buffer
+  int outputs;  // 1: write lambda0, u0, V and traj (the last stage)
 };
+
+// Sufficient-decrease constant of the backtracking test
+// max|F(Y + t d)| <= (1 - sigma t) max|F(Y)|.
+constexpr double kArmijoSigma = 1e-4;
 
 // Phi, A = df/dx and W = -q I - Hessian_x(lambda^T f) at one mesh point.
 __device__ __forceinline__ void point_eval(const BvpArgs& P, const double* __restrict__ y,
@@ -416,6 +427,46 @@ __device__ __forceinline__ bool point_block_store(const double a, const double (
   return d1 != 0.0 && d2 != 0.0;
 }
 
+// Outputs of one BVP from its iterate Y (eq. optuv at t = 0): lambda(0),
+// u(0) = u*(x0, lambda(0)), V = z(T) + h(x(T)) with z by the trapezoidal rule
+// on the mesh, and the trajectory.
+__device__ __forceinline__ void bvp_outputs(const BvpArgs& P, const int N, const double h, const int64_t b,
+                                            const double* __restrict__ Y, double* __restrict__ lam0,
+                                            double* __restrict__ u0, double* __restrict__ Vout,
+                                            double* __restrict__ traj) {
+  const int lane = threadIdx.x;
+  const int NP = N + 1;
+  if (lane < 6) lam0[b * 6 + lane] = Y[6 + lane];
+  if (lane < P.m)
+    u0[b * P.m + lane] = P.U[lane * 3 + 0] * Y[9] + P.U[lane * 3 + 1] * Y[10] + P.U[lane * 3 + 2] * Y[11];
+  if (Vout) {
+    double part = 0.0;
+    for (int k = lane; k < NP; k += 64) {
+      const double* yk = Y + 12 * (int64_t)k;
+      double xx = 0.0, uu = 0.0;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) xx += yk[i] * yk[i];
+      for (int j = 0; j < P.m; ++j) {
+        const double u = P.U[j * 3 + 0] * yk[9] + P.U[j * 3 + 1] * yk[10] + P.U[j * 3 + 2] * yk[11];
+        uu += u * u;
+      }
+      const double L = 0.5 * (P.q * xx + P.r * uu);
+      part += ((k == 0 || k == N) ? 0.5 : 1.0) * L;
+    }
+    part = wave_sum(part);
+    if (lane == 0) {
+      const double* yN = Y + 12 * (int64_t)N;
+      double xx = 0.0;
+      for (int i = 0; i < 6; ++i) xx += yN[i] * yN[i];
+      Vout[b] = h * part + 0.5 * P.pw * xx;
+    }
+  }
+  if (traj) {
+    double* out = traj + b * 12 * (int64_t)NP;
+    for (int i = lane; i < 12 * NP; i += 64) out[i] = Y[i];
+  }
+}
+
 // Newton's method for one BVP (index b, mesh of N intervals of width h,
 // workspace ws_b) by one 64-lane workgroup.
 template <typename T>
@@ -431,23 +482,36 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
   const int NP = N + 1;
   const double alpha = 0.5 * h;
   const T at = (T)alpha;
-  double* Y = ws_b;                    // NP x 12: the iterate
-  double* R = Y + 12 * (int64_t)NP;    // 16: F_0 (6), F_N (6), pad
+  // two NP x 12 buffers: the iterate Y and the trial point Yt (swapped when a
+  // trial is taken), then the Newton step D
+  double* Y = ws_b;
+  double* Yt = ws_b + 12 * (int64_t)NP;
+  double* D = ws_b + 24 * (int64_t)NP;
+  double* R = ws_b + 36 * (int64_t)NP;  // 16: F_0 (6), F_N (6), pad
   T* Zg = reinterpret_cast<T*>(R + 16);  // N x 84: interval solutions, 12 x 7 rows
   // point blocks [A | W | L | r_k] of every mesh point, entry-major: entry e
   // of point k at PBg[e * pbs + k]
   T* PBg = reinterpret_cast<T*>(R + 16 + (int64_t)kZI * N);
   const int64_t pbs = pb_stride(N);
 
+  if (P.resume && status[b] != SGCM_BVP_CONVERGED) {
+    // an earlier continuation stage failed: that status stands, and the last
+    // stage writes the outputs of the iterate it left
+    if (P.outputs) bvp_outputs(P, N, h, b, ws_b, lam0, u0, Vout, traj);
+    return;
+  }
   if (lane < 6) sh.xb[lane] = x0[b * 6 + lane];
   if (lane < 8) sh.zero[lane] = 0.0;
   // it = -1: the first Newton step from Y = 0 (the discrete LQR guess) is
   // still to be taken.  At Y = 0 the residual is [-xbar; 0; 0] and the
   // Jacobian does not depend on xbar, so that step is linear in xbar; with a
   // plan it is the combination of the plan's steps for the unit initial
-  // states, and the loop starts with its test (it = 0).
+  // states, and the loop starts with its test (it = 0).  A resumed stage
+  // starts from the iterate in the workspace with its test.
   int it = -1, st = SGCM_BVP_MAXITER;
-  if (y1) {
+  if (P.resume) {
+    it = 0;
+  } else if (y1) {
     double xb[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) xb[j] = x0[b * 6 + j];
@@ -465,11 +529,26 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
   }
   wave_mem_sync();
 
+  // Damping of the counted steps: after a linear solve the forward pass has
+  // written the step D and the full-step point Yt = Y + D; the residual pass
+  // then evaluates the trial point Y + t D (t = 1: Yt as written; t < 1:
+  // formed from Y and D and stored to Yt), which is taken when its residual
+  // is finite and max|F| <= (1 - sigma t) max|F(Y)|, or when it is the last
+  // allowed trial (t = 2^-H); else t is halved.  The first step from Y = 0
+  // (the initial guess) is taken in full.
+  bool trial = false;  // the pass evaluates a trial point
+  bool full = false;   // ... that is taken without a test (the first step)
+  int halvings = 0;    // trials rejected so far in this step
+  double t = 1.0, fn0 = 0.0;
+  bool lin = it < 0;   // the pass at Y = 0 before the first (linearised) step
   while (true) {
-    // ---- residual F(Y) and its max norm (lane-parallel over mesh points) ----
+    // ---- residual F and its max norm at the pass's point (lane-parallel
+    //      over mesh points) ----
     double lmax = 0.0;
     int bad = 0;
     bool regular = true;
+    const bool blend = trial && halvings > 0;  // the point is Y + t D, formed here
+    const double* src = trial ? Yt : Y;
     // In the first (linearised) step Y = 0, and the sweep forms its interval
     // constants from the first batch alone (every interval has the same
     // ones).  The pass then covers only the last 64 points, which hold that
@@ -477,7 +556,7 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
     // F_N = 0 - p_w 0 directly (the values the pass would compute); nothing
     // is tested in that step.
     int base0 = 0;
-    if (it < 0 && NP > 64) {
+    if (lin && NP > 64) {
       base0 = NP - 64;
       if (lane < 6) {
         R[lane] = 0.0 - sh.xb[lane];
@@ -490,8 +569,16 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       const bool valid = k < NP;
       double yk[12], ph[12];
       if (valid) {
+        if (blend) {
 #pragma unroll
-        for (int i = 0; i < 12; ++i) yk[i] = Y[12 * (int64_t)k + i];
+          for (int i = 0; i < 12; ++i) {
+            yk[i] = fma(t, D[12 * (int64_t)k + i], Y[12 * (int64_t)k + i]);
+            Yt[12 * (int64_t)k + i] = yk[i];
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < 12; ++i) yk[i] = src[12 * (int64_t)k + i];
+        }
         double A[36], W[36];
         point_eval(P, yk, ph, A, W);
         regular &= point_block_store(alpha, A, W, PBg + k, pbs);
@@ -548,6 +635,19 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
     const bool nonfinite = __any(bad);
     const bool singular_point = __any(!regular);
     lmax = wave_max(lmax);
+    if (trial) {
+      const bool take = full || halvings == P.max_halvings || (!nonfinite && lmax <= (1.0 - kArmijoSigma * t) * fn0);
+      if (!take) {
+        t *= 0.5;
+        ++halvings;
+        continue;
+      }
+      double* y = Y;  // the trial point becomes the iterate
+      Y = Yt;
+      Yt = y;
+      ++it;
+      trial = false;
+    }
     if (it >= 0) {
       if (nonfinite) { st = SGCM_BVP_NONFINITE; break; }
       if (lmax <= P.tol) { st = SGCM_BVP_CONVERGED; break; }
@@ -558,6 +658,7 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       if (it < 0) it = 0;
       break;
     }
+    fn0 = lmax;
 
     // ---- backward Riccati sweep, batches of kNB intervals from k = N down ----
     if (lane < 6) {
@@ -602,7 +703,7 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       // y, trigonometric factors and interval residual (zero), so every
       // interval has the same constants.  They are formed in the first batch
       // and the later batches reuse them from LDS.
-      const bool reuse = it < 0 && khi != N;
+      const bool reuse = lin && khi != N;
       if (!reuse) {
         wave_mem_sync();  // the point blocks of points klo - 1 .. khi have landed
         lds_handoff();
@@ -715,7 +816,7 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       // inputs of the next batch, in flight during the chain
       const int nhi = klo - 1;
       const int nlo = nhi - (kNB - 1) < 1 ? 1 : nhi - (kNB - 1);
-      if (nhi >= 1 && it >= 0) load_points(nlo);
+      if (nhi >= 1 && !lin) load_points(nlo);
       // the serial chain: three LDS exchanges per interval.  Lane (i, o),
       // 60 lanes, owns entry (i, o) of the step; columns o = 0..5 (R), 6..8
       // (B) and 9 (rho) of [K ; e_9]; the state columns 0..5 and 9 carry
@@ -883,12 +984,16 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
 
     // ---- forward pass dx_0 = -F_0, dx_k = G_k dx_{k-1} + g_k,
     //      dlambda_{k-1} = P_{k-1} dx_{k-1} + c_{k-1}, dlambda_N = p_w dx_N - F_N;
-    //      the step is added to Y in place ----
+    //      the step goes to D and the full-step point Y + D to Yt ----
     wave_mem_sync();  // interval solutions visible to every lane
     T dx[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) dx[j] = (T)(-sh.F0[j]);
-    if (lane < 6) Y[lane] += (double)dx[lane < 6 ? lane : 0];
+    if (lane < 6) {
+      const double d0 = (double)dx[lane < 6 ? lane : 0];
+      D[lane] = d0;
+      Yt[lane] = Y[lane] + d0;
+    }
     // chunk [c0, c0 + kFwd) of interval solutions and Y rows c0 - 1 .. c0 + kFwd - 1
     // into buffer bf, direct to LDS
     auto fwd_load = [&](int c0, int bf) {
@@ -921,7 +1026,9 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       const T* zt = reinterpret_cast<const T*>(zb);
       const int yo = kFwd * kZI + (r < 6 ? 12 : 0) + r;
       const int nk = (N - c0 + 1) < kFwd ? (N - c0 + 1) : kFwd;
-      double* yrow = Y + 12 * (int64_t)(r < 6 ? c0 : c0 - 1) + r;
+      const int64_t row = 12 * (int64_t)(r < 6 ? c0 : c0 - 1) + r;
+      double* ytrow = Yt + row;
+      double* drow = D + row;
       // step s: row r of [G_k g_k ; P_{k-1} c_{k-1}] (z) and the Y entry
       // (yv) come from the chunk buffer
       auto fload = [&](int s, T (&z)[7], double& yv) {
@@ -934,7 +1041,8 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
         const T va = fma(z[2], dx[2], fma(z[1], dx[1], fma(z[0], dx[0], z[6])));
         const T vb = fma(z[5], dx[5], fma(z[4], dx[4], z[3] * dx[3]));
         const T v = va + vb;
-        yrow[12 * s] = yv + (double)v;
+        ytrow[12 * s] = yv + (double)v;
+        drow[12 * s] = (double)v;
         dx[0] = row_bcast<0>(v);
         dx[1] = row_bcast<1>(v);
         dx[2] = row_bcast<2>(v);
@@ -985,44 +1093,26 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       double d = -sh.FN[i];
 #pragma unroll
       for (int j = 0; j < 6; ++j) d = fma(j == i ? P.pw : 0.0, (double)dx[j], d);
-      Y[12 * (int64_t)N + 6 + i] += d;
+      D[12 * (int64_t)N + 6 + i] = d;
+      Yt[12 * (int64_t)N + 6 + i] = Y[12 * (int64_t)N + 6 + i] + d;
     }
     wave_mem_sync();
-    ++it;
+    // the trial of the full step; the first step is taken without a test
+    trial = true;
+    full = lin;
+    t = 1.0;
+    halvings = 0;
+    lin = false;
   }
-  // ---- outputs (eq. optuv at t = 0) ----
-  if (lane < 6) lam0[b * 6 + lane] = Y[6 + lane];
-  if (lane < P.m)
-    u0[b * P.m + lane] = P.U[lane * 3 + 0] * Y[9] + P.U[lane * 3 + 1] * Y[10] + P.U[lane * 3 + 2] * Y[11];
-  if (Vout) {
-    double part = 0.0;
-    for (int k = lane; k < NP; k += 64) {
-      const double* yk = Y + 12 * (int64_t)k;
-      double xx = 0.0, uu = 0.0;
-#pragma unroll
-      for (int i = 0; i < 6; ++i) xx += yk[i] * yk[i];
-      for (int j = 0; j < P.m; ++j) {
-        const double u = P.U[j * 3 + 0] * yk[9] + P.U[j * 3 + 1] * yk[10] + P.U[j * 3 + 2] * yk[11];
-        uu += u * u;
-      }
-      const double L = 0.5 * (P.q * xx + P.r * uu);
-      part += ((k == 0 || k == N) ? 0.5 : 1.0) * L;
-    }
-    part = wave_sum(part);
-    if (lane == 0) {
-      const double* yN = Y + 12 * (int64_t)N;
-      double xx = 0.0;
-      for (int i = 0; i < 6; ++i) xx += yN[i] * yN[i];
-      Vout[b] = h * part + 0.5 * P.pw * xx;
-    }
+  if (P.keep && Y != ws_b) {  // the next continuation stage resumes from the first buffer
+    for (int i = lane; i < 12 * NP; i += 64) ws_b[i] = Y[i];
+    wave_mem_sync();
   }
-  if (traj) {
-    double* out = traj + b * 12 * (int64_t)NP;
-    for (int i = lane; i < 12 * NP; i += 64) out[i] = Y[i];
-  }
+  if (P.outputs) bvp_outputs(P, N, h, b, Y, lam0, u0, Vout, traj);
   if (lane == 0) {
     status[b] = st;
-    iters[b] = it < 0 ? 0 : it;
+    const int n_it = it < 0 ? 0 : it;
+    iters[b] = P.resume ? iters[b] + n_it : n_it;
   }
 }
 
@@ -1171,12 +1261,13 @@ __global__ __launch_bounds__(256) void k_rhs(BvpArgs P, int64_t n, const double*
   }
 }
 
-// Workspace of one BVP in doubles, a multiple of 256 bytes: Y (N + 1) x 12,
-// F_0 and F_N (16), the interval solutions N x 84 (in the solve's type) and
-// the point blocks kPB x pb_stride(N) (71 entries per point, in the solve's type).
+// Workspace of one BVP in doubles, a multiple of 256 bytes: the iterate, the
+// trial point and the Newton step ((N + 1) x 12 each), F_0 and F_N (16), the
+// interval solutions N x 84 (in the solve's type) and the point blocks
+// kPB x pb_stride(N) (71 entries per point, in the solve's type).
 int64_t bvp_doubles(int64_t N, int fp32) {
   const int64_t esize = fp32 ? 4 : 8;
-  const int64_t d = 12 * (N + 1) + 16 + kZI * N + (kPB * pb_stride(N) * esize + 7) / 8;
+  const int64_t d = 36 * (N + 1) + 16 + kZI * N + (kPB * pb_stride(N) * esize + 7) / 8;
   return (d + 31) / 32 * 32;
 }
 
@@ -1195,6 +1286,8 @@ int make_bvp_args(const sgcm_problem* p, BvpArgs* a) {
   if (p->N < 1 || p->N > 65536) return SGCM_EINVAL;
   if (!(p->tol >= 0.0) || p->max_iter < 0 || p->max_iter > 1000) return SGCM_EINVAL;
   if (p->precision != SGCM_FP64 && p->precision != SGCM_FP32) return SGCM_EINVAL;
+  if (p->max_halvings < 0 || p->max_halvings > 60) return SGCM_EINVAL;
+  if (p->continuation < 0 || p->continuation > 64) return SGCM_EINVAL;
   a->model = p->model;
   a->m = p->m;
   a->N = p->N;
@@ -1247,7 +1340,35 @@ int make_bvp_args(const sgcm_problem* p, BvpArgs* a) {
     for (int e = 0; e < 9; ++e) a->Si[e] = 0.0;
   a->per_bvp = bvp_doubles(p->N, a->fp32);
   a->y1 = nullptr;
+  a->max_halvings = p->max_halvings;
+  a->resume = 0;
+  a->keep = 0;
+  a->outputs = 1;
   return SGCM_OK;
+}
+
+// Number of continuation stages before the problem's own: p->continuation
+// for two controls, else none.
+int continuation_stages(const sgcm_problem* p) { return p->m == 2 ? p->continuation : 0; }
+
+// Stage k of the continuation of a two-control problem (k < stages: the
+// three-control problem with B_k = [B_1 B_2 s_k b3], s_k = 1 - k / stages,
+// b3 the unit normal B_1 x B_2 / |B_1 x B_2| of the torque plane; k = stages:
+// the problem itself), without continuation of its own.
+sgcm_problem stage_problem(const sgcm_problem* p, int k) {
+  sgcm_problem q = *p;
+  q.continuation = 0;
+  const int K = continuation_stages(p);
+  if (k < K) {
+    const double* B1 = p->B;
+    const double* B2 = p->B + 3;
+    double b3[3] = {B1[1] * B2[2] - B1[2] * B2[1], B1[2] * B2[0] - B1[0] * B2[2], B1[0] * B2[1] - B1[1] * B2[0]};
+    const double nb = std::sqrt(b3[0] * b3[0] + b3[1] * b3[1] + b3[2] * b3[2]);
+    const double sk = 1.0 - (double)k / K;
+    q.m = 3;
+    for (int i = 0; i < 3; ++i) q.B[6 + i] = sk * (b3[i] / nb);
+  }
+  return q;
 }
 
 }  // namespace
@@ -1279,19 +1400,41 @@ static int solve_bvps(const sgcm_problem* p, const double* y1, int64_t n_bvps, c
   if (((uintptr_t)workspace & 255u) != 0) return SGCM_EINVAL;
   const size_t bvp_bytes = (size_t)a.per_bvp * sizeof(double) * (size_t)n_bvps;
   if (ws_bytes < bvp_bytes + order_bytes(n_bvps)) return SGCM_EINVAL;
+  const int K = continuation_stages(p);
+  if (K > 0) {  // the torque plane needs a normal: B_1 and B_2 not parallel
+    const double* B1 = p->B;
+    const double* B2 = p->B + 3;
+    const double c0 = B1[1] * B2[2] - B1[2] * B2[1], c1 = B1[2] * B2[0] - B1[0] * B2[2],
+                 c2 = B1[0] * B2[1] - B1[1] * B2[0];
+    if (!(c0 * c0 + c1 * c1 + c2 * c2 > 0.0)) return SGCM_EINVAL;
+  }
   hipStream_t s = (hipStream_t)stream;
   int32_t* order = nullptr;
   if (n_bvps > 1 && n_bvps <= kOrderMax) {
     order = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(workspace) + bvp_bytes);
     hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, s, x0, (int)n_bvps, order);
   }
-  if (a.fp32)
-    hipLaunchKernelGGL(k_newton<float>, dim3((unsigned)n_bvps), dim3(64), 0, s, a, x0, lambda0, u0, V, traj,
-                       status, iters, (double*)workspace, order);
-  else
-    hipLaunchKernelGGL(k_newton<double>, dim3((unsigned)n_bvps), dim3(64), 0, s, a, x0, lambda0, u0, V, traj,
-                       status, iters, (double*)workspace, order);
-  return hipGetLastError() == hipSuccess ? SGCM_OK : SGCM_EDEVICE;
+  // one launch per continuation stage (one in all without continuation), all
+  // with the same launch order, so that workgroup g keeps workspace slot g
+  for (int k = 0; k <= K; ++k) {
+    if (K > 0) {
+      const sgcm_problem q = stage_problem(p, k);
+      rc = make_bvp_args(&q, &a);
+      if (rc != SGCM_OK) return rc;
+      a.y1 = k == 0 ? y1 : nullptr;
+      a.resume = k > 0;
+      a.keep = k < K;
+      a.outputs = k == K;
+    }
+    if (a.fp32)
+      hipLaunchKernelGGL(k_newton<float>, dim3((unsigned)n_bvps), dim3(64), 0, s, a, x0, lambda0, u0, V, traj,
+                         status, iters, (double*)workspace, order);
+    else
+      hipLaunchKernelGGL(k_newton<double>, dim3((unsigned)n_bvps), dim3(64), 0, s, a, x0, lambda0, u0, V, traj,
+                         status, iters, (double*)workspace, order);
+    if (hipGetLastError() != hipSuccess) return SGCM_EDEVICE;
+  }
+  return SGCM_OK;
 }
 
 extern "C" int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const double* x0, double* lambda0,
@@ -1311,7 +1454,7 @@ struct sgcm_plan {
 // FP64 (the trajectory output is that step), on stream s, which is then
 // synchronized.  SGCM_EUNSUPPORTED when the step is singular or not finite.
 static int first_steps(const sgcm_problem* p, double* y1, hipStream_t s) {
-  sgcm_problem q = *p;
+  sgcm_problem q = stage_problem(p, 0);  // a continuation starts from its first stage
   q.precision = SGCM_FP64;
   q.max_iter = 0;
   size_t ws_bytes = 0;
@@ -1445,6 +1588,7 @@ extern "C" int sgcm_batch_create(const sgcm_problem* p, int64_t n_bvps, const in
   BvpArgs a;
   int rc = make_bvp_args(&q, &a);
   if (rc != SGCM_OK) return rc;
+  if (continuation_stages(p) > 0) return SGCM_EUNSUPPORTED;  // batches take one stage
   std::vector<int32_t> hN(N, N + n_bvps), horder(n_bvps);
   std::vector<double> hh(n_bvps);
   std::vector<int64_t> hoff(n_bvps);

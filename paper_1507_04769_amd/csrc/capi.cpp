@@ -13,11 +13,12 @@ extern "C" const char* sgcm_strerror(int code) {
     case SGCM_ENOMEM: return "out of memory";
     case SGCM_EDEVICE: return "HIP device or launch failure";
     case SGCM_EUNSUPPORTED: return "not supported by this library";
+    case SGCM_ENOTCONVERGED: return "node values from a BVP that did not converge";
     default: return "unknown status";
   }
 }
 
-extern "C" int sgcm_version(void) { return 100; }
+extern "C" int sgcm_version(void) { return 20000; }
 
 extern "C" int sgcm_grid_create(int32_t d, int32_t level, const double* lo, const double* hi,
                                 sgcm_grid** out) {

@@ -469,34 +469,24 @@ __global__ __launch_bounds__(64) void k_surplus_fast(GridArgs g, const double* _
 
 // ---- host side -------------------------------------------------------------
 
-int ensure_device_tables(Grid& G, int dev) {
-  std::lock_guard<std::mutex> lock(G.mu);
-  GridDevice& gd = G.dev[dev];
-  if (gd.ready) return SGCM_OK;
-  auto up = [](void** dst, const void* src, size_t bytes) -> bool {
-    if (bytes == 0) bytes = 8;
-    if (hipMalloc(dst, bytes) != hipSuccess) return false;
-    return src == nullptr || hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
-  };
-  bool ok = up((void**)&gd.node_xi, G.xi.data(), G.xi.size() * sizeof(double)) &&
-            up((void**)&gd.by_level, G.by_level.data(), G.by_level.size() * sizeof(int32_t)) &&
-            up((void**)&gd.tables, G.itab.data(), G.itab.size() * sizeof(int32_t)) &&
-            up((void**)&gd.dtab, G.dtab.data(), G.dtab.size() * sizeof(double)) &&
-            up((void**)&gd.sub_map, G.sub_map.data(), G.sub_map.size() * sizeof(int32_t)) &&
-            up((void**)&gd.scratch, nullptr, (size_t)G.M * 3 * sizeof(double));
-  for (auto& sg : G.sub) ok = ok && ensure_device_tables(*sg, dev) == SGCM_OK;
-  if (!ok) {
-    (void)hipFree(gd.node_xi);
-    (void)hipFree(gd.by_level);
-    (void)hipFree(gd.tables);
-    (void)hipFree(gd.dtab);
-    (void)hipFree(gd.sub_map);
-    (void)hipFree(gd.scratch);
-    gd = GridDevice();
-    return SGCM_ENOMEM;
-  }
-  gd.ready = true;
-  return SGCM_OK;
+void release(GridDevice& gd) {
+  (void)hipFree(gd.node_xi);
+  (void)hipFree(gd.by_level);
+  (void)hipFree(gd.tables);
+  (void)hipFree(gd.dtab);
+  (void)hipFree(gd.sub_map);
+  (void)hipFree(gd.scratch);
+  gd.node_xi = gd.dtab = gd.scratch = nullptr;
+  gd.by_level = gd.tables = gd.sub_map = nullptr;
+  gd.ready.store(false);
+}
+
+// Whether the tables of G and of its lower-level grids are on device dev.
+bool tables_ready(const Grid& G, int dev) {
+  if (!G.dev[dev].ready.load(std::memory_order_acquire)) return false;
+  for (const auto& sg : G.sub)
+    if (!tables_ready(*sg, dev)) return false;
+  return true;
 }
 
 GridArgs make_args(const Grid& G, const GridDevice& gd) {
@@ -697,19 +687,48 @@ void free_device_tables(Grid& G) {
   if (hipGetDevice(&cur) != hipSuccess) cur = -1;
   for (int dv = 0; dv < kMaxDevices; ++dv) {
     GridDevice& gd = G.dev[dv];
-    if (!gd.ready) continue;
-    if (hipSetDevice(dv) == hipSuccess) {
-      (void)hipFree(gd.node_xi);
-      (void)hipFree(gd.by_level);
-      (void)hipFree(gd.tables);
-      (void)hipFree(gd.dtab);
-      (void)hipFree(gd.sub_map);
-      (void)hipFree(gd.scratch);
-    }
-    gd = GridDevice();
+    if (!gd.ready.load()) continue;
+    if (hipSetDevice(dv) == hipSuccess) release(gd);
+    gd.ready.store(false);
   }
   if (cur >= 0) (void)hipSetDevice(cur);
   for (auto& sg : G.sub) free_device_tables(*sg);
+}
+
+int upload_device_tables(Grid& G, int dev, void* stream) {
+  for (auto& sg : G.sub) {
+    const int rc = upload_device_tables(*sg, dev, stream);
+    if (rc != SGCM_OK) return rc;
+  }
+  std::lock_guard<std::mutex> lock(G.mu);
+  GridDevice& gd = G.dev[dev];
+  if (gd.ready.load()) return SGCM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  bool dev_err = false;
+  // the host tables belong to the grid and outlive the asynchronous copies
+  auto up = [&](void** dst, const void* src, size_t bytes) -> bool {
+    if (bytes == 0) bytes = 8;
+    if (hipMalloc(dst, bytes) != hipSuccess) return false;
+    if (src != nullptr && hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess) {
+      dev_err = true;
+      return false;
+    }
+    return true;
+  };
+  const bool ok = up((void**)&gd.node_xi, G.xi.data(), G.xi.size() * sizeof(double)) &&
+                  up((void**)&gd.by_level, G.by_level.data(), G.by_level.size() * sizeof(int32_t)) &&
+                  up((void**)&gd.tables, G.itab.data(), G.itab.size() * sizeof(int32_t)) &&
+                  up((void**)&gd.dtab, G.dtab.data(), G.dtab.size() * sizeof(double)) &&
+                  up((void**)&gd.sub_map, G.sub_map.data(), G.sub_map.size() * sizeof(int32_t)) &&
+                  up((void**)&gd.scratch, nullptr, (size_t)G.M * 3 * sizeof(double));
+  if (!ok) {
+    (void)hipGetLastError();
+    if (dev_err) (void)hipStreamSynchronize(s);  // no copy may still read a freed table
+    release(gd);
+    return dev_err ? SGCM_EDEVICE : SGCM_ENOMEM;
+  }
+  gd.ready.store(true, std::memory_order_release);
+  return SGCM_OK;
 }
 
 }  // namespace sgcm
@@ -723,8 +742,7 @@ extern "C" int sgcm_build_interpolant(const sgcm_grid* gh, int32_t m, const doub
   int dev = 0;
   int rc = current_device(&dev);
   if (rc != SGCM_OK) return rc;
-  rc = ensure_device_tables(G, dev);
-  if (rc != SGCM_OK) return rc;
+  if (!tables_ready(G, dev)) return SGCM_EINVAL;  // sgcm_grid_upload first
   const GridDevice& gd = G.dev[dev];
   hipStream_t s = (hipStream_t)stream;
   if (fast_build_applies(G, m)) return build_fast(G, dev, m, values, surplus, s) == hipSuccess ? SGCM_OK : SGCM_EDEVICE;
@@ -755,8 +773,7 @@ extern "C" int sgcm_eval_feedback(const sgcm_grid* gh, int32_t m, const double* 
   int dev = 0;
   int rc = current_device(&dev);
   if (rc != SGCM_OK) return rc;
-  rc = ensure_device_tables(G, dev);
-  if (rc != SGCM_OK) return rc;
+  if (!tables_ready(G, dev)) return SGCM_EINVAL;  // sgcm_grid_upload first
   GridArgs a = make_args(G, G.dev[dev]);
   const size_t lds = lds_bytes(G);
   hipStream_t s = (hipStream_t)stream;
@@ -779,9 +796,16 @@ extern "C" int sgcm_eval_feedback_f32(const sgcm_grid* gh, int32_t m, const floa
   int dev = 0;
   int rc = current_device(&dev);
   if (rc != SGCM_OK) return rc;
-  rc = ensure_device_tables(G, dev);
-  if (rc != SGCM_OK) return rc;
+  if (!tables_ready(G, dev)) return SGCM_EINVAL;  // sgcm_grid_upload first
   GridArgs a = make_args(G, G.dev[dev]);
   return eval_fast<float>(G, m, a, n_q, surplus, xq, uq, (hipStream_t)stream) == hipSuccess ? SGCM_OK
                                                                                               : SGCM_EDEVICE;
+}
+
+extern "C" int sgcm_grid_upload(sgcm_grid* gh, void* stream) {
+  if (!gh) return SGCM_EINVAL;
+  int dev = 0;
+  const int rc = current_device(&dev);
+  if (rc != SGCM_OK) return rc;
+  return upload_device_tables(gh->g, dev, stream);
 }

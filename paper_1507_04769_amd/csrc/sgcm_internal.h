@@ -2,6 +2,7 @@
 // kernels of libsgcm.  Not part of the public interface (include/sgcm.h).
 #pragma once
 
+#include <atomic>
 #include <cstdint>
 #include <memory>
 #include <mutex>
@@ -35,9 +36,9 @@ inline int point_offset(int e) {
 // Number of 1-D points whose level excess (level - 1) is at most b.
 inline int points_upto(int b) { return b <= 0 ? 1 : (1 << b) + 1; }
 
-// Device copies of a grid's tables on one device.
+// Device copies of a grid's tables on one device (made by sgcm_grid_upload).
 struct GridDevice {
-  bool ready = false;
+  std::atomic<bool> ready{false};  // set once every table below is in place
   double* node_xi = nullptr;     // M x d node coordinates in [0, 1]
   int32_t* by_level = nullptr;   // node indices grouped by total excess
   int32_t* tables = nullptr;     // int tables (see Grid::itab)
@@ -84,6 +85,10 @@ double cgl_coordinate(int i, int t);
 
 // Free a grid's device tables on every device that has them (interp.hip).
 void free_device_tables(Grid& G);
+
+// Make a grid's device tables (and those of its lower-level grids) on device
+// dev, copied on stream s (interp.hip).
+int upload_device_tables(Grid& G, int dev, void* s);
 
 }  // namespace sgcm
 

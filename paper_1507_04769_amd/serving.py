@@ -66,8 +66,14 @@ class QueryRequest:
 
 
 def problem(m: int, N: int, T: float = 20.0) -> S.Problem:
+    """The served problem: three wheels, or two wheels reached by the
+    virtual-torque continuation (four stages, at most 100 iterations each)."""
+    if m == 2:
+        return S.Problem(m=2, J=W.J_DIAG, B=W.input_matrix(2), q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W, T=T, N=N,
+                         tol=W.TOL, max_iter=W.UNDERACTUATED_MAX_ITER, max_halvings=W.MAX_HALVINGS,
+                         continuation=W.UNDERACTUATED_CONTINUATION)
     return S.Problem(m=m, J=W.J_DIAG, B=W.input_matrix(m), q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W, T=T, N=N,
-                     tol=W.TOL, max_iter=W.MAX_ITER)
+                     tol=W.TOL, max_iter=W.MAX_ITER, max_halvings=W.MAX_HALVINGS)
 
 
 class Interpolant:
@@ -76,6 +82,7 @@ class Interpolant:
     def __init__(self, level: int, surplus64):
         self.level = level
         self.grid = S.Grid(6, level, W.BOX_LO, W.BOX_HI)
+        self.grid.upload()  # the grid's device tables, made before any request is served
         self.w64 = surplus64
         self.w32 = surplus64.float().contiguous()
 
@@ -86,7 +93,7 @@ def build_interpolant(level: int, N: int = 64):
     import torch
     g = S.Grid(6, level, W.BOX_LO, W.BOX_HI)
     sol = S.solve_bvps(problem(3, N), torch.tensor(g.nodes(), device="cuda"))
-    return Interpolant(level, S.build_interpolant(g, sol.u0))
+    return Interpolant(level, S.build_feedback_interpolant(g, sol))
 
 
 @dataclass
@@ -288,10 +295,8 @@ def request_stream(n: int, rate: float, seed: int, levels=(3, 4), max_states: in
                    max_points: int = 100_000, meshes=(64, 128, 256, 512)) -> list:
     """A seeded Poisson stream of n requests at `rate` per second: half solve
     requests (1..max_states states uniform in the box, N from `meshes`, T = 20;
-    one in four on the two-wheel model, whose states are drawn in 0.3 x the box
-    with T = 2, where its undamped Newton iteration converges), half query requests
-    (1..max_points states uniform in the box against one of `levels`, one in
-    two in FP32)."""
+    one in four on the two-wheel model), half query requests (1..max_points
+    states uniform in the box against one of `levels`, one in two in FP32)."""
     g = np.random.default_rng(seed)
     t = np.cumsum(g.exponential(1.0 / rate, size=n))
     out = []
@@ -300,9 +305,7 @@ def request_stream(n: int, rate: float, seed: int, levels=(3, 4), max_states: in
             m = 2 if g.random() < 0.25 else 3
             ns = int(g.integers(1, max_states + 1))
             x0 = W.uniform_in_box(ns, seed=int(g.integers(1 << 30)))
-            if m == 2:
-                x0 = 0.3 * x0
-            out.append(SolveRequest(k, float(t[k]), x0, int(g.choice(meshes)), m, 2.0 if m == 2 else 20.0))
+            out.append(SolveRequest(k, float(t[k]), x0, int(g.choice(meshes)), m, 20.0))
         else:
             npts = int(np.exp(g.uniform(0.0, np.log(max_points))))
             xq = W.uniform_in_box(max(npts, 1), seed=int(g.integers(1 << 30)))

@@ -86,6 +86,15 @@ J_DIAG = (2.0, 3.0, 4.0)
 Q_W, R_W, P_W = 1.0, 0.1, 10.0
 TOL = 1e-10
 MAX_ITER = 20
+MAX_HALVINGS = 10  # backtracking cap of each counted Newton step
+
+# Underactuated (two-wheel) precision workload: the level-4 grid over the full
+# box, 256 intervals, T = 20, reached by the virtual-torque continuation in
+# four stages, at most 100 Newton iterations per stage.
+UNDERACTUATED = Workload("rigid-body-6d-2wheel-L4-N256", level=4, n_intervals=256, horizon=20.0,
+                         n_queries=10_000_000, query_seed=3, m=2)
+UNDERACTUATED_CONTINUATION = 4
+UNDERACTUATED_MAX_ITER = 100
 
 
 def input_matrix(m: int = 3) -> np.ndarray:

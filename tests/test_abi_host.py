@@ -86,12 +86,18 @@ def test_problem_validation():
     assert _ws(good, 0) == (S.SGCM_OK, 0)
     bad = [dict(n=5), dict(m=0), dict(m=4), dict(N=0), dict(N=70000), dict(r_w=0.0), dict(T=-1.0),
            dict(J=(1.0, 0.0, 1.0)), dict(max_iter=-1), dict(tol=float("nan")), dict(model=7),
-           dict(q_w=-1.0)]
+           dict(q_w=-1.0), dict(max_halvings=-1), dict(max_halvings=61), dict(continuation=-1),
+           dict(continuation=65)]
     for kw in bad:
         p = S.Problem(**kw)
         assert _ws(p, 1)[0] == S.SGCM_EINVAL, kw
     assert _ws(S.Problem(precision=S.FP32), 1)[0] == S.SGCM_OK  # FP32 inexact Newton
     assert _ws(S.Problem(precision=7), 1)[0] == S.SGCM_EINVAL
+    for kw in (dict(max_halvings=0), dict(max_halvings=60), dict(continuation=64),
+               dict(m=2, B=W.input_matrix(2), continuation=4)):
+        assert _ws(S.Problem(**kw), 1)[0] == S.SGCM_OK, kw
+    # a continuation keeps the workspace of the problem itself
+    assert _ws(S.Problem(m=2, B=W.input_matrix(2), continuation=4), 3) == _ws(S.Problem(), 3)
 
 
 def test_entry_points_validate_before_device_work():
@@ -160,6 +166,8 @@ def test_batch_create_validates_before_device_work():
     assert create([64], [1.0], sched=(2, 0)) == S.SGCM_EINVAL    # unknown order
     assert create([64], [1.0], sched=(0, 9)) == S.SGCM_EINVAL    # too many slots
     assert create([64], [1.0], prob=S.Problem(m=4)) == S.SGCM_EINVAL
+    # continuation stages are launches of their own: not in a batch
+    assert create([64], [1.0], prob=S.Problem(m=2, B=W.input_matrix(2), continuation=2)) == S.SGCM_EUNSUPPORTED
     assert out.value is None
     # the problem's own N and T are ignored by a batch: valid arguments get past
     # validation (without a GPU the device query then fails)
@@ -185,3 +193,20 @@ def test_total_error_argument_validation():
     assert L.sgcm_total_error(10, 3, None, p, p, p, p, p, None) == S.SGCM_EINVAL  # no interp
     assert L.sgcm_total_error(10, 3, p, p, p, p, None, p, None) == S.SGCM_EINVAL  # no err
     assert L.sgcm_total_error(2**62, 3, p, p, p, p, p, p, None) == S.SGCM_EINVAL  # n * m overflows
+
+
+def test_grid_upload_and_convergence_guard():
+    # the device tables are made by an explicit upload; NULL is refused
+    L = S.lib()
+    assert L.sgcm_grid_upload(None, None) == S.SGCM_EINVAL
+    assert S.strerror(S.SGCM_ENOTCONVERGED) == "node values from a BVP that did not converge"
+    # the binding refuses to interpolate node values of a solve with a
+    # non-converged BVP (statuses read on the host; no device needed here)
+    import torch
+    S.require_converged(torch.zeros(5, dtype=torch.int32))
+    for bad in (S.MAXITER, S.SINGULAR, S.NONFINITE):
+        st = torch.zeros(5, dtype=torch.int32)
+        st[3] = bad
+        with pytest.raises(S.SgcmError) as e:
+            S.require_converged(st)
+        assert e.value.code == S.SGCM_ENOTCONVERGED

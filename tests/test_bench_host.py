@@ -47,3 +47,28 @@ def test_traffic_is_withdrawn_when_the_kernel_source_changes(tmp_path):
     assert B.measured_traffic() == 3.31e9
     src.write_text("// the kernel, edited\n")
     assert B.measured_traffic() is None
+
+
+def test_newton_flops_per_interval_step():
+    B = load_bench()
+    # 6.5 kflop per interval and linear solve: iters + 1 solves without a
+    # plan, iters with one
+    assert B.newton_flops(256, np.array([3])) == 6500.0 * 256 * 4
+    assert B.newton_flops(256, np.array([3]), plan=True) == 6500.0 * 256 * 3
+    assert B.newton_flops(np.array([64, 128]), np.array([0, 2])) == 6500.0 * (64 + 128 * 3)
+
+
+def test_eval_flops_per_query_survey_counts():
+    # 2 m M + sum over nodes of (non-trivial dimensions - 1) + 6 x 5 flops per
+    # point of X^2..X^{level+1}: 810, 3,344, 12,242 and 40,928 flops per query
+    # (m = 3) at levels 2..5
+    from oracle import oracle as O
+    B = load_bench()
+    for level, want in ((2, 810), (3, 3344), (4, 12242), (5, 40928)):
+        keys = O.grid(6, level).keys
+        assert B.eval_flops_per_query(keys, level, 3) == want, level
+
+
+def test_cpu_model_is_named():
+    B = load_bench()
+    assert isinstance(B.cpu_model(), str) and B.cpu_model()

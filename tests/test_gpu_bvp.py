@@ -28,13 +28,14 @@ def rel_err(a, b):
     return np.max(np.abs(a - b), axis=1) / np.maximum(np.max(np.abs(b), axis=1), 1e-8)
 
 
-def problems(model=S.MODEL_RIGID_BODY, m=3, N=64, T=20.0, tol=W.TOL, max_iter=W.MAX_ITER):
+def problems(model=S.MODEL_RIGID_BODY, m=3, N=64, T=20.0, tol=W.TOL, max_iter=W.MAX_ITER,
+             max_halvings=W.MAX_HALVINGS, continuation=0):
     B = W.input_matrix(m)
     g = S.Problem(model=model, m=m, J=W.J_DIAG, B=B, q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W, T=T, N=N,
-                  tol=tol, max_iter=max_iter)
+                  tol=tol, max_iter=max_iter, max_halvings=max_halvings, continuation=continuation)
     o = O.Problem(model={S.MODEL_RIGID_BODY: O.RIGID_BODY, S.MODEL_LINEARISED: O.LINEARISED}[model],
                   n=6, m=m, J=W.J_DIAG, B=B, q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W, T=T, N=N, tol=tol,
-                  max_iter=max_iter)
+                  max_iter=max_iter, max_halvings=max_halvings, continuation=continuation)
     return g, o
 
 
@@ -109,19 +110,118 @@ def test_underactuated_short_horizon_parity():
 
 def test_full_workload_parity():
     # level-4 grid (1457 nodes), N = 256: the whole grid on the GPU in the
-    # launch configuration the benchmark times; the oracle on a seeded sample
-    # of nodes, and the oracle's residual of every GPU trajectory.
+    # launch configuration the benchmark times, every node against the oracle
+    # (status and iterations bit-exact; lambda(0), u(0), V and the whole
+    # trajectory within 1e-8), and the oracle's residual of every trajectory
     w = W.FULL
     gp, op = problems(N=w.n_intervals, T=w.horizon)
     x0 = O.grid(6, w.level, W.BOX_LO, W.BOX_HI).nodes
     g = gpu_solve(gp, x0)
     assert np.all(g["status"] == S.CONVERGED)
-    idx = np.unique(np.concatenate([[0, 1, 2, len(x0) - 1], W.sample_indices(len(x0), 28, seed=112)]))
-    o = O.solve_bvps(op, x0[idx], want_traj=True)
-    sub = {k: (v[idx] if v is not None else None) for k, v in g.items()}
-    assert_parity(sub, o)
+    o = O.solve_bvps(op, x0, want_traj=True)
+    assert_parity(g, o)
+    assert np.bincount(g["iters"]).tolist() == [193, 0, 180, 944, 140]
     F = O.residual(op, x0, g["traj"])
     assert np.max(np.abs(F)) <= W.TOL + 1e-12
+
+
+def test_damped_steps_match_oracle():
+    # two wheels over the full box, T = 5, N = 8 and N = 64: some full Newton
+    # steps fail the decrease test and are halved; statuses and iteration
+    # counts bit-exact against the oracle, values within 1e-8
+    for N, seed in ((8, 140), (64, 141)):
+        gp, op = problems(m=2, N=N, T=5.0, max_iter=40)
+        x0 = W.uniform_in_box(48, seed=seed)
+        assert_parity(gpu_solve(gp, x0), O.solve_bvps(op, x0, want_traj=True))
+    # the cap H = 0 is the undamped iteration
+    gp, op = problems(m=2, N=16, T=5.0, max_iter=12, max_halvings=0)
+    x0 = W.uniform_in_box(16, seed=142)
+    assert_parity(gpu_solve(gp, x0), O.solve_bvps(op, x0, want_traj=True))
+
+
+def test_underactuated_continuation_small_grid():
+    # two wheels, level-2 grid over the full box, N = 64, T = 20: the
+    # virtual-torque continuation in four stages, at most 100 iterations per
+    # stage; statuses (including the stages that stall), iteration totals and
+    # values against the oracle
+    gp, op = problems(m=2, N=64, T=20.0, max_iter=W.UNDERACTUATED_MAX_ITER,
+                      continuation=W.UNDERACTUATED_CONTINUATION)
+    x0 = O.grid(6, 2, W.BOX_LO, W.BOX_HI).nodes
+    g = gpu_solve(gp, x0)
+    o = O.solve_bvps(op, x0, want_traj=True)
+    assert np.sum(o.status == O.CONVERGED) >= 84
+    assert_parity(g, o)
+
+
+# A node whose solve takes many damped steps follows a path that rounding can
+# change: the two sides eliminate the Newton system differently, so an
+# accept-or-halve decision of the backtracking that is close to its threshold
+# can go either way, and from there the iterates differ (several extremals
+# exist for the underactuated body; Sec. 2 Assumption 1).  Below this total
+# iteration count (four continuation stages of about ten Newton steps) the
+# underactuated nodes are required to match the oracle exactly.
+DAMPED_REGIME_ITERS = 40
+
+
+def assert_underactuated_parity(g, o, traj_check_problem=None, x0=None):
+    """Status and iterations bit-exact, and values within 1e-8, at every node
+    the oracle solves in fewer than DAMPED_REGIME_ITERS iterations; at the
+    others (at most 1 % of the nodes) the same kind of outcome (converged or
+    stalled, nothing non-finite or singular), values within 1e-8 where both
+    reach the same solution, and every GPU-converged trajectory a solution of
+    the collocation equations by the oracle's residual."""
+    short = o.iters < DAMPED_REGIME_ITERS
+    assert np.array_equal(g["status"][short], o.status[short])
+    assert np.array_equal(g["iters"][short], o.iters[short])
+    ok = short & (o.status == O.CONVERGED)
+    assert np.all(rel_err(g["lambda0"][ok], o.lambda0[ok]) <= REL)
+    assert np.all(rel_err(g["u0"][ok], o.u0[ok]) <= REL)
+    assert np.all(rel_err(g["V"][ok, None], o.V[ok, None]) <= REL)
+    assert np.all(np.isin(g["status"], (S.CONVERGED, S.MAXITER)))
+    long_ = ~short
+    differ = long_ & ((g["status"] != o.status) | (g["iters"] != o.iters))
+    same = long_ & (g["status"] == S.CONVERGED) & (o.status == O.CONVERGED)
+    e = rel_err(g["lambda0"][same], o.lambda0[same])
+    print("damped regime: %d nodes, %d with another status or iteration count, %d converged on both sides "
+          "of which %d to another extremal" % (long_.sum(), differ.sum(), same.sum(), np.sum(e > REL)))
+    assert differ.sum() + np.sum(e > REL) <= 0.01 * len(o.status)
+    if traj_check_problem is not None:
+        conv = g["status"] == S.CONVERGED
+        F = O.residual(traj_check_problem, x0[conv], g["traj"][conv])
+        assert np.max(np.abs(F)) <= W.TOL + 1e-12
+
+
+def test_underactuated_full_workload():
+    # the precision workload's FP64 reference: two wheels, level-4 grid over
+    # the full box (1457 nodes), N = 256, T = 20, continuation in four stages;
+    # every node against the oracle
+    w = W.UNDERACTUATED
+    gp, op = problems(m=2, N=w.n_intervals, T=w.horizon, max_iter=W.UNDERACTUATED_MAX_ITER,
+                      continuation=W.UNDERACTUATED_CONTINUATION)
+    x0 = O.grid(6, w.level, W.BOX_LO, W.BOX_HI).nodes
+    g = gpu_solve(gp, x0)
+    o = O.solve_bvps(op, x0)
+    assert np.sum(o.status == O.CONVERGED) >= 1430
+    assert np.sum(o.iters < DAMPED_REGIME_ITERS) >= 1000
+    assert_underactuated_parity(g, o, op, x0)
+
+
+def test_continuation_inputs():
+    # B_1 parallel to B_2 has no torque-plane normal: refused before any launch
+    torch = _torch()
+    gp, _ = problems(m=2, N=16, T=2.0, continuation=2)
+    gp.B = np.array([[1.0, 2.0], [0.0, 0.0], [0.0, 0.0]])
+    x0 = torch.zeros((3, 6), dtype=torch.float64, device="cuda")
+    with pytest.raises(S.SgcmError) as e:
+        S.solve_bvps(gp, x0)
+    assert e.value.code == S.SGCM_EINVAL
+    # three controls: the continuation does not apply (same bits as without)
+    gp3, _ = problems(N=16, T=2.0)
+    gc3, _ = problems(N=16, T=2.0, continuation=3)
+    x0 = W.uniform_in_box(5, seed=143)
+    a, b = gpu_solve(gp3, x0), gpu_solve(gc3, x0)
+    for k in ("lambda0", "u0", "V", "traj", "status", "iters"):
+        assert np.array_equal(a[k], b[k]), k
 
 
 def test_status_rules():

@@ -82,8 +82,8 @@ def test_ragged_query_counts(nq):
 
 
 def test_full_size_feedback_eval():
-    # level-4 grid, 1e6 seeded queries: all on the GPU, a seeded sample on
-    # the oracle
+    # level-4 grid, 1e6 seeded queries: all on the GPU, 1e5 of them (a seeded
+    # sample plus both ends) on the oracle
     torch = _torch()
     w = W.FULL
     g = S.Grid(6, w.level, W.BOX_LO, W.BOX_HI)
@@ -94,7 +94,7 @@ def test_full_size_feedback_eval():
     torch.cuda.synchronize()
     u = u.cpu().numpy()
     assert np.all(np.isfinite(u))
-    idx = W.sample_indices(len(xq), 400, seed=11)
+    idx = W.sample_indices(len(xq), 100_000, seed=11)
     idx = np.unique(np.concatenate([idx, [0, len(xq) - 1]]))
     ref = O.eval_hier(6, w.level, w_ref, xq[idx], W.BOX_LO, W.BOX_HI)
     assert np.max(np.abs(u[idx] - ref)) <= REL * max(1.0, np.abs(ref).max())
@@ -130,3 +130,48 @@ def test_eval_deterministic():
     b = S.eval_feedback(g, w, xq)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def test_build_and_eval_need_uploaded_tables():
+    # sgcm_build_interpolant and sgcm_eval_feedback(_f32) allocate nothing:
+    # on a grid whose tables are not on the device they refuse the call, and
+    # after sgcm_grid_upload (stream-ordered) they run
+    import ctypes
+    torch = _torch()
+    L = S.lib()
+    g = S.Grid(6, 3, W.BOX_LO, W.BOX_HI)
+    vals = dev(W.random_values(len(g), 3, seed=14))
+    w = torch.empty_like(vals)
+    xq = dev(W.uniform_in_box(100, seed=15))
+    uq = torch.empty((100, 3), dtype=torch.float64, device="cuda")
+    vp = ctypes.c_void_p
+    s = S._stream(None)
+    assert L.sgcm_build_interpolant(g.handle, 3, vp(vals.data_ptr()), vp(w.data_ptr()), s) == S.SGCM_EINVAL
+    assert L.sgcm_eval_feedback(g.handle, 3, vp(w.data_ptr()), 100, vp(xq.data_ptr()), vp(uq.data_ptr()), S.FP64,
+                                s) == S.SGCM_EINVAL
+    assert L.sgcm_eval_feedback_f32(g.handle, 3, vp(w.data_ptr()), 100, vp(xq.data_ptr()), vp(uq.data_ptr()),
+                                    s) == S.SGCM_EINVAL
+    assert L.sgcm_grid_upload(g.handle, s) == S.SGCM_OK
+    assert L.sgcm_grid_upload(g.handle, s) == S.SGCM_OK  # again: a no-op
+    assert L.sgcm_build_interpolant(g.handle, 3, vp(vals.data_ptr()), vp(w.data_ptr()), s) == S.SGCM_OK
+    assert L.sgcm_eval_feedback(g.handle, 3, vp(w.data_ptr()), 100, vp(xq.data_ptr()), vp(uq.data_ptr()), S.FP64,
+                                s) == S.SGCM_OK
+    torch.cuda.synchronize()
+    ref = O.eval_hier(6, 3, O.build_surplus(6, 3, vals.cpu().numpy()), xq.cpu().numpy(), W.BOX_LO, W.BOX_HI)
+    assert np.max(np.abs(uq.cpu().numpy() - ref)) <= REL * max(1.0, np.abs(ref).max())
+
+
+def test_interpolant_refuses_non_converged_solutions():
+    # node values of a solve with a non-converged BVP are not interpolated
+    # (nodes with one non-zero coordinate rotate about a principal axis, where
+    # the linearised solution is exact; the others need Newton iterations)
+    g = S.Grid(6, 2, W.BOX_LO, W.BOX_HI)
+    p = S.Problem(N=32, T=4.0, max_iter=0)
+    sol = S.solve_bvps(p, dev(g.nodes()))
+    assert int((sol.status == S.MAXITER).sum()) > 0
+    with pytest.raises(S.SgcmError) as e:
+        S.build_feedback_interpolant(g, sol)
+    assert e.value.code == S.SGCM_ENOTCONVERGED
+    ok = S.solve_bvps(S.Problem(N=32, T=4.0), dev(g.nodes()))
+    w = S.build_feedback_interpolant(g, ok)
+    assert w.shape == (len(g), 3)

@@ -81,12 +81,12 @@ def test_fp32_eval_rejects_unsupported():
         S.eval_feedback_f32(g, torch.zeros((len(g), 1), device="cuda"), torch.zeros((4, 3), device="cuda"))
 
 
-def problems(m=3, N=64, T=20.0, fp32=True):
+def problems(m=3, N=64, T=20.0, fp32=True, max_iter=W.MAX_ITER, continuation=0):
     B = W.input_matrix(m)
     g = S.Problem(m=m, J=W.J_DIAG, B=B, q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W, T=T, N=N, tol=W.TOL,
-                  max_iter=W.MAX_ITER, precision=S.FP32 if fp32 else S.FP64)
+                  max_iter=max_iter, precision=S.FP32 if fp32 else S.FP64, continuation=continuation)
     o = O.Problem(n=6, m=m, J=W.J_DIAG, B=B, q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W, T=T, N=N, tol=W.TOL,
-                  max_iter=W.MAX_ITER)
+                  max_iter=max_iter, continuation=continuation)
     return g, o
 
 
@@ -124,14 +124,37 @@ def test_fp32_newton_underactuated_region():
     check_fp32_solve(solve(gp, x0), O.solve_bvps(op, x0), "two wheels")
 
 
-def test_fp32_newton_full_workload_sample():
+def test_fp32_newton_full_workload():
+    # every node of the level-4 grid (N = 256) against the FP64 oracle
     w = W.FULL
     gp, op = problems(N=w.n_intervals, T=w.horizon)
     x0 = O.grid(6, w.level, W.BOX_LO, W.BOX_HI).nodes
+    check_fp32_solve(solve(gp, x0), O.solve_bvps(op, x0), "level-4 grid")
+
+
+def test_fp32_newton_underactuated_full_workload():
+    # the precision workload: two wheels, level-4 grid over the full box,
+    # N = 256, T = 20, virtual-torque continuation; the FP32 inexact Newton
+    # against the FP64 oracle at every node where both converge
+    w = W.UNDERACTUATED
+    gp, op = problems(m=2, N=w.n_intervals, T=w.horizon, max_iter=W.UNDERACTUATED_MAX_ITER,
+                      continuation=W.UNDERACTUATED_CONTINUATION)
+    x0 = O.grid(6, w.level, W.BOX_LO, W.BOX_HI).nodes
     g = solve(gp, x0)
-    assert np.all(g["status"] == S.CONVERGED)
-    idx = np.unique(np.concatenate([[0, len(x0) - 1], W.sample_indices(len(x0), 14, seed=440)]))
-    check_fp32_solve({k: v[idx] for k, v in g.items()}, O.solve_bvps(op, x0[idx]), "level-4 grid sample")
+    o = O.solve_bvps(op, x0)
+    both = (g["status"] == S.CONVERGED) & (o.status == O.CONVERGED)
+    assert np.sum(g["status"] == S.CONVERGED) >= 1430 and np.sum(both) >= 1420
+    e_l = rel_err(g["lambda0"][both], o.lambda0[both])
+    e_u = rel_err(g["u0"][both], o.u0[both])
+    # several extremals exist (Sec. 2 Assumption 1): a node may converge to
+    # another one than the oracle's; such nodes are counted, not compared
+    same = e_l <= SOLVE_REL
+    print("two wheels, level 4: FP32 Newton converged %d, both %d, %d to another extremal; same extremal: "
+          "lambda0 max rel %.3g RMS %.3g; u0 max rel %.3g RMS %.3g" % (
+              np.sum(g["status"] == S.CONVERGED), np.sum(both), np.sum(~same), e_l[same].max(),
+              np.sqrt(np.mean(e_l[same] ** 2)), e_u[same].max(), np.sqrt(np.mean(e_u[same] ** 2))))
+    assert np.sum(~same) <= 0.01 * len(x0)
+    assert e_u[same].max() <= SOLVE_REL
 
 
 def test_fp32_batch_matches_fp32_solver():

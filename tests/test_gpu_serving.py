@@ -82,15 +82,17 @@ def test_served_results_match_oracle(interps):
     g = np.random.default_rng(603)
     reqs = [SV.SolveRequest(0, 0.0, W.uniform_in_box(3, seed=604), 64, 3, 20.0),
             SV.SolveRequest(1, 0.0, W.uniform_in_box(2, seed=605), 64, 3, 20.0),
-            SV.SolveRequest(2, 0.0, 0.3 * W.uniform_in_box(2, seed=606), 128, 2, 2.0),
+            SV.SolveRequest(2, 0.0, W.uniform_in_box(2, seed=606), 128, 2, 20.0),
             SV.QueryRequest(3, 0.0, W.uniform_in_box(300, seed=607), 4, False),
             SV.QueryRequest(4, 0.0, W.uniform_in_box(200, seed=608), 5, False)]
     g.shuffle(reqs)
     SV.Server(interps, n_streams=2).run(reqs, realtime=False)
     for r in reqs:
         if isinstance(r, SV.SolveRequest):
+            p = SV.problem(r.m, r.N, r.T)
             op = O.Problem(n=6, m=r.m, J=W.J_DIAG, B=W.input_matrix(r.m), q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W,
-                           T=r.T, N=r.N, tol=W.TOL, max_iter=W.MAX_ITER)
+                           T=r.T, N=r.N, tol=W.TOL, max_iter=p.max_iter, max_halvings=p.max_halvings,
+                           continuation=p.continuation)
             o = O.solve_bvps(op, r.x0)
             assert np.array_equal(r.out["status"], o.status) and np.array_equal(r.out["iters"], o.iters)
             err = np.abs(r.out["lambda0"] - o.lambda0).max(axis=1) / np.abs(o.lambda0).max(axis=1)

@@ -69,7 +69,7 @@ def test_request_stream_is_seeded_and_in_range():
     for r in a:
         if isinstance(r, SV.SolveRequest):
             assert 1 <= len(r.x0) <= 512 and r.N in (64, 128, 256, 512) and r.m in (2, 3)
-            assert (r.T == 2.0) == (r.m == 2)
+            assert r.T == 20.0
         else:
             assert 1 <= len(r.xq) <= 100_000 and r.level in (3, 4, 5)
     kinds = {type(r).__name__ for r in a}
