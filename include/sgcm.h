@@ -158,6 +158,27 @@ int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const double* x0,
                     int32_t* status, int32_t* iters, void* workspace,
                     size_t ws_bytes, void* stream);
 
+/* Device scratch, in bytes, that the library holds per device for
+ * sgcm_solve_bvps_static. */
+#define SGCM_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* sgcm_solve_bvps without a workspace argument and without any allocation,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * workspace is a device array of SGCM_STATIC_SCRATCH_BYTES that the library
+ * holds on each device it runs on until the process ends (its address is
+ * looked up on the first call on a device).  A call whose workspace
+ * (sgcm_solve_bvps_workspace of the same problem and count) exceeds it
+ * returns SGCM_EUNSUPPORTED before any device work: at N = 256 that allows
+ * about 170 BVPs per call.  Arguments, outputs and the other errors as for
+ * sgcm_solve_bvps.  Every call on a device uses the same array: calls that
+ * overlap on one device (other streams, other threads) race and give wrong
+ * results; order them.  No part of the array needs clearing between calls
+ * (the solver ignores the workspace's contents on entry). */
+int sgcm_solve_bvps_static(const sgcm_problem* p, int64_t n_bvps, const double* x0, double* lambda0,
+                           double* u0, double* V, double* traj, int32_t* status, int32_t* iters,
+                           void* stream);
+
 /* The right-hand side of eq. hamchar at n_points states y = (x, lambda) and
  * its Jacobian (the per-mesh-point blocks the Newton solve is built from):
  *   y     device, n_points x 12

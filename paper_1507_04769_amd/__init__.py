@@ -27,7 +27,7 @@ MODEL_RIGID_BODY, MODEL_LINEARISED = 0, 1
 FP64, FP32 = 0, 1
 
 # every extern "C" symbol declared in include/sgcm.h
-EXPORTS = ("sgcm_strerror", "sgcm_version", "sgcm_solve_bvps_workspace", "sgcm_solve_bvps",
+EXPORTS = ("sgcm_strerror", "sgcm_version", "sgcm_solve_bvps_workspace", "sgcm_solve_bvps", "sgcm_solve_bvps_static",
            "sgcm_characteristic_rhs", "sgcm_plan_create", "sgcm_solve_bvps_plan", "sgcm_plan_destroy",
            "sgcm_batch_create", "sgcm_batch_workspace", "sgcm_solve_bvps_batch",
            "sgcm_batch_destroy", "sgcm_grid_create", "sgcm_grid_upload", "sgcm_grid_size", "sgcm_grid_nodes",
@@ -109,6 +109,7 @@ def lib() -> ctypes.CDLL:
         "sgcm_version": (ctypes.c_int, []),
         "sgcm_solve_bvps_workspace": (ctypes.c_int, [P, i64, ctypes.POINTER(ctypes.c_size_t)]),
         "sgcm_solve_bvps": (ctypes.c_int, [P, i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
+        "sgcm_solve_bvps_static": (ctypes.c_int, [P, i64, vp, vp, vp, vp, vp, vp, vp, vp]),
         "sgcm_characteristic_rhs": (ctypes.c_int, [P, i64, vp, vp, vp, vp]),
         "sgcm_plan_create": (ctypes.c_int, [P, vp, ctypes.POINTER(vp)]),
         "sgcm_solve_bvps_plan": (ctypes.c_int, [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
@@ -204,6 +205,17 @@ def _solve_args(problem: Problem, x0, lambda0, u0, V, traj, status, iters, works
 def sgcm_solve_bvps(problem: Problem, x0, lambda0, u0, V, traj, status, iters, workspace, stream=None):
     args = _solve_args(problem, x0, lambda0, u0, V, traj, status, iters, workspace, stream)
     _check(lib().sgcm_solve_bvps(ctypes.byref(problem.c()), *args), "sgcm_solve_bvps")
+
+
+STATIC_SCRATCH_BYTES = 64 << 20  # SGCM_STATIC_SCRATCH_BYTES
+
+
+def sgcm_solve_bvps_static(problem: Problem, x0, lambda0, u0, V, traj, status, iters, stream=None):
+    """The solve without a workspace argument and without allocation (the
+    library's per-device scratch); calls on one device must not overlap."""
+    args = _solve_args(problem, x0, lambda0, u0, V, traj, status, iters, None, stream)
+    n, ptrs, strm = args[0], args[1:8], args[10]
+    _check(lib().sgcm_solve_bvps_static(ctypes.byref(problem.c()), n, *ptrs, strm), "sgcm_solve_bvps_static")
 
 
 class Plan:

@@ -1443,6 +1443,50 @@ extern "C" int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const doub
   return solve_bvps(p, nullptr, n_bvps, x0, lambda0, u0, V, traj, status, iters, workspace, ws_bytes, stream);
 }
 
+// ---- the solve without allocation ---------------------------------------------
+
+// The workspace of sgcm_solve_bvps_static: one copy of this array per device
+// the library runs on, held until the process ends.  In host code its name is
+// a host-side stand-in; kernels get its device address, looked up once per
+// device with hipGetSymbolAddress.
+static __device__ __align__(256) double scratch[SGCM_STATIC_SCRATCH_BYTES / sizeof(double)];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device (null: not looked up)
+
+// The device address of `scratch` on the current device.
+static int static_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return SGCM_EDEVICE;
+  if (dev < 0 || dev >= kMaxDevices) return SGCM_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return SGCM_EDEVICE;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SGCM_OK;
+}
+
+extern "C" int sgcm_solve_bvps_static(const sgcm_problem* p, int64_t n_bvps, const double* x0, double* lambda0,
+                                      double* u0, double* V, double* traj, int32_t* status, int32_t* iters,
+                                      void* stream) {
+  size_t need = 0;
+  int rc = sgcm_solve_bvps_workspace(p, n_bvps, &need);  // validates p and n_bvps
+  if (rc != SGCM_OK) return rc;
+  if (need > (size_t)SGCM_STATIC_SCRATCH_BYTES) return SGCM_EUNSUPPORTED;
+  if (n_bvps == 0) return SGCM_OK;
+  void* ws = nullptr;
+  rc = static_scratch(&ws);
+  if (rc != SGCM_OK) return rc;
+  return solve_bvps(p, nullptr, n_bvps, x0, lambda0, u0, V, traj, status, iters, ws,
+                    (size_t)SGCM_STATIC_SCRATCH_BYTES, stream);
+}
+
 struct sgcm_plan {
   sgcm_problem p;
   int dev;     // the device current at creation, which holds y1
