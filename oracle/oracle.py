@@ -26,6 +26,7 @@ _SRC = os.path.join(_HERE, "sgcm_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 RIGID_BODY, LINEARISED, EXAMPLE3 = 0, 1, 2
+TRAPEZOID, LOBATTO4 = 0, 1  # collocation formulas (two- and four-point Lobatto IIIA)
 CONVERGED, MAXITER, SINGULAR, NONFINITE = 0, 1, 2, 3
 
 
@@ -45,7 +46,7 @@ class _Problem(ctypes.Structure):
                 ("q_w", ctypes.c_double), ("r_w", ctypes.c_double), ("p_w", ctypes.c_double),
                 ("T", ctypes.c_double), ("N", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("max_halvings", ctypes.c_int32),
-                ("continuation", ctypes.c_int32)]
+                ("continuation", ctypes.c_int32), ("scheme", ctypes.c_int32)]
 
 
 @dataclass
@@ -65,6 +66,7 @@ class Problem:
     max_iter: int = 20
     max_halvings: int = 10   # backtracking cap of each Newton step (0: full steps)
     continuation: int = 0    # two controls: stages of the virtual-torque continuation
+    scheme: int = TRAPEZOID  # collocation formula
 
     def c(self) -> _Problem:
         p = _Problem()
@@ -80,6 +82,7 @@ class Problem:
         p.q_w, p.r_w, p.p_w = self.q_w, self.r_w, self.p_w
         p.T, p.N, p.tol, p.max_iter = self.T, self.N, self.tol, self.max_iter
         p.max_halvings, p.continuation = self.max_halvings, self.continuation
+        p.scheme = self.scheme
         return p
 
 
@@ -100,6 +103,9 @@ def lib():
             "oracle_residual": (None, [P, i64, d, d, d, ci]),
             "oracle_jacobian_dense": (None, [P, d, d]),
             "oracle_solve_bvps": (None, [P, i64, d, d, d, d, d, i32, i32, d, ci]),
+            "oracle_solve_bvps_full": (None, [P, i64, d, d, d, d, d, i32, i32, d, d, ci]),
+            "oracle_collocation_dim": (i64, [P]),
+            "oracle_lobatto_tableau": (None, [d, d]),
             "oracle_grid_size": (i64, [ci, ci]),
             "oracle_grid": (i64, [ci, ci, d, d, d, d, i32, i32]),
             "oracle_lagrange": (None, [ci, ci, i64, d, d]),
@@ -156,8 +162,22 @@ def ustar(prob: Problem, y):
     return u
 
 
+def lobatto_tableau():
+    """(c, A) of the four-point Lobatto IIIA formula (4 and 4 x 4)."""
+    c, a = np.zeros(4), np.zeros(16)
+    lib().oracle_lobatto_tableau(_dp(c), _dp(a))
+    return c, a.reshape(4, 4)
+
+
+def collocation_dim(prob: Problem) -> int:
+    """Unknowns of the collocation system: 2n (N + 1) for the trapezoid,
+    2n (3N + 1) for the four-point Lobatto IIIA formula (with its stages)."""
+    return int(lib().oracle_collocation_dim(ctypes.byref(prob.c())))
+
+
 def residual(prob: Problem, x0, traj, nthreads: int | None = None):
-    """Collocation residual F(Y) of given trajectories (nb x (N+1) x 2n)."""
+    """Collocation residual F(Y) of given unknown vectors (nb x dim; for the
+    trapezoid the trajectories nb x (N+1) x 2n)."""
     x0 = _f64(x0).reshape(-1, prob.n)
     nb = x0.shape[0]
     Y = _f64(traj).reshape(nb, -1)
@@ -168,7 +188,7 @@ def residual(prob: Problem, x0, traj, nthreads: int | None = None):
 
 
 def jacobian_dense(prob: Problem, Y):
-    dim = 2 * prob.n * (prob.N + 1)
+    dim = collocation_dim(prob)
     Y = _f64(Y).reshape(dim)
     Jd = np.zeros((dim, dim))
     lib().oracle_jacobian_dense(ctypes.byref(prob.c()), _dp(Y), _dp(Jd))
@@ -184,10 +204,13 @@ class BVPResult:
     status: np.ndarray
     iters: np.ndarray
     fnorm: np.ndarray
+    unknowns: np.ndarray | None = None
 
 
-def solve_bvps(prob: Problem, x0, want_traj: bool = False, nthreads: int | None = None):
-    """Solve the characteristic BVP (eq. hamchar) from every row of x0."""
+def solve_bvps(prob: Problem, x0, want_traj: bool = False, nthreads: int | None = None,
+               want_unknowns: bool = False):
+    """Solve the characteristic BVP (eq. hamchar) from every row of x0; traj
+    holds the mesh values, unknowns the whole unknown vector."""
     n, m, N = prob.n, prob.m, prob.N
     x0 = _f64(x0).reshape(-1, n)
     nb = x0.shape[0]
@@ -195,12 +218,13 @@ def solve_bvps(prob: Problem, x0, want_traj: bool = False, nthreads: int | None 
     u0 = np.zeros((nb, m))
     V = np.zeros(nb)
     traj = np.zeros((nb, N + 1, 2 * n)) if want_traj else None
+    unk = np.zeros((nb, collocation_dim(prob))) if want_unknowns else None
     st = np.zeros(nb, dtype=np.int32)
     it = np.zeros(nb, dtype=np.int32)
     fn = np.zeros(nb)
-    lib().oracle_solve_bvps(ctypes.byref(prob.c()), nb, _dp(x0), _dp(lam), _dp(u0), _dp(V),
-                            _dp(traj), _ip(st), _ip(it), _dp(fn), nthreads or default_threads())
-    return BVPResult(lam, u0, V, traj, st, it, fn)
+    lib().oracle_solve_bvps_full(ctypes.byref(prob.c()), nb, _dp(x0), _dp(lam), _dp(u0), _dp(V),
+                                 _dp(traj), _ip(st), _ip(it), _dp(fn), _dp(unk), nthreads or default_threads())
+    return BVPResult(lam, u0, V, traj, st, it, fn, unk)
 
 
 # --- sparse grid and interpolation -----------------------------------------

@@ -114,7 +114,10 @@ typedef struct {
   int32_t max_iter;  // Newton iterations after the first (linearised) step
   int32_t max_halvings;  // backtracking cap H of each Newton step (0: full steps)
   int32_t continuation;  // K > 0 (two controls only): continuation stages, see solve_bvp
+  int32_t scheme;        // ORC_TRAPEZOID or ORC_LOBATTO4 (collocation formula)
 } oracle_problem;
+
+enum { ORC_TRAPEZOID = 0, ORC_LOBATTO4 = 1 };
 
 }  // extern "C"
 
@@ -370,6 +373,9 @@ struct Collocation {
   explicit Collocation(const oracle_problem& pp)
       : p(pp), n(pp.n), ny(2 * pp.n), N(pp.N), dim(2 * pp.n * (pp.N + 1)),
         hstep(pp.T / pp.N), Phi((size_t)ny * (N + 1)), dPhi((size_t)ny * ny * (N + 1)) {}
+  int kl() const { return 3 * n - 1; }
+  int ku() const { return 3 * n - 1; }
+  const double* mesh_point(const double* Y, int k) const { return Y + (size_t)k * ny; }
 
   void eval_points(const double* Y, bool with_jac) {
     for (int k = 0; k <= N; ++k)
@@ -420,6 +426,126 @@ struct Collocation {
       set(rowN + i, colN + n + i, 1.0);
     }
   }
+};
+
+// ---------------------------------------------------------------------------
+// Four-point Lobatto IIIA collocation of eq. hamchar (the paper's BVP
+// formula, Sec. 3.1 and Sec. 5.1) on t_k = k T / N.  On each interval the
+// collocation points are t_k + c_j h, c = (0, (5 - sqrt 5)/10, (5 + sqrt 5)/10, 1);
+// the stage values Z_{k,1} = y_k, Z_{k,2}, Z_{k,3}, Z_{k,4} = y_{k+1} satisfy
+//   Z_{k,i} = y_k + h sum_j a_ij Phi(Z_{k,j}),  i = 2, 3, 4,
+// with a_ij = integral from 0 to c_i of the Lagrange polynomial l_j on c (the
+// collocation polynomial through the four points satisfies the ODE at each
+// of them).  Unknowns: Y = (y_0, [Z_{k,2}, Z_{k,3}, y_{k+1}] for k = 0..N-1);
+// F = [ x_0 - xbar ; the 3 x 2n stage equations of every interval ;
+//       lambda_N - (dh/dx)(x_N)^T ].
+// ---------------------------------------------------------------------------
+
+// The Lobatto IIIA coefficients of the four-point formula from their
+// definition: the Lagrange polynomials on c expanded in monomials and
+// integrated term by term.
+struct LobattoTableau {
+  double c[4], a[4][4];
+  LobattoTableau() {
+    const double r5 = std::sqrt(5.0);
+    c[0] = 0.0;
+    c[1] = (5.0 - r5) / 10.0;
+    c[2] = (5.0 + r5) / 10.0;
+    c[3] = 1.0;
+    for (int j = 0; j < 4; ++j) {
+      double poly[4] = {1.0, 0.0, 0.0, 0.0};  // coefficients of s^0..s^3
+      for (int m = 0; m < 4; ++m) {
+        if (m == j) continue;
+        const double den = c[j] - c[m];
+        double next[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int e = 0; e < 3; ++e) {  // poly * (s - c_m) / (c_j - c_m)
+          next[e + 1] += poly[e] / den;
+          next[e] -= poly[e] * c[m] / den;
+        }
+        for (int e = 0; e < 4; ++e) poly[e] = next[e];
+      }
+      for (int i = 0; i < 4; ++i) {
+        double v = 0.0, pw = c[i];
+        for (int e = 0; e < 4; ++e) {
+          v += poly[e] * pw / (e + 1);
+          pw *= c[i];
+        }
+        a[i][j] = v;
+      }
+    }
+  }
+};
+
+struct LobattoCollocation {
+  const oracle_problem& p;
+  int n, ny, N, dim;
+  double hstep;
+  LobattoTableau tab;
+  std::vector<double> Phi, dPhi;  // per collocation point: y_k at 3k, Z_{k,2} at 3k+1, Z_{k,3} at 3k+2
+  explicit LobattoCollocation(const oracle_problem& pp)
+      : p(pp), n(pp.n), ny(2 * pp.n), N(pp.N), dim(2 * pp.n * (3 * pp.N + 1)), hstep(pp.T / pp.N),
+        Phi((size_t)ny * (3 * N + 1)), dPhi((size_t)ny * ny * (3 * N + 1)) {}
+  int kl() const { return 4 * ny - 1; }
+  int ku() const { return 4 * ny - 1; }
+  // offset in Y of collocation point q (= 3k + j - 1 for stage j of interval k)
+  static size_t point(int q, int ny) { return (size_t)q * ny; }
+
+  void eval_points(const double* Y, bool with_jac) {
+    for (int q = 0; q <= 3 * N; ++q)
+      phi_and_jacobian(p, Y + point(q, ny), &Phi[(size_t)q * ny], with_jac ? &dPhi[(size_t)q * ny * ny] : nullptr);
+  }
+
+  void residual(const double* xbar, const double* Y, double* F) {
+    for (int i = 0; i < n; ++i) F[i] = Y[i] - xbar[i];
+    for (int k = 0; k < N; ++k) {
+      const double* yk = Y + point(3 * k, ny);
+      for (int i = 1; i < 4; ++i) {
+        const double* zi = Y + point(3 * k + i, ny);
+        double* Fi = F + n + (size_t)(3 * k + i - 1) * ny;
+        for (int r = 0; r < ny; ++r) {
+          double s = 0.0;
+          for (int j = 0; j < 4; ++j) s += tab.a[i][j] * Phi[(size_t)(3 * k + j) * ny + r];
+          Fi[r] = zi[r] - yk[r] - hstep * s;
+        }
+      }
+    }
+    const double* yN = Y + point(3 * N, ny);
+    double g[8], Hh[64];
+    terminal_derivs(p, yN, g, Hh);
+    double* FN = F + n + (size_t)3 * N * ny;
+    for (int i = 0; i < n; ++i) FN[i] = yN[n + i] - g[i];
+  }
+
+  template <class SetFn>
+  void jacobian(const double* Y, SetFn set) {
+    for (int i = 0; i < n; ++i) set(i, i, 1.0);
+    for (int k = 0; k < N; ++k)
+      for (int i = 1; i < 4; ++i) {
+        const int row0 = n + (3 * k + i - 1) * ny;
+        for (int j = 0; j < 4; ++j) {
+          const double* D = &dPhi[(size_t)(3 * k + j) * ny * ny];
+          const int col0 = (3 * k + j) * ny;
+          for (int r = 0; r < ny; ++r)
+            for (int c = 0; c < ny; ++c) {
+              double v = -hstep * tab.a[i][j] * D[r * ny + c];
+              if (r == c && j == i) v += 1.0;
+              if (r == c && j == 0) v -= 1.0;
+              set(row0 + r, col0 + c, v);
+            }
+        }
+      }
+    const double* yN = Y + point(3 * N, ny);
+    double g[8], Hh[64];
+    terminal_derivs(p, yN, g, Hh);
+    const int rowN = n + 3 * N * ny, colN = 3 * N * ny;
+    for (int i = 0; i < n; ++i) {
+      for (int j = 0; j < n; ++j) set(rowN + i, colN + j, -Hh[i * n + j]);
+      set(rowN + i, colN + n + i, 1.0);
+    }
+  }
+
+  // the mesh values y_k (rows of the trajectory) inside Y
+  const double* mesh_point(const double* Y, int k) const { return Y + point(3 * k, ny); }
 };
 
 // Banded matrix with kl sub-diagonals and ku super-diagonals, stored by
@@ -505,12 +631,12 @@ constexpr double kArmijoSigma = 1e-4;
 
 // Newton's iteration on F(Y) = 0.  from_zero: start at Y = 0 and take the
 // first (uncounted) step in full; else start at the given Y with its test.
-int newton_solve(const oracle_problem& p, const double* xbar, double* Y, bool from_zero, int* iters_out,
-                 double* fnorm_out) {
-  Collocation C(p);
-  const int dim = C.dim, n = p.n;
-  const int kl = 3 * n - 1, ku = 3 * n - 1;
-  Band A(dim, kl, ku);
+template <class Coll>
+int newton_iterate(const oracle_problem& p, const double* xbar, double* Y, bool from_zero, int* iters_out,
+                   double* fnorm_out) {
+  Coll C(p);
+  const int dim = C.dim;
+  Band A(dim, C.kl(), C.ku());
   std::vector<double> F(dim), d(dim), Yt(dim), Ft(dim);
   // the Newton step d = -F'(Y)^{-1} F(Y); false on an exactly zero pivot
   auto newton_direction = [&]() -> bool {
@@ -551,6 +677,18 @@ int newton_solve(const oracle_problem& p, const double* xbar, double* Y, bool fr
     }
     std::copy(Yt.begin(), Yt.end(), Y);
   }
+}
+
+// Newton's iteration with the problem's collocation formula.
+int newton_solve(const oracle_problem& p, const double* xbar, double* Y, bool from_zero, int* iters_out,
+                 double* fnorm_out) {
+  if (p.scheme == ORC_LOBATTO4) return newton_iterate<LobattoCollocation>(p, xbar, Y, from_zero, iters_out, fnorm_out);
+  return newton_iterate<Collocation>(p, xbar, Y, from_zero, iters_out, fnorm_out);
+}
+
+// Number of unknowns of the collocation system of p.
+int64_t collocation_dim(const oracle_problem& p) {
+  return p.scheme == ORC_LOBATTO4 ? 2 * (int64_t)p.n * (3 * (int64_t)p.N + 1) : 2 * (int64_t)p.n * (p.N + 1);
 }
 
 // The characteristic BVP from xbar.  With two controls and continuation K > 0
@@ -722,6 +860,28 @@ double binom(int n, int k) {
   return r;
 }
 
+template <class Coll>
+void residual_of(const oracle_problem* p, int64_t nb, const double* xbar, const double* Y, double* F,
+                 int nthreads) {
+  const int n = p->n;
+  const int64_t dim = collocation_dim(*p);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+  for (int64_t b = 0; b < nb; ++b) {
+    Coll C(*p);
+    C.eval_points(Y + b * dim, false);
+    C.residual(xbar + b * n, Y + b * dim, F + b * dim);
+  }
+}
+
+template <class Coll>
+void jacobian_dense_of(const oracle_problem* p, const double* Y, double* Jd) {
+  Coll C(*p);
+  const int dim = C.dim;
+  std::fill(Jd, Jd + (size_t)dim * dim, 0.0);
+  C.eval_points(Y, true);
+  C.jacobian(Y, [&](int i, int j, double v) { Jd[(size_t)i * dim + j] = v; });
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -742,35 +902,46 @@ void oracle_ustar(const oracle_problem* p, int64_t npts, const double* y, double
 }
 
 // collocation residual F(Y) for given trajectories (nb of them)
+// the four-point Lobatto IIIA tableau: nodes c (4) and coefficients a (4 x 4)
+void oracle_lobatto_tableau(double* c, double* a) {
+  LobattoTableau t;
+  for (int i = 0; i < 4; ++i) {
+    c[i] = t.c[i];
+    for (int j = 0; j < 4; ++j) a[i * 4 + j] = t.a[i][j];
+  }
+}
+
+// number of unknowns (and of residual entries) of the collocation system
+int64_t oracle_collocation_dim(const oracle_problem* p) { return collocation_dim(*p); }
+
+// collocation residual F(Y) of nb unknown vectors Y (nb x dim)
 void oracle_residual(const oracle_problem* p, int64_t nb, const double* xbar, const double* Y,
                      double* F, int nthreads) {
-  const int n = p->n;
-  const int64_t dim = 2 * (int64_t)n * (p->N + 1);
-#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
-  for (int64_t b = 0; b < nb; ++b) {
-    Collocation C(*p);
-    C.eval_points(Y + b * dim, false);
-    C.residual(xbar + b * n, Y + b * dim, F + b * dim);
-  }
+  if (p->scheme == ORC_LOBATTO4)
+    residual_of<LobattoCollocation>(p, nb, xbar, Y, F, nthreads);
+  else
+    residual_of<Collocation>(p, nb, xbar, Y, F, nthreads);
 }
 
 // dense Jacobian F'(Y) (dim x dim row-major) for small meshes
 void oracle_jacobian_dense(const oracle_problem* p, const double* Y, double* Jd) {
-  Collocation C(*p);
-  const int dim = C.dim;
-  std::fill(Jd, Jd + (size_t)dim * dim, 0.0);
-  C.eval_points(Y, true);
-  C.jacobian(Y, [&](int i, int j, double v) { Jd[(size_t)i * dim + j] = v; });
+  if (p->scheme == ORC_LOBATTO4)
+    jacobian_dense_of<LobattoCollocation>(p, Y, Jd);
+  else
+    jacobian_dense_of<Collocation>(p, Y, Jd);
 }
 
 // Solve nb BVPs from initial states x0 (nb x n).  Outputs (any may be null):
-// lambda0 (nb x n), u0 (nb x m), V (nb), traj (nb x (N+1) x 2n), status, iters,
-// fnorm (final max|F|).
-void oracle_solve_bvps(const oracle_problem* p, int64_t nb, const double* x0, double* lambda0,
-                       double* u0, double* V, double* traj, int32_t* status, int32_t* iters,
-                       double* fnorm, int nthreads) {
+// lambda0 (nb x n), u0 (nb x m), V (nb), traj (nb x (N+1) x 2n, the mesh
+// values), status, iters, fnorm (final max|F|), unknowns (nb x dim: the whole
+// unknown vector, with the Lobatto interior stages).
+void oracle_solve_bvps_full(const oracle_problem* p, int64_t nb, const double* x0, double* lambda0,
+                            double* u0, double* V, double* traj, int32_t* status, int32_t* iters,
+                            double* fnorm, double* unknowns, int nthreads) {
   const int n = p->n, m = p->m, ny = 2 * n, N = p->N;
-  const int64_t dim = (int64_t)ny * (N + 1);
+  const int64_t dim = collocation_dim(*p);
+  const bool lob = p->scheme == ORC_LOBATTO4;
+  const int pts = lob ? 3 : 1;  // collocation points per interval in Y
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
   for (int64_t b = 0; b < nb; ++b) {
     std::vector<double> Y(dim);
@@ -784,19 +955,43 @@ void oracle_solve_bvps(const oracle_problem* p, int64_t nb, const double* x0, do
       for (int i = 0; i < n; ++i) lambda0[b * n + i] = Y[n + i];
     if (u0) ustar(*p, Y.data(), u0 + b * m);
     if (V) {
-      // z(T) by the trapezoidal rule on the mesh, plus h(x(T))  (eq. optuv)
-      double hstep = p->T / N, z = 0.0, Lprev = 0.0;
-      for (int k = 0; k <= N; ++k) {
-        double u[3];
-        ustar(*p, &Y[(size_t)k * ny], u);
-        double Lk = L_model(*p, &Y[(size_t)k * ny], u);
-        if (k > 0) z += 0.5 * hstep * (Lprev + Lk);
-        Lprev = Lk;
+      // z(T) by the formula's quadrature on the mesh (the trapezoidal rule,
+      // or the Lobatto weights b_j = a_4j over the four points of each
+      // interval), plus h(x(T))  (eq. optuv)
+      const double hstep = p->T / N;
+      double z = 0.0;
+      if (lob) {
+        LobattoTableau tab;
+        for (int k = 0; k < N; ++k)
+          for (int j = 0; j < 4; ++j) {
+            const double* yq = &Y[(size_t)(3 * k + j) * ny];
+            double u[3];
+            ustar(*p, yq, u);
+            z += hstep * tab.a[3][j] * L_model(*p, yq, u);
+          }
+      } else {
+        double Lprev = 0.0;
+        for (int k = 0; k <= N; ++k) {
+          double u[3];
+          ustar(*p, &Y[(size_t)k * ny], u);
+          double Lk = L_model(*p, &Y[(size_t)k * ny], u);
+          if (k > 0) z += 0.5 * hstep * (Lprev + Lk);
+          Lprev = Lk;
+        }
       }
-      V[b] = z + h_model(*p, &Y[(size_t)N * ny]);
+      V[b] = z + h_model(*p, &Y[(size_t)pts * N * ny]);
     }
-    if (traj) std::memcpy(traj + b * dim, Y.data(), sizeof(double) * dim);
+    if (traj)
+      for (int k = 0; k <= N; ++k)
+        std::memcpy(traj + (b * (N + 1) + k) * ny, &Y[(size_t)pts * k * ny], sizeof(double) * ny);
+    if (unknowns) std::memcpy(unknowns + b * dim, Y.data(), sizeof(double) * dim);
   }
+}
+
+void oracle_solve_bvps(const oracle_problem* p, int64_t nb, const double* x0, double* lambda0,
+                       double* u0, double* V, double* traj, int32_t* status, int32_t* iters,
+                       double* fnorm, int nthreads) {
+  oracle_solve_bvps_full(p, nb, x0, lambda0, u0, V, traj, status, iters, fnorm, nullptr, nthreads);
 }
 
 // ---- sparse grid ----------------------------------------------------------
