@@ -378,9 +378,12 @@ def underactuated_leg(dev, reps: int) -> dict:
 
 def validation_leg(dev, prob, grid, u0, V, surplus, n_nodes_intervals: int, reps: int) -> dict:
     """Monte Carlo total-error estimate of the interpolant (Sec. 4.3): 1280
-    uniform states, reference from 2x and 4x the nodes' intervals (Richardson
-    extrapolation), for the feedback u(0, x) (the step's interpolant) and the
-    value V(0, x) (an interpolant of the node values of V)."""
+    uniform states, the reference from the four-point Lobatto IIIA formula
+    with error control (meshes doubled from N/4 until the order-6
+    extrapolation's correction is within 1e-7), for the feedback u(0, x) (the
+    step's interpolant) and the value V(0, x) (an interpolant of the node
+    values of V); the trapezoid with its order-2 extrapolation on 2N and 4N
+    intervals beside it."""
     import torch
     import paper_1507_04769_amd as S
     from paper_1507_04769_amd import autotune as A
@@ -388,18 +391,24 @@ def validation_leg(dev, prob, grid, u0, V, surplus, n_nodes_intervals: int, reps
     from paper_1507_04769_amd import workloads as W
     w_V = S.build_interpolant(grid, V.view(-1, 1).contiguous())
     xs = torch.tensor(W.uniform_in_box(VA.N_SAMPLES, seed=VA.SAMPLE_SEED), device=dev)
-    n_ref = 2 * n_nodes_intervals
-    est = VA.Estimator(prob, n_ref)
-    r = est(grid, surplus, xs, w_V)
-    ms = A.time_ms(lambda: est(grid, surplus, xs, w_V), reps)
-    su, sV = r.stats_u.cpu().numpy(), r.stats_V.cpu().numpy()
-    st = r.status.cpu().numpy()
-    return {"samples": VA.N_SAMPLES, "seed": VA.SAMPLE_SEED, "node_intervals": n_nodes_intervals,
-            "reference_intervals": [n_ref, 2 * n_ref],
-            "reference_converged": [int(np.sum(st[0] == S.CONVERGED)), int(np.sum(st[1] == S.CONVERGED))],
-            "u_error": {"max": float(su[0]), "rms": float(su[1]), "reference_correction_max": float(su[2])},
-            "V_error": {"max": float(sV[0]), "rms": float(sV[1]), "reference_correction_max": float(sV[2])},
-            "ms": float(np.median(ms)), "samples_per_s": VA.N_SAMPLES / (float(np.median(ms)) / 1e3)}
+    out = {"samples": VA.N_SAMPLES, "seed": VA.SAMPLE_SEED, "node_intervals": n_nodes_intervals}
+    for name, scheme, n_ref in (("lobatto4", S.LOBATTO4, max(n_nodes_intervals // 4, 1)),
+                                ("trapezoid", S.TRAPEZOID, 2 * n_nodes_intervals)):
+        est = VA.Estimator(prob, n_ref, scheme=scheme)
+        r = est(grid, surplus, xs, w_V)
+        ms = A.time_ms(lambda: est(grid, surplus, xs, w_V), reps)
+        su, sV = r.stats_u.cpu().numpy(), r.stats_V.cpu().numpy()
+        st = r.status.cpu().numpy()
+        out[name] = {"reference_intervals": [r.n_ref, 2 * r.n_ref], "reference_order": est.order,
+                     "reference_converged": [int(np.sum(st[0] == S.CONVERGED)), int(np.sum(st[1] == S.CONVERGED))],
+                     "reference_error_estimate": r.correction,
+                     "u_error": {"max": float(su[0]), "rms": float(su[1]), "mae": float(su[3]),
+                                 "relative_mae": float(su[4]), "reference_correction_max": float(su[2])},
+                     "V_error": {"max": float(sV[0]), "rms": float(sV[1]), "mae": float(sV[3]),
+                                 "relative_mae": float(sV[4]), "reference_correction_max": float(sV[2])},
+                     "ms": float(np.median(ms)), "samples_per_s": VA.N_SAMPLES / (float(np.median(ms)) / 1e3)}
+    out["lobatto4"]["tolerance"] = VA.REF_TOL
+    return out
 
 
 def serving_leg(n_requests: int, rate: float) -> dict:

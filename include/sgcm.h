@@ -71,11 +71,25 @@ typedef enum { SGCM_MODEL_RIGID_BODY = 0, SGCM_MODEL_LINEARISED = 1 } sgcm_model
 
 typedef enum { SGCM_FP64 = 0, SGCM_FP32 = 1 } sgcm_precision;
 
+/* Collocation formula of the BVP (both members of the Lobatto IIIA family):
+ *   SGCM_TRAPEZOID  the two-point formula, y_k - y_{k-1} = (h/2)(Phi_{k-1} + Phi_k),
+ *                   second order;
+ *   SGCM_LOBATTO4   the four-point formula the paper solves its BVPs with
+ *                   (Sec. 3.1, Sec. 5.1): on each interval the collocation
+ *                   points t_k + c_j h, c = (0, (5 - sqrt 5)/10, (5 + sqrt 5)/10, 1),
+ *                   two interior stages per interval, order 6 at the mesh
+ *                   points; the error is controlled by the caller by mesh
+ *                   doubling (the difference of the solutions on N and 2N
+ *                   intervals estimates 63/64 of the coarse one's error).
+ *                   FP64 only; no plans or batches (SGCM_EUNSUPPORTED). */
+typedef enum { SGCM_TRAPEZOID = 0, SGCM_LOBATTO4 = 1 } sgcm_scheme;
+
 /* The optimal-control problem of Sec. 2 and its discretisation.
  * Cost: integral over [0,T] of 0.5 (q_w x^T x + r_w u^T u) dt
  *       + 0.5 p_w x(T)^T x(T).
- * Discretisation: trapezoidal collocation (the two-point Lobatto IIIA
- * formula) on N uniform intervals of [0, T]; Newton's method from the zero
+ * Discretisation: collocation by the problem's scheme (trapezoid: the
+ * two-point Lobatto IIIA formula; or the four-point formula, see
+ * sgcm_scheme) on N uniform intervals of [0, T]; Newton's method from the zero
  * trajectory; its first step, the solve of the problem linearised about the
  * origin (the LQR initial guess), is not counted and is taken in full; then
  * at iteration it = 0, 1, ...: NONFINITE if the residual F is not finite,
@@ -116,6 +130,7 @@ typedef struct sgcm_problem {
                         0..60 (0: full steps; see below)                      */
   int32_t continuation; /* two controls: K > 0 continuation stages (0..64; see
                         below); ignored for one or three controls             */
+  int32_t scheme;    /* sgcm_scheme of the collocation                       */
 } sgcm_problem;
 
 /* ---- library ------------------------------------------------------------- */
@@ -141,8 +156,10 @@ int sgcm_solve_bvps_workspace(const sgcm_problem* p, int64_t n_bvps, size_t* byt
  *   lambda0  device, n_bvps x 6: the costate lambda(0)
  *   u0       device, n_bvps x m: the feedback u*(0, x0) = u*(x0, lambda(0))
  *   V        device, n_bvps, or NULL: the cost z(T) + h(x(T)), z integrated
- *            by the trapezoidal rule on the mesh
+ *            by the scheme's quadrature on the mesh (the trapezoidal rule, or
+ *            the Lobatto weights over each interval's four points)
  *   traj     device, n_bvps x (N+1) x 12, or NULL: (x_k, lambda_k), t_k = kT/N
+ *            (the mesh values; not the interior Lobatto stages)
  *   status   device, n_bvps (sgcm_bvp_status)
  *   iters    device, n_bvps: Newton iterations after the first step
  *   workspace, ws_bytes: device scratch of at least
@@ -360,21 +377,26 @@ int sgcm_eval_feedback_f32(const sgcm_grid* g, int32_t m, const float* surplus, 
 /* The error of the interpolant at n sample states against BVP solutions more
  * accurate than those at the grid nodes (the Monte Carlo estimate of
  * e_interp + e_bvp of Sec. 4.3).  The reference at a sample is the Richardson
- * extrapolation of two trapezoidal solutions, on N and 2N intervals of the
- * same horizon: ref = (4 fine - coarse) / 3, which removes the h^2 term of
- * the trapezoid's error (its expansion has even powers of h only).
- *   interp  device, n x m: the interpolant at the samples (sgcm_eval_feedback)
- *   coarse  device, n x m: the same quantity solved on N intervals
- *   fine    device, n x m: solved on 2N intervals
- *   ref     device, n x m out: the extrapolated reference
- *   err     device, n out: max over the m components of |interp - ref|
- *   stats   device, 3 out: [0] max of err, [1] RMS of err, [2] max over
+ * extrapolation of two solutions of a formula of order p (order), on N and
+ * 2N intervals of the same horizon: ref = (2^p fine - coarse) / (2^p - 1),
+ * which removes the h^p term of the error (p = 2 for the trapezoid, whose
+ * error expands in even powers of h; p = 6 for the four-point Lobatto IIIA
+ * formula at the mesh points).
+ *   order    p, 1..16
+ *   interp   device, n x m: the interpolant at the samples (sgcm_eval_feedback)
+ *   coarse   device, n x m: the same quantity solved on N intervals
+ *   fine     device, n x m: solved on 2N intervals
+ *   ref      device, n x m out: the extrapolated reference
+ *   err      device, n out: max over the m components of |interp - ref|
+ *   stats    device, 5 out: [0] max of err, [1] RMS of err, [2] max over
  *           samples and components of |fine - ref| (the extrapolation's
- *           correction to the fine solution, an estimate of its error)
+ *           correction to the fine solution, an estimate of its error),
+ *           [3] the mean absolute error (mean of err), [4] the mean relative
+ *           error, mean of err / max(max_c |ref|, 1e-8) (Sec. 5.1, Table 1)
  * Row-major arrays; no output may overlap an input.  A NaN in any input
- * propagates to its err entry and to stats[0..2].  n == 0 writes zeros to
- * stats.  1 <= m <= 64.  One workgroup does the whole call, in stream order. */
-int sgcm_total_error(int64_t n, int32_t m, const double* interp, const double* coarse,
+ * propagates to its err entry and to stats.  n == 0 writes zeros to stats.
+ * 1 <= m <= 64.  One workgroup does the whole call, in stream order. */
+int sgcm_total_error(int64_t n, int32_t m, int32_t order, const double* interp, const double* coarse,
                      const double* fine, double* ref, double* err, double* stats, void* stream);
 
 #ifdef __cplusplus

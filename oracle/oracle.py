@@ -300,25 +300,28 @@ def eval_comb(d: int, level: int, values, xq, lo=None, hi=None, nthreads: int | 
     return out
 
 
-def total_error(interp, coarse, fine):
+def total_error(interp, coarse, fine, order: int = 2):
     """Monte Carlo estimate of e_interp + e_bvp (Sec. 4.3): the interpolant's
     values at sample states (``interp``, n x m) against a reference solution
     that is more accurate than the solutions at the grid nodes.  The paper takes
     the reference from an error-controlled solver; here it is the Richardson
-    extrapolation of trapezoidal solutions on N (``coarse``) and 2N (``fine``)
-    intervals of the same horizon, whose global errors are c h^2 + O(h^4):
-    ref = fine + (fine - coarse) / 3 = (4 fine - coarse) / 3.
+    extrapolation of the solutions of a formula of order p on N (``coarse``)
+    and 2N (``fine``) intervals of the same horizon, whose global errors are
+    c h^p + higher order: ref = (2^p fine - coarse) / (2^p - 1) (p = 2: the
+    trapezoid; p = 6: the four-point Lobatto IIIA formula).
 
     Returns (ref, err, stats): err[i] = max_c |interp[i, c] - ref[i, c]|
-    (NaN if any term is NaN) and stats = [max err, RMS err,
-    max |fine - ref|], with zeros for an empty sample."""
+    (NaN if any term is NaN) and stats = [max err, RMS err, max |fine - ref|,
+    mean err (the MAE of Sec. 5.1), mean of err / max(max_c |ref|, 1e-8) (the
+    relative MAE)], with zeros for an empty sample."""
     interp, coarse, fine = (np.asarray(a, dtype=np.float64) for a in (interp, coarse, fine))
-    ref = (4.0 * fine - coarse) / 3.0
+    s = 2.0 ** order
+    ref = (s * fine - coarse) / (s - 1.0)
     n = interp.shape[0]
     if n == 0:
-        return ref, np.zeros(0), np.zeros(3)
+        return ref, np.zeros(0), np.zeros(5)
     err = np.max(np.abs(interp - ref), axis=1)
     corr = np.max(np.abs(fine - ref))
-    stats = np.array([np.max(err), np.sqrt(np.mean(err * err)), corr])
+    rel = err / np.maximum(np.max(np.abs(ref), axis=1), 1e-8)
+    stats = np.array([np.max(err), np.sqrt(np.mean(err * err)), corr, np.mean(err), np.mean(rel)])
     return ref, err, stats
-

@@ -25,6 +25,7 @@ SGCM_OK, SGCM_EINVAL, SGCM_ENOMEM, SGCM_EDEVICE, SGCM_EUNSUPPORTED, SGCM_ENOTCON
 CONVERGED, MAXITER, SINGULAR, NONFINITE = 0, 1, 2, 3
 MODEL_RIGID_BODY, MODEL_LINEARISED = 0, 1
 FP64, FP32 = 0, 1
+TRAPEZOID, LOBATTO4 = 0, 1  # collocation formulas (sgcm_scheme)
 
 # every extern "C" symbol declared in include/sgcm.h
 EXPORTS = ("sgcm_strerror", "sgcm_version", "sgcm_solve_bvps_workspace", "sgcm_solve_bvps", "sgcm_solve_bvps_static",
@@ -47,7 +48,8 @@ class _CProblem(ctypes.Structure):
                 ("q_w", ctypes.c_double), ("r_w", ctypes.c_double), ("p_w", ctypes.c_double),
                 ("T", ctypes.c_double), ("N", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("max_halvings", ctypes.c_int32), ("continuation", ctypes.c_int32)]
+                ("max_halvings", ctypes.c_int32), ("continuation", ctypes.c_int32),
+                ("scheme", ctypes.c_int32)]
 
 
 @dataclass
@@ -68,6 +70,7 @@ class Problem:
     n: int = 6
     max_halvings: int = 10  # backtracking cap of each counted Newton step (0: full steps)
     continuation: int = 0   # two controls: stages of the virtual-torque continuation
+    scheme: int = TRAPEZOID  # collocation formula
 
     def c(self) -> _CProblem:
         p = _CProblem()
@@ -83,6 +86,7 @@ class Problem:
         p.N, p.tol, p.max_iter = int(self.N), float(self.tol), int(self.max_iter)
         p.precision = int(self.precision)
         p.max_halvings, p.continuation = int(self.max_halvings), int(self.continuation)
+        p.scheme = int(self.scheme)
         return p
 
 
@@ -127,7 +131,7 @@ def lib() -> ctypes.CDLL:
         "sgcm_build_interpolant": (ctypes.c_int, [vp, i32, vp, vp, vp]),
         "sgcm_eval_feedback": (ctypes.c_int, [vp, i32, vp, i64, vp, vp, i32, vp]),
         "sgcm_eval_feedback_f32": (ctypes.c_int, [vp, i32, vp, i64, vp, vp, vp]),
-        "sgcm_total_error": (ctypes.c_int, [i64, i32, vp, vp, vp, vp, vp, vp, vp]),
+        "sgcm_total_error": (ctypes.c_int, [i64, i32, i32, vp, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -395,7 +399,7 @@ def sgcm_eval_feedback(grid: Grid, surplus, xq, uq, precision: int = FP64, strea
     _check(rc, "sgcm_eval_feedback")
 
 
-def sgcm_total_error(interp, coarse, fine, ref, err, stats, stream=None):
+def sgcm_total_error(interp, coarse, fine, ref, err, stats, stream=None, order: int = 2):
     import torch
     if interp.dim() != 2:
         raise ValueError("interp must be n x m")
@@ -404,9 +408,9 @@ def sgcm_total_error(interp, coarse, fine, ref, err, stats, stream=None):
         if tuple(t.shape) != (n, m):
             raise ValueError("%s must be %d x %d" % (name, n, m))
     f64 = torch.float64
-    rc = lib().sgcm_total_error(int(n), int(m), _ptr(interp, f64, "interp"), _ptr(coarse, f64, "coarse"),
-                                _ptr(fine, f64, "fine"), _ptr(ref, f64, "ref", n * m), _ptr(err, f64, "err", n),
-                                _ptr(stats, f64, "stats", 3), _stream(stream))
+    rc = lib().sgcm_total_error(int(n), int(m), int(order), _ptr(interp, f64, "interp"),
+                                _ptr(coarse, f64, "coarse"), _ptr(fine, f64, "fine"), _ptr(ref, f64, "ref", n * m),
+                                _ptr(err, f64, "err", n), _ptr(stats, f64, "stats", 5), _stream(stream))
     _check(rc, "sgcm_total_error")
 
 
@@ -538,15 +542,15 @@ def eval_feedback(grid: Grid, surplus, xq, precision: int = FP64, stream=None):
     return uq
 
 
-def total_error(interp, coarse, fine, stream=None):
+def total_error(interp, coarse, fine, stream=None, order: int = 2):
     """The total-error estimate of the interpolant at sample states: returns
-    (ref, err, stats) with ref = (4 fine - coarse) / 3 (n x m), err the
-    per-sample max error (n) and stats = [max err, RMS err, max |fine - ref|]
-    (device tensors)."""
+    (ref, err, stats) with ref = (2^p fine - coarse) / (2^p - 1) (n x m), err
+    the per-sample max error (n) and stats = [max err, RMS err,
+    max |fine - ref|, mean err, mean relative err] (device tensors)."""
     import torch
     n, m = interp.shape
     ref = torch.empty((n, m), dtype=torch.float64, device=interp.device)
     err = torch.empty((n,), dtype=torch.float64, device=interp.device)
-    stats = torch.empty((3,), dtype=torch.float64, device=interp.device)
-    sgcm_total_error(interp, coarse, fine, ref, err, stats, stream)
+    stats = torch.empty((5,), dtype=torch.float64, device=interp.device)
+    sgcm_total_error(interp, coarse, fine, ref, err, stats, stream, order)
     return ref, err, stats

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsgcm.so")
-SOURCES = ["grid.cpp", "capi.cpp", "bvp.hip", "interp.hip", "validate.hip"]
+SOURCES = ["grid.cpp", "capi.cpp", "bvp.hip", "lobatto.hip", "interp.hip", "validate.hip"]
 ARCH = os.environ.get("SGCM_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled for all device code.
@@ -26,18 +26,31 @@ def _hipcc():
     return "hipcc"
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
-    """Compile every source to an object in parallel, then link the library."""
+def _stale(obj: str, src: str, headers: list) -> bool:
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(f) > t for f in [src] + headers)
+
+
+def build(verbose: bool = False, jobs: int = 4, incremental: bool = False) -> str:
+    """Compile every source to an object in parallel, then link the library.
+    incremental: recompile only the sources (or headers) newer than their
+    objects."""
     obj_dir = os.path.join(HERE, "_build")
     os.makedirs(obj_dir, exist_ok=True)
     hipcc = _hipcc()
     common = ["-O3", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
               "-Wall"]
+    headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    headers.append(os.path.join(ROOT, "include", "sgcm.h"))
     procs, objs = [], []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(obj_dir, src + ".o")
         objs.append(obj)
+        if incremental and not _stale(obj, path, headers):
+            continue
         if src.endswith(".hip"):
             cmd = [hipcc, "-x", "hip", "--offload-arch=" + ARCH] + DEVICE_FLAGS + common + ["-c", path,
                                                                                              "-o", obj]
@@ -66,4 +79,4 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

@@ -186,27 +186,32 @@ def test_total_error_argument_validation():
     # are never dereferenced on these paths
     L = S.lib()
     p = ctypes.c_void_p(256)
-    assert L.sgcm_total_error(-1, 3, p, p, p, p, p, p, None) == S.SGCM_EINVAL   # n < 0
-    assert L.sgcm_total_error(10, 0, p, p, p, p, p, p, None) == S.SGCM_EINVAL   # m < 1
-    assert L.sgcm_total_error(10, 65, p, p, p, p, p, p, None) == S.SGCM_EINVAL  # m > 64
-    assert L.sgcm_total_error(10, 3, p, p, p, p, p, None, None) == S.SGCM_EINVAL  # no stats
-    assert L.sgcm_total_error(10, 3, None, p, p, p, p, p, None) == S.SGCM_EINVAL  # no interp
-    assert L.sgcm_total_error(10, 3, p, p, p, p, None, p, None) == S.SGCM_EINVAL  # no err
-    assert L.sgcm_total_error(2**62, 3, p, p, p, p, p, p, None) == S.SGCM_EINVAL  # n * m overflows
+    assert L.sgcm_total_error(-1, 3, 2, p, p, p, p, p, p, None) == S.SGCM_EINVAL   # n < 0
+    assert L.sgcm_total_error(10, 0, 2, p, p, p, p, p, p, None) == S.SGCM_EINVAL   # m < 1
+    assert L.sgcm_total_error(10, 65, 2, p, p, p, p, p, p, None) == S.SGCM_EINVAL  # m > 64
+    assert L.sgcm_total_error(10, 3, 0, p, p, p, p, p, p, None) == S.SGCM_EINVAL   # order < 1
+    assert L.sgcm_total_error(10, 3, 17, p, p, p, p, p, p, None) == S.SGCM_EINVAL  # order > 16
+    assert L.sgcm_total_error(10, 3, 2, p, p, p, p, p, None, None) == S.SGCM_EINVAL  # no stats
+    assert L.sgcm_total_error(10, 3, 2, None, p, p, p, p, p, None) == S.SGCM_EINVAL  # no interp
+    assert L.sgcm_total_error(10, 3, 2, p, p, p, p, None, p, None) == S.SGCM_EINVAL  # no err
+    assert L.sgcm_total_error(2**62, 3, 2, p, p, p, p, p, p, None) == S.SGCM_EINVAL  # n * m overflows
 
 
-def test_grid_upload_and_convergence_guard():
-    # the device tables are made by an explicit upload; NULL is refused
+def test_scheme_validation():
+    # the four-point Lobatto IIIA formula: FP64 only, no plans or batches
+    assert _ws(S.Problem(scheme=S.LOBATTO4), 2)[0] == S.SGCM_OK
+    assert _ws(S.Problem(scheme=7), 1)[0] == S.SGCM_EINVAL
+    assert _ws(S.Problem(scheme=S.LOBATTO4, precision=S.FP32), 1)[0] == S.SGCM_EUNSUPPORTED
+    # its workspace per BVP (stages, their Jacobians and the condensation) is
+    # larger than the trapezoid's
+    assert _ws(S.Problem(scheme=S.LOBATTO4, N=64), 1)[1] > _ws(S.Problem(N=64), 1)[1]
     L = S.lib()
-    assert L.sgcm_grid_upload(None, None) == S.SGCM_EINVAL
-    assert S.strerror(S.SGCM_ENOTCONVERGED) == "node values from a BVP that did not converge"
-    # the binding refuses to interpolate node values of a solve with a
-    # non-converged BVP (statuses read on the host; no device needed here)
-    import torch
-    S.require_converged(torch.zeros(5, dtype=torch.int32))
-    for bad in (S.MAXITER, S.SINGULAR, S.NONFINITE):
-        st = torch.zeros(5, dtype=torch.int32)
-        st[3] = bad
-        with pytest.raises(S.SgcmError) as e:
-            S.require_converged(st)
-        assert e.value.code == S.SGCM_ENOTCONVERGED
+    out = ctypes.c_void_p()
+    assert L.sgcm_plan_create(ctypes.byref(S.Problem(scheme=S.LOBATTO4).c()), None, ctypes.byref(out)) == \
+        S.SGCM_EUNSUPPORTED
+    N = np.ascontiguousarray([8], dtype=np.int32)
+    T = np.ascontiguousarray([1.0])
+    sc = S._CSchedule(1, 0)
+    assert L.sgcm_batch_create(ctypes.byref(S.Problem(scheme=S.LOBATTO4).c()), 1, N.ctypes.data_as(ctypes.c_void_p),
+                               T.ctypes.data_as(ctypes.c_void_p), ctypes.byref(sc), ctypes.byref(out)) == \
+        S.SGCM_EUNSUPPORTED

@@ -50,6 +50,12 @@ def test_total_error_hand_example():
     # |fine - ref| = [[0.25, 0.5], [0, 0.25]]
     assert stats[0] == 0.5 and stats[2] == 0.5
     assert stats[1] == np.sqrt((0.25 + 0.015625) / 2)
+    # the mean absolute error and the mean relative error (max |ref| per row: 3, 2)
+    assert stats[3] == (0.5 + 0.125) / 2
+    assert stats[4] == (0.5 / 3.0 + 0.125 / 2.0) / 2
+    # order 6: (64 fine - coarse) / 63
+    ref6, _, _ = O.total_error(interp, coarse, fine, order=6)
+    assert np.array_equal(ref6, (64.0 * fine - coarse) / 63.0)
 
 
 def test_total_error_nan_and_empty():
@@ -60,7 +66,7 @@ def test_total_error_nan_and_empty():
     assert err[0] == 0.0 and np.isnan(err[1]) and err[2] == 0.0
     assert np.isnan(stats[0]) and np.isnan(stats[1]) and stats[2] == 0.0
     ref, err, stats = O.total_error(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 3)))
-    assert ref.shape == (0, 3) and err.shape == (0,) and np.array_equal(stats, np.zeros(3))
+    assert ref.shape == (0, 3) and err.shape == (0,) and np.array_equal(stats, np.zeros(5))
 
 
 def test_richardson_reference_is_fourth_order_on_linear_model():
@@ -87,6 +93,26 @@ def test_richardson_reference_is_fourth_order_on_linear_model():
     orders = np.log2(np.array(e_fine_lam[:-1]) / np.array(e_fine_lam[1:]))
     assert np.all(np.abs(orders - 2.0) < 0.1), orders
     assert e_ref_lam[1] < 1e-2 * e_fine_lam[1]
+
+
+def test_lobatto_reference_on_linear_model():
+    # the four-point Lobatto IIIA solutions on N and 2N intervals, extrapolated
+    # at order 6: the reference is far more accurate than the fine solution,
+    # whose error the correction |fine - ref| estimates (order 6 in h)
+    T = 5.0
+    x = W.uniform_in_box(4, seed=33)
+    lam_ex = x @ lqr_P0(T).T
+    e_ref, e_fine = [], []
+    for N in (4, 8, 16):
+        c = O.solve_bvps(O.Problem(**{**linear(N, T).__dict__, "scheme": O.LOBATTO4}), x)
+        f = O.solve_bvps(O.Problem(**{**linear(2 * N, T).__dict__, "scheme": O.LOBATTO4}), x)
+        ref, _, stats = O.total_error(np.zeros_like(c.lambda0), c.lambda0, f.lambda0, order=6)
+        e_ref.append(np.abs(ref - lam_ex).max())
+        e_fine.append(np.abs(f.lambda0 - lam_ex).max())
+        assert abs(stats[2] / e_fine[-1] - 1.0) < 0.1
+    orders = np.log2(np.array(e_fine[:-1]) / np.array(e_fine[1:]))
+    assert np.all(np.abs(orders - 6.0) < 0.3), orders
+    assert np.all(np.array(e_ref) < 0.05 * np.array(e_fine))
 
 
 @pytest.mark.parametrize("level", [2, 3])
