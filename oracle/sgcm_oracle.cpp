@@ -17,8 +17,9 @@
 //     of the combination formula eq. interpolation2 (route B);
 //   * the characteristics two-point BVP of eq. hamchar at one initial state:
 //     state and costate equations evaluated at u* = argmin_u H (Sec. 2),
-//     discretised by trapezoidal collocation on a uniform mesh, solved by
-//     Newton's method from the zero trajectory, with the Jacobian from
+//     discretised by trapezoidal collocation on a uniform mesh, or by the
+//     four-point Lobatto IIIA collocation the paper uses (Sec. 3.1, Sec. 5.1),
+//     solved by Newton's method from the zero trajectory, with the Jacobian from
 //     hyper-dual (second-order forward-mode) automatic differentiation of the
 //     hand-written f, L and h only, and a plain banded LU with row partial
 //     pivoting;

@@ -301,11 +301,10 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
   const double alpha = 0.5 * h;
   const T at = (T)alpha;
   // two NP x 12 buffers: the iterate Y and the trial point Yt (swapped when a
-  // trial is taken), then the Newton step D
+  // trial is taken)
   double* Y = ws_b;
   double* Yt = ws_b + 12 * (int64_t)NP;
-  double* D = ws_b + 24 * (int64_t)NP;
-  double* R = ws_b + 36 * (int64_t)NP;  // 16: F_0 (6), F_N (6), pad
+  double* R = ws_b + 24 * (int64_t)NP;  // 16: F_0 (6), F_N (6), pad
   T* Zg = reinterpret_cast<T*>(R + 16);  // N x 84: interval solutions, 12 x 7 rows
   // point blocks [A | W | L | r_k] of every mesh point, entry-major: entry e
   // of point k at PBg[e * pbs + k]
@@ -348,12 +347,13 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
   wave_mem_sync();
 
   // Damping of the counted steps: after a linear solve the forward pass has
-  // written the step D and the full-step point Yt = Y + D; the residual pass
-  // then evaluates the trial point Y + t D (t = 1: Yt as written; t < 1:
-  // formed from Y and D and stored to Yt), which is taken when its residual
-  // is finite and max|F| <= (1 - sigma t) max|F(Y)|, or when it is the last
-  // allowed trial (t = 2^-H); else t is halved.  The first step from Y = 0
-  // (the initial guess) is taken in full.
+  // written the full-step point Yt = Y + d; the residual pass then evaluates
+  // the trial point Y + t d (t = 1: Yt as written; each halving of t moves Yt
+  // halfway back to Y in place, Yt <- Y + (Yt - Y) / 2, which is Y + t d up to
+  // rounding), which is taken when its residual is finite and
+  // max|F| <= (1 - sigma t) max|F(Y)|, or when it is the last allowed trial
+  // (t = 2^-H); else t is halved.  The first step from Y = 0 (the initial
+  // guess) is taken in full.
   bool trial = false;  // the pass evaluates a trial point
   bool full = false;   // ... that is taken without a test (the first step)
   int halvings = 0;    // trials rejected so far in this step
@@ -365,7 +365,7 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
     double lmax = 0.0;
     int bad = 0;
     bool regular = true;
-    const bool blend = trial && halvings > 0;  // the point is Y + t D, formed here
+    const bool blend = trial && halvings > 0;  // the point is Y + t d, formed here from Yt
     const double* src = trial ? Yt : Y;
     // In the first (linearised) step Y = 0, and the sweep forms its interval
     // constants from the first batch alone (every interval has the same
@@ -390,7 +390,8 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
         if (blend) {
 #pragma unroll
           for (int i = 0; i < 12; ++i) {
-            yk[i] = fma(t, D[12 * (int64_t)k + i], Y[12 * (int64_t)k + i]);
+            const double y0 = Y[12 * (int64_t)k + i];
+            yk[i] = fma(0.5, Yt[12 * (int64_t)k + i] - y0, y0);
             Yt[12 * (int64_t)k + i] = yk[i];
           }
         } else {
@@ -802,16 +803,12 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
 
     // ---- forward pass dx_0 = -F_0, dx_k = G_k dx_{k-1} + g_k,
     //      dlambda_{k-1} = P_{k-1} dx_{k-1} + c_{k-1}, dlambda_N = p_w dx_N - F_N;
-    //      the step goes to D and the full-step point Y + D to Yt ----
+    //      the full-step point Y + d goes to Yt ----
     wave_mem_sync();  // interval solutions visible to every lane
     T dx[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) dx[j] = (T)(-sh.F0[j]);
-    if (lane < 6) {
-      const double d0 = (double)dx[lane < 6 ? lane : 0];
-      D[lane] = d0;
-      Yt[lane] = Y[lane] + d0;
-    }
+    if (lane < 6) Yt[lane] = Y[lane] + (double)dx[lane < 6 ? lane : 0];
     // chunk [c0, c0 + kFwd) of interval solutions and Y rows c0 - 1 .. c0 + kFwd - 1
     // into buffer bf, direct to LDS
     auto fwd_load = [&](int c0, int bf) {
@@ -846,7 +843,6 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       const int nk = (N - c0 + 1) < kFwd ? (N - c0 + 1) : kFwd;
       const int64_t row = 12 * (int64_t)(r < 6 ? c0 : c0 - 1) + r;
       double* ytrow = Yt + row;
-      double* drow = D + row;
       // step s: row r of [G_k g_k ; P_{k-1} c_{k-1}] (z) and the Y entry
       // (yv) come from the chunk buffer
       auto fload = [&](int s, T (&z)[7], double& yv) {
@@ -860,7 +856,6 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
         const T vb = fma(z[5], dx[5], fma(z[4], dx[4], z[3] * dx[3]));
         const T v = va + vb;
         ytrow[12 * s] = yv + (double)v;
-        drow[12 * s] = (double)v;
         dx[0] = row_bcast<0>(v);
         dx[1] = row_bcast<1>(v);
         dx[2] = row_bcast<2>(v);
@@ -911,7 +906,6 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       double d = -sh.FN[i];
 #pragma unroll
       for (int j = 0; j < 6; ++j) d = fma(j == i ? P.pw : 0.0, (double)dx[j], d);
-      D[12 * (int64_t)N + 6 + i] = d;
       Yt[12 * (int64_t)N + 6 + i] = Y[12 * (int64_t)N + 6 + i] + d;
     }
     wave_mem_sync();
@@ -1079,13 +1073,13 @@ __global__ __launch_bounds__(256) void k_rhs(BvpArgs P, int64_t n, const double*
   }
 }
 
-// Workspace of one BVP in doubles, a multiple of 256 bytes: the iterate, the
-// trial point and the Newton step ((N + 1) x 12 each), F_0 and F_N (16), the
+// Workspace of one BVP in doubles, a multiple of 256 bytes: the iterate and
+// the trial point ((N + 1) x 12 each), F_0 and F_N (16), the
 // interval solutions N x 84 (in the solve's type) and the point blocks
 // kPB x pb_stride(N) (71 entries per point, in the solve's type).
 int64_t bvp_doubles(int64_t N, int fp32) {
   const int64_t esize = fp32 ? 4 : 8;
-  const int64_t d = 36 * (N + 1) + 16 + kZI * N + (kPB * pb_stride(N) * esize + 7) / 8;
+  const int64_t d = 24 * (N + 1) + 16 + kZI * N + (kPB * pb_stride(N) * esize + 7) / 8;
   return (d + 31) / 32 * 32;
 }
 
