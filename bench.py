@@ -17,6 +17,7 @@ line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -197,8 +198,8 @@ def batched_leg(dev, reps: int) -> dict:
     import torch
     import paper_1507_04769_amd as S
     from paper_1507_04769_amd import autotune as A
-    order, slots, src = A.tuned_schedule()
-    problem = A.batch_problem()
+    order, slots, nb, fc, src = A.tuned_schedule()
+    problem = A.batch_problem(nb=nb, fc=fc)
     x0h, N, T = A.batch_inputs()
     x0 = torch.tensor(x0h, device=dev)
     b = S.Batch(problem, N, T, order=order, slots_per_cu=slots)
@@ -228,10 +229,17 @@ def batched_leg(dev, reps: int) -> dict:
             "roofline": alu_roofline("k_newton_batch_grid<double>" if slots == 0 else "k_newton_batch<double>",
                                      flops, bms, PEAK_FP64_TFLOPS),
             "schedule": {"order": "larger N*T first" if order == S.ORDER_LONGEST_FIRST else "as given",
-                         "slots_per_cu": slots, "source": os.path.relpath(src, ROOT) if src else "default"},
+                         "slots_per_cu": slots, "tile": tile_info(nb, fc, src)},
             "graph": True, "ms": bms, "bvps_per_s": converged / (bms / 1e3),
             "unbatched": {"launches": ngroups, "ms": ubms, "bvps_per_s": converged / (ubms / 1e3)},
             "speedup_vs_unbatched": ubms / bms}
+
+
+def tile_info(nb: int, fc: int, src) -> dict:
+    """The solver tile a leg ran with (intervals per sweep batch and per
+    forward-pass chunk; 0 is the library default) and where it came from."""
+    return {"sweep_batch": nb or 8, "forward_chunk": fc or 12,
+            "source": os.path.relpath(src, ROOT) if src else "default"}
 
 
 def rel_rows(a, b):
@@ -266,7 +274,9 @@ def precision_leg(dev, prob, grid, x0, lam64, u064, it64, surplus, eval_flops_q:
     from oracle import oracle as O
     from paper_1507_04769_amd import autotune as A
     from paper_1507_04769_amd import workloads as W
-    p32 = dataclasses.replace(prob, precision=S.FP32)
+    nb32, fc32, src32 = A.tuned_tile("fp32", with_plan=True)
+    nb64, fc64, src64 = A.tuned_tile("fp64", with_plan=True)
+    p32 = dataclasses.replace(prob, precision=S.FP32, sweep_batch=nb32, forward_chunk=fc32)
     M = x0.shape[0]
     lam = torch.empty_like(lam64)
     u0 = torch.empty_like(u064)
@@ -274,7 +284,7 @@ def precision_leg(dev, prob, grid, x0, lam64, u064, it64, surplus, eval_flops_q:
     st = torch.empty((M,), dtype=torch.int32, device=dev)
     it = torch.empty((M,), dtype=torch.int32, device=dev)
     ws = torch.empty((S.sgcm_solve_bvps_workspace(p32, M) // 8 + 32,), dtype=torch.float64, device=dev)
-    p64 = dataclasses.replace(prob, precision=S.FP64)
+    p64 = dataclasses.replace(prob, precision=S.FP64, sweep_batch=nb64, forward_chunk=fc64)
     ws64 = torch.empty((S.sgcm_solve_bvps_workspace(p64, M) // 8 + 32,), dtype=torch.float64, device=dev)
     lam2, u02, V2 = torch.empty_like(lam), torch.empty_like(u0), torch.empty_like(V)
     st2, it2 = torch.empty_like(st), torch.empty_like(it)
@@ -293,6 +303,7 @@ def precision_leg(dev, prob, grid, x0, lam64, u064, it64, surplus, eval_flops_q:
     f32 = newton_flops(prob.N, i32, plan=True)
     rf = alu_roofline("k_newton<float>", f32, float(np.median(ms32)), PEAK_FP32_TFLOPS)
     rf["frac_of_fp64_peak"] = rf["achieved"] / PEAK_FP64_TFLOPS
+    rf["tile"] = tile_info(nb32, fc32, src32)
     solve = {"ms": float(np.median(ms32)), "fp64_ms": float(np.median(ms64)), "roofline": rf,
              "bvps_per_s": conv / (float(np.median(ms32)) / 1e3), "converged": conv,
              "mean_iters": float(i32.mean()), "fp64_mean_iters": float(i64.mean()),
@@ -482,8 +493,13 @@ def main():
     wl = W.FULL if args.workload == "full" else W.SMALL
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    from paper_1507_04769_amd import autotune as A
+    # the solver tile chosen by the autotuner for this workload (the tile
+    # changes the time only, never a result)
+    nb, fc, tile_src = A.tuned_tile("fp64") if wl.name == W.FULL.name else (0, 0, None)
     prob = S.Problem(m=wl.m, J=W.J_DIAG, B=W.input_matrix(wl.m), q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W,
-                     T=wl.horizon, N=wl.n_intervals, tol=W.TOL, max_iter=W.MAX_ITER, max_halvings=W.MAX_HALVINGS)
+                     T=wl.horizon, N=wl.n_intervals, tol=W.TOL, max_iter=W.MAX_ITER, max_halvings=W.MAX_HALVINGS,
+                     sweep_batch=nb, forward_chunk=fc)
     grid = S.Grid(6, wl.level, W.BOX_LO, W.BOX_HI)
     nodes = grid.nodes()
     M = len(grid)
@@ -540,7 +556,9 @@ def main():
         st_p, it_p = torch.empty_like(st), torch.empty_like(it)
         torch.cuda.synchronize()
         t_plan = time.perf_counter()
-        plan = S.Plan(prob, stream)
+        pnb, pfc, psrc = A.tuned_tile("fp64", with_plan=True) if wl.name == W.FULL.name else (0, 0, None)
+        pprob = dataclasses.replace(prob, sweep_batch=pnb, forward_chunk=pfc)
+        plan = S.Plan(pprob, stream)
         plan_ms = (time.perf_counter() - t_plan) * 1e3
         ev_p, _ = timed_steps(make_step(lambda: S.sgcm_solve_bvps_plan(plan, x0, lam_p, u0, V_p, traj_p, st_p, it_p,
                                                                        ws, stream)), args.steps, args.warmup, stream, 4)
@@ -555,8 +573,8 @@ def main():
                      "same_status_and_iters": bool(torch.equal(st, st_p) and torch.equal(it, it_p)),
                      "lambda0_max_rel_diff": float(((lam - lam_p).abs().amax(dim=1) /
                                                     lam.abs().amax(dim=1).clamp_min(1e-8)).max().item()),
-                     "roofline": alu_roofline("k_newton (sgcm_solve_bvps_plan)", pflops, float(np.mean(psolve)),
-                                              PEAK_FP64_TFLOPS),
+                     "roofline": {**alu_roofline("k_newton (sgcm_solve_bvps_plan)", pflops, float(np.mean(psolve)),
+                                                 PEAK_FP64_TFLOPS), "tile": tile_info(pnb, pfc, psrc)},
                      "note": "the plan is made once per problem, outside the timed steps"}
         del lam_p, u0_p, V_p, traj_p
         # the headline step's outputs feed the legs below: restore them
@@ -620,6 +638,7 @@ def main():
                      "traffic": measured_traffic() if wl.name == W.FULL.name else None,
                      "algorithmic_flops_per_launch": flops,
                      "interval_steps_per_launch": float(np.sum(wl.n_intervals * (iters + 1.0))),
+                     "tile": tile_info(nb, fc, tile_src),
                      "kernel_count": {"flops_per_launch": builder_flops,
                                       "achieved": builder_flops / (float(np.mean(solve_ms)) / 1e3) / 1e12}},
         "eval_roofline": eval_rf,

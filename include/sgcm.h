@@ -131,6 +131,13 @@ typedef struct sgcm_problem {
   int32_t continuation; /* two controls: K > 0 continuation stages (0..64; see
                         below); ignored for one or three controls             */
   int32_t scheme;    /* sgcm_scheme of the collocation                       */
+  int32_t sweep_batch;   /* tile of the trapezoidal solve: intervals per
+                        backward-sweep batch, 8 or 10 (0: 8)                 */
+  int32_t forward_chunk; /* tile of the trapezoidal solve: intervals per
+                        forward-pass chunk, 8 or 12 (0: 12).  The tiles
+                        change only the time, never a result (bit for bit);
+                        other values return SGCM_EUNSUPPORTED; the
+                        four-point formula ignores them                     */
 } sgcm_problem;
 
 /* ---- library ------------------------------------------------------------- */

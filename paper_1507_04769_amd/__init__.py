@@ -49,7 +49,8 @@ class _CProblem(ctypes.Structure):
                 ("T", ctypes.c_double), ("N", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("max_halvings", ctypes.c_int32), ("continuation", ctypes.c_int32),
-                ("scheme", ctypes.c_int32)]
+                ("scheme", ctypes.c_int32), ("sweep_batch", ctypes.c_int32),
+                ("forward_chunk", ctypes.c_int32)]
 
 
 @dataclass
@@ -71,6 +72,8 @@ class Problem:
     max_halvings: int = 10  # backtracking cap of each counted Newton step (0: full steps)
     continuation: int = 0   # two controls: stages of the virtual-torque continuation
     scheme: int = TRAPEZOID  # collocation formula
+    sweep_batch: int = 0     # tile: intervals per sweep batch (8 or 10; 0: 8)
+    forward_chunk: int = 0   # tile: intervals per forward-pass chunk (8 or 12; 0: 12)
 
     def c(self) -> _CProblem:
         p = _CProblem()
@@ -87,6 +90,7 @@ class Problem:
         p.precision = int(self.precision)
         p.max_halvings, p.continuation = int(self.max_halvings), int(self.continuation)
         p.scheme = int(self.scheme)
+        p.sweep_batch, p.forward_chunk = int(self.sweep_batch), int(self.forward_chunk)
         return p
 
 

@@ -42,6 +42,7 @@
 #include <algorithm>
 #include <cstddef>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "model.h"
@@ -104,14 +105,26 @@ __device__ __forceinline__ void g2lds16(const double* src, double* dst) {
 // banks (32 banks of 4 bytes): columns of K and Q 12 banks apart, rows of
 // [F | H | Gam'] 12 banks apart; point blocks are entry-major, so lanes that
 // read one entry of consecutive points read consecutive words.
-constexpr int kNB = 8;             // intervals per sweep batch
 constexpr int kKc = 60;            // K = [R | B | rho], column-major, 6 per column
 constexpr int kFHr = 22;           // row of F (6), H (6), Gam' (7), pad
 constexpr int kCst = kKc + 6 * kFHr + 2;  // per interval, 4 banks apart
-constexpr int kFwd = 12;           // intervals per forward-pass chunk (two chunk buffers; even)
 constexpr int kZI = 84;            // interval solution [G g ; P c], row-major 12 x 7
-constexpr int kFwdY = 12 * (kFwd + 1);     // rows of Y a chunk updates
-constexpr int kFwdBuf = kFwd * kZI + kFwdY;
+
+// Tile sizes of the solve (a launch-time choice; results do not depend on
+// them): NB intervals per sweep batch (the interval constants of a batch are
+// formed together, one lane per (interval, row pair)), FC intervals per
+// forward-pass chunk (two chunk buffers; even).  Instantiated for NB in
+// {8, 10} and FC in {8, 12}.
+template <int NB, int FC>
+struct Tile {
+  static_assert(NB >= 1 && 3 * NB <= 64, "sweep batch");
+  static_assert(FC >= 2 && FC % 2 == 0, "forward chunk");
+  static constexpr int kNB = NB;
+  static constexpr int kFwd = FC;
+  static constexpr int kFwdY = 12 * (FC + 1);        // rows of Y a chunk updates
+  static constexpr int kFwdBuf = FC * kZI + kFwdY;
+};
+constexpr int kMaxNB = 10;  // the largest sweep batch instantiated
 
 // Structural zeros of A = df/dx and W at a mesh point (both models): the
 // rates do not depend on the angles, yaw does not enter the kinematics, and
@@ -162,32 +175,35 @@ __host__ __device__ constexpr PbIndex make_pb_index() {
 __device__ constexpr PbIndex kPbIdx = make_pb_index();
 
 // Point blocks of a batch in LDS: entry e of point p0 + s at [e][s], kSP
-// points per entry (16-byte units, so p0 is a multiple of 16 / sizeof(T)
-// and the 9 points klo - 1 .. klo + 7 always fit).
-template <typename T>
+// points per entry (16-byte units, so p0 is a multiple of kU = 16 / sizeof(T)
+// and the NB + 1 points klo - 1 .. klo + NB - 1, which start less than kU
+// points after p0, always fit).
+template <typename T, int NB>
 struct PointBlockLayout {
-  static constexpr int kU = 16 / (int)sizeof(T);        // points per 16-byte unit
-  static constexpr int kSP = sizeof(T) == 8 ? 10 : 12;  // points per entry in LDS
+  static constexpr int kU = 16 / (int)sizeof(T);                 // points per 16-byte unit
+  static constexpr int kSP = (NB + kU + kU - 1) / kU * kU;       // points per entry in LDS
 };
 
-// Points per entry of a BVP's global point-block array (a multiple of 4 that
-// covers the last batch's 16-byte-aligned window).
+// Points per entry of a BVP's global point-block array: a multiple of 4
+// that holds the N + 1 mesh points and every batch's 16-byte-aligned window
+// for all instantiated tiles (a window starts at most N - NB and spans kSP
+// <= NB + 2 kU - 1 points, so it ends before N + 2 kU <= N + 8).
 __host__ __device__ inline int64_t pb_stride(int64_t N) {
-  const int64_t n = N + 4 > 12 ? N + 4 : 12;
+  const int64_t n = N + 8 > 16 ? N + 8 : 16;
   return (n + 3) / 4 * 4;
 }
 
 // T is the arithmetic type of the Newton linear solve (double, or float for
 // the FP32 inexact Newton); the residual pass and the Y rows of the forward
 // pass are FP64 in both.
-template <typename T>
+template <typename T, int NB, int FC>
 struct __align__(16) SweepShared {
   union {
     struct {
-      T pts[kPB * PointBlockLayout<T>::kSP];  // point blocks of one batch, entry-major
-      T cst[kNB * kCst];                     // interval constants of one batch
+      T pts[kPB * PointBlockLayout<T, NB>::kSP];  // point blocks of one batch, entry-major
+      T cst[NB * kCst];                          // interval constants of one batch
     } b;
-    double fwd[2 * kFwdBuf];        // forward pass: two chunks of [Z | Y rows]
+    double fwd[2 * Tile<NB, FC>::kFwdBuf];  // forward pass: two chunks of [Z | Y rows]
     double pa[2 * 64 * 12];         // residual pass: Phi and y of one 64-point chunk
   } u;
   // chain exchange buffers, one entry per lane: lane 10 i + o holds entry
@@ -287,14 +303,16 @@ __device__ __forceinline__ void bvp_outputs(const BvpArgs& P, const int N, const
 
 // Newton's method for one BVP (index b, mesh of N intervals of width h,
 // workspace ws_b) by one 64-lane workgroup.
-template <typename T>
+template <typename T, int NB, int FC>
 __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const double h, const int64_t b,
                                            const double* __restrict__ y1, double* ws_b,
                                            const double* __restrict__ x0, double* __restrict__ lam0,
                                            double* __restrict__ u0, double* __restrict__ Vout,
                                            double* __restrict__ traj, int32_t* __restrict__ status,
-                                           int32_t* __restrict__ iters, SweepShared<T>& sh) {
+                                           int32_t* __restrict__ iters, SweepShared<T, NB, FC>& sh) {
   using V2 = typename Vec2<T>::type;
+  constexpr int kNB = Tile<NB, FC>::kNB, kFwd = Tile<NB, FC>::kFwd;
+  constexpr int kFwdY = Tile<NB, FC>::kFwdY, kFwdBuf = Tile<NB, FC>::kFwdBuf;
   const int lane0 = threadIdx.x;
   const int lane = lane0;
   const int NP = N + 1;
@@ -494,10 +512,10 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
       pv = (T)((o < 6) ? (o == i ? P.pw : 0.0) : -sh.FN[i]);
     }
     // point blocks of the window of kSP points from p0 = (lo - 1) rounded
-    // down to a 16-byte unit (it covers points lo - 1 .. lo + 7) into LDS,
+    // down to a 16-byte unit (it covers points lo - 1 .. lo + kNB - 1) into LDS,
     // entry-major, by direct global-to-LDS loads: 16-byte unit u of the
     // window (entry u / (kSP / kU), part u % (kSP / kU)) to LDS unit u
-    constexpr int kU = PointBlockLayout<T>::kU, kSP = PointBlockLayout<T>::kSP;
+    constexpr int kU = PointBlockLayout<T, NB>::kU, kSP = PointBlockLayout<T, NB>::kSP;
     auto load_points = [&](int lo) {
       const int l = opaque_lane(lane0);
       const int64_t p0 = (lo - 1) / kU * kU;
@@ -534,8 +552,8 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
         // with a structural zero are skipped at compile time: those of A and
         // W, and L[3..5][0..2] = 0 (row i + 3 of L_k, column i of L_{k-1}).
         {
-          const int l = opaque_lane(lane0);
-          const int tl = l & 7, ip = l >> 3;
+          const unsigned l = (unsigned)opaque_lane(lane0);
+          const int tl = (int)(l % kNB), ip = (int)(l / kNB);
           if (ip < 3 && tl < nb) {
             const int k = khi - tl;
             const T* pa = sh.u.b.pts + (k - 1 - p0b);  // point k - 1: entry e at pa[e * kSP]
@@ -928,17 +946,17 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
   }
 }
 
-template <typename T>
+template <typename T, int NB, int FC>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_newton(
     BvpArgs P, const double* __restrict__ x0, double* __restrict__ lam0, double* __restrict__ u0,
     double* __restrict__ Vout, double* __restrict__ traj, int32_t* __restrict__ status,
     int32_t* __restrict__ iters, double* __restrict__ ws, const int32_t* __restrict__ order) {
-  __shared__ SweepShared<T> sh;
+  __shared__ SweepShared<T, NB, FC> sh;
   // the workspace is scratch: workgroup g uses slot g whatever BVP it takes,
   // so that consecutive workgroups keep consecutive memory
   const int64_t b = order ? order[blockIdx.x] : blockIdx.x;
-  newton_bvp(P, P.N, P.h, b, P.y1, ws + (int64_t)blockIdx.x * P.per_bvp, x0, lam0, u0, Vout, traj, status, iters,
-             sh);
+  newton_bvp<T, NB, FC>(P, P.N, P.h, b, P.y1, ws + (int64_t)blockIdx.x * P.per_bvp, x0, lam0, u0, Vout, traj,
+                        status, iters, sh);
 }
 
 // The order in which the workgroups of one launch take the BVPs: decreasing
@@ -1016,18 +1034,18 @@ __device__ __forceinline__ int64_t next_position(int32_t* counter) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
-template <typename T>
+template <typename T, int NB, int FC>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_newton_batch(
     BvpArgs P, BatchArgs B, const double* __restrict__ x0, double* __restrict__ lam0, double* __restrict__ u0,
     double* __restrict__ Vout, int32_t* __restrict__ status, int32_t* __restrict__ iters,
     double* __restrict__ ws) {
-  __shared__ SweepShared<T> sh;
+  __shared__ SweepShared<T, NB, FC> sh;
   int64_t pos = B.persistent ? next_position(B.counter) : (int64_t)blockIdx.x;
   while (pos < B.n) {
     const int64_t j = B.order[pos];
     const int64_t yo = B.y1off[j];
-    newton_bvp(P, B.N[j], B.h[j], j, yo >= 0 ? B.y1 + yo : nullptr, ws + B.off[j], x0, lam0, u0, Vout, nullptr,
-               status, iters, sh);
+    newton_bvp<T, NB, FC>(P, B.N[j], B.h[j], j, yo >= 0 ? B.y1 + yo : nullptr, ws + B.off[j], x0, lam0, u0,
+                          Vout, nullptr, status, iters, sh);
     if (!B.persistent) break;
     pos = next_position(B.counter);
   }
@@ -1035,20 +1053,36 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 
 // One workgroup per BVP in plan order (the form without a slot loop, which
 // keeps the registers of the loop out of the Newton solve).
-template <typename T>
+template <typename T, int NB, int FC>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_newton_batch_grid(
     BvpArgs P, BatchArgs B, const double* __restrict__ x0, double* __restrict__ lam0, double* __restrict__ u0,
     double* __restrict__ Vout, int32_t* __restrict__ status, int32_t* __restrict__ iters,
     double* __restrict__ ws) {
-  __shared__ SweepShared<T> sh;
+  __shared__ SweepShared<T, NB, FC> sh;
   const int64_t j = B.order[blockIdx.x];
   const int64_t yo = B.y1off[j];
-  newton_bvp(P, B.N[j], B.h[j], j, yo >= 0 ? B.y1 + yo : nullptr, ws + B.off[j], x0, lam0, u0, Vout, nullptr,
-             status, iters, sh);
+  newton_bvp<T, NB, FC>(P, B.N[j], B.h[j], j, yo >= 0 ? B.y1 + yo : nullptr, ws + B.off[j], x0, lam0, u0, Vout,
+                        nullptr, status, iters, sh);
 }
 
 __global__ void k_reset_counter(int32_t* counter) {
   if (threadIdx.x == 0) *counter = 0;
+}
+
+// Calls f(NB, FC) with the instantiated tile (as integral constants) that
+// matches the arguments' sweep batch and forward chunk.
+template <int V>
+using Int = std::integral_constant<int, V>;
+template <class F>
+void with_tile(const BvpArgs& a, F&& f) {
+  if (a.nb == 10 && a.fc == 12)
+    f(Int<10>{}, Int<12>{});
+  else if (a.nb == 8 && a.fc == 8)
+    f(Int<8>{}, Int<8>{});
+  else if (a.nb == 10 && a.fc == 8)
+    f(Int<10>{}, Int<8>{});
+  else
+    f(Int<8>{}, Int<12>{});
 }
 
 __global__ __launch_bounds__(256) void k_rhs(BvpArgs P, int64_t n, const double* __restrict__ y,
@@ -1102,6 +1136,10 @@ int make_bvp_args(const sgcm_problem* p, BvpArgs* a) {
   if (p->continuation < 0 || p->continuation > 64) return SGCM_EINVAL;
   if (p->scheme != SGCM_TRAPEZOID && p->scheme != SGCM_LOBATTO4) return SGCM_EINVAL;
   if (p->scheme == SGCM_LOBATTO4 && p->precision != SGCM_FP64) return SGCM_EUNSUPPORTED;
+  if (p->sweep_batch < 0 || p->forward_chunk < 0) return SGCM_EINVAL;
+  if ((p->sweep_batch != 0 && p->sweep_batch != 8 && p->sweep_batch != 10) ||
+      (p->forward_chunk != 0 && p->forward_chunk != 8 && p->forward_chunk != 12))
+    return SGCM_EUNSUPPORTED;
   a->model = p->model;
   a->m = p->m;
   a->N = p->N;
@@ -1167,6 +1205,8 @@ int make_bvp_args(const sgcm_problem* p, BvpArgs* a) {
   }
   a->y1 = nullptr;
   a->max_halvings = p->max_halvings;
+  a->nb = p->sweep_batch ? p->sweep_batch : 8;
+  a->fc = p->forward_chunk ? p->forward_chunk : 12;
   a->resume = 0;
   a->keep = 0;
   a->outputs = 1;
@@ -1257,12 +1297,15 @@ static int solve_bvps(const sgcm_problem* p, const double* y1, int64_t n_bvps, c
         return SGCM_EDEVICE;
       continue;
     }
-    if (a.fp32)
-      hipLaunchKernelGGL(k_newton<float>, dim3((unsigned)n_bvps), dim3(64), 0, s, a, x0, lambda0, u0, V, traj,
-                         status, iters, (double*)workspace, order);
-    else
-      hipLaunchKernelGGL(k_newton<double>, dim3((unsigned)n_bvps), dim3(64), 0, s, a, x0, lambda0, u0, V, traj,
-                         status, iters, (double*)workspace, order);
+    with_tile(a, [&](auto nb, auto fc) {
+      constexpr int NB = decltype(nb)::value, FC = decltype(fc)::value;
+      if (a.fp32)
+        hipLaunchKernelGGL((k_newton<float, NB, FC>), dim3((unsigned)n_bvps), dim3(64), 0, s, a, x0, lambda0, u0, V,
+                           traj, status, iters, (double*)workspace, order);
+      else
+        hipLaunchKernelGGL((k_newton<double, NB, FC>), dim3((unsigned)n_bvps), dim3(64), 0, s, a, x0, lambda0, u0,
+                           V, traj, status, iters, (double*)workspace, order);
+    });
     if (hipGetLastError() != hipSuccess) return SGCM_EDEVICE;
   }
   return SGCM_OK;
@@ -1584,19 +1627,22 @@ extern "C" int sgcm_solve_bvps_batch(const sgcm_batch* b, const double* x0, doub
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b->counter);
   }
   const unsigned g = (unsigned)(B.persistent ? (b->slots < b->n ? b->slots : b->n) : b->n);
-  if (!B.persistent) {
-    if (b->args.fp32)
-      hipLaunchKernelGGL(k_newton_batch_grid<float>, dim3(g), dim3(64), 0, s, b->args, B, x0, lambda0, u0, V,
+  with_tile(b->args, [&](auto nb, auto fc) {
+    constexpr int NB = decltype(nb)::value, FC = decltype(fc)::value;
+    if (!B.persistent) {
+      if (b->args.fp32)
+        hipLaunchKernelGGL((k_newton_batch_grid<float, NB, FC>), dim3(g), dim3(64), 0, s, b->args, B, x0, lambda0,
+                           u0, V, status, iters, (double*)workspace);
+      else
+        hipLaunchKernelGGL((k_newton_batch_grid<double, NB, FC>), dim3(g), dim3(64), 0, s, b->args, B, x0, lambda0,
+                           u0, V, status, iters, (double*)workspace);
+    } else if (b->args.fp32)
+      hipLaunchKernelGGL((k_newton_batch<float, NB, FC>), dim3(g), dim3(64), 0, s, b->args, B, x0, lambda0, u0, V,
                          status, iters, (double*)workspace);
     else
-      hipLaunchKernelGGL(k_newton_batch_grid<double>, dim3(g), dim3(64), 0, s, b->args, B, x0, lambda0, u0, V,
+      hipLaunchKernelGGL((k_newton_batch<double, NB, FC>), dim3(g), dim3(64), 0, s, b->args, B, x0, lambda0, u0, V,
                          status, iters, (double*)workspace);
-  } else if (b->args.fp32)
-    hipLaunchKernelGGL(k_newton_batch<float>, dim3(g), dim3(64), 0, s, b->args, B, x0, lambda0, u0, V, status,
-                       iters, (double*)workspace);
-  else
-    hipLaunchKernelGGL(k_newton_batch<double>, dim3(g), dim3(64), 0, s, b->args, B, x0, lambda0, u0, V, status,
-                       iters, (double*)workspace);
+  });
   return hipGetLastError() == hipSuccess ? SGCM_OK : SGCM_EDEVICE;
 }
 

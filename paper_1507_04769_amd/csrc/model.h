@@ -35,6 +35,7 @@ struct BvpArgs {
   int outputs;  // 1: write lambda0, u0, V and traj (the last stage)
   int scheme;   // sgcm_scheme of the collocation
   double lob[4][4];  // the four-point Lobatto IIIA tableau (SGCM_LOBATTO4)
+  int nb, fc;   // tile sizes of the trapezoidal solve: sweep batch, forward chunk
 };
 
 // Sufficient-decrease constant of the backtracking test

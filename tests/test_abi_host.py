@@ -215,3 +215,15 @@ def test_scheme_validation():
     assert L.sgcm_batch_create(ctypes.byref(S.Problem(scheme=S.LOBATTO4).c()), 1, N.ctypes.data_as(ctypes.c_void_p),
                                T.ctypes.data_as(ctypes.c_void_p), ctypes.byref(sc), ctypes.byref(out)) == \
         S.SGCM_EUNSUPPORTED
+
+
+def test_tile_validation():
+    # the tiles of the trapezoidal solve: sweep batch 8 or 10, forward chunk 8
+    # or 12 (0: the defaults); they do not change the workspace
+    for nb in (0, 8, 10):
+        for fc in (0, 8, 12):
+            assert _ws(S.Problem(sweep_batch=nb, forward_chunk=fc), 5) == _ws(S.Problem(), 5), (nb, fc)
+    for kw in (dict(sweep_batch=-1), dict(forward_chunk=-8)):
+        assert _ws(S.Problem(**kw), 1)[0] == S.SGCM_EINVAL, kw
+    for kw in (dict(sweep_batch=9), dict(sweep_batch=16), dict(forward_chunk=10), dict(forward_chunk=16)):
+        assert _ws(S.Problem(**kw), 1)[0] == S.SGCM_EUNSUPPORTED, kw

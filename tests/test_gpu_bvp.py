@@ -6,6 +6,8 @@ iteration count bit-exact; lambda(0), u(0), V and the trajectory within
 Inputs: the sparse-grid nodes (oracle grid) of the rigid-body workloads and
 seeded uniform states; every call goes through the C ABI of libsgcm.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -299,3 +301,42 @@ def test_launch_above_the_ordered_size():
     pick = np.r_[0:8, 4090:4100]
     o = O.solve_bvps(op, x0[pick])
     assert_parity({k: a[k][pick] for k in a}, o)
+
+
+TILES = ((8, 12), (10, 12), (8, 8), (10, 8))
+
+
+@pytest.mark.parametrize("precision", [S.FP64, S.FP32])
+def test_tiles_do_not_change_results(precision):
+    # every instantiated (sweep batch, forward chunk) gives the same bits: the
+    # level-3 grid on N = 100 (a ragged last batch and chunk for every tile),
+    # and damped two-wheel solves with continuation on N = 37, where
+    # backtracking and the resumed stages run too; and the batch kernels
+    cases = [(dict(N=100, T=20.0), O.grid(6, 3, W.BOX_LO, W.BOX_HI).nodes),
+             (dict(m=2, N=37, T=5.0, max_iter=40, continuation=2), W.uniform_in_box(48, seed=140))]
+    for kw, xs in cases:
+        ref = None
+        for nb, fc in TILES:
+            gp = dataclasses.replace(problems(**kw)[0], precision=precision, sweep_batch=nb, forward_chunk=fc)
+            g = gpu_solve(gp, xs)
+            if ref is None:
+                ref = g
+                continue
+            for k in ref:
+                assert np.array_equal(ref[k], g[k], equal_nan=True), (nb, fc, k)
+    torch = _torch()
+    x0 = O.grid(6, 3, W.BOX_LO, W.BOX_HI).nodes[:300]
+    N = np.resize(np.array([37, 64, 100], dtype=np.int32), len(x0))
+    T = np.resize(np.array([5.0, 20.0]), len(x0))
+    ref = None
+    for nb, fc in TILES:
+        gp = dataclasses.replace(problems()[0], precision=precision, sweep_batch=nb, forward_chunk=fc)
+        b = S.Batch(gp, N, T)
+        r = S.solve_bvps_batch(b, torch.tensor(x0, device="cuda"))
+        torch.cuda.synchronize()
+        g = {k: getattr(r, k).cpu().numpy() for k in ("lambda0", "u0", "V", "status", "iters")}
+        if ref is None:
+            ref = g
+            continue
+        for k in ref:
+            assert np.array_equal(ref[k], g[k]), ("batch", nb, fc, k)
