@@ -132,7 +132,7 @@ typedef struct sgcm_problem {
                         below); ignored for one or three controls             */
   int32_t scheme;    /* sgcm_scheme of the collocation                       */
   int32_t sweep_batch;   /* tile of the trapezoidal solve: intervals per
-                        backward-sweep batch, 8 or 10 (0: 8)                 */
+                        backward-sweep batch, 8, 10, 12 or 16 (0: 8)         */
   int32_t forward_chunk; /* tile of the trapezoidal solve: intervals per
                         forward-pass chunk, 8 or 12 (0: 12).  The tiles
                         change only the time, never a result (bit for bit);

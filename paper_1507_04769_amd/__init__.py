@@ -72,7 +72,7 @@ class Problem:
     max_halvings: int = 10  # backtracking cap of each counted Newton step (0: full steps)
     continuation: int = 0   # two controls: stages of the virtual-torque continuation
     scheme: int = TRAPEZOID  # collocation formula
-    sweep_batch: int = 0     # tile: intervals per sweep batch (8 or 10; 0: 8)
+    sweep_batch: int = 0     # tile: intervals per sweep batch (8, 10, 12 or 16; 0: 8)
     forward_chunk: int = 0   # tile: intervals per forward-pass chunk (8 or 12; 0: 12)
 
     def c(self) -> _CProblem:

@@ -31,7 +31,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "tuned", "batch_%s.json" % W.BATCH.name)
 SOLVE_OUT = os.path.join(HERE, "tuned", "solve_%s.json" % W.FULL.name)
 # solver tiles: (intervals per sweep batch, intervals per forward-pass chunk)
-TILES = ((8, 12), (10, 12), (8, 8), (10, 8))
+TILES = ((8, 12), (10, 12), (12, 12), (16, 12), (8, 8), (10, 8), (12, 8), (16, 8))
 CANDIDATES = [(order, slots, nb, fc) for order in (S.ORDER_GIVEN, S.ORDER_LONGEST_FIRST)
               for slots in (0, 1, 2, 3, 4, 5, 6) for nb, fc in TILES]
 

@@ -114,7 +114,7 @@ constexpr int kZI = 84;            // interval solution [G g ; P c], row-major 1
 // them): NB intervals per sweep batch (the interval constants of a batch are
 // formed together, one lane per (interval, row pair)), FC intervals per
 // forward-pass chunk (two chunk buffers; even).  Instantiated for NB in
-// {8, 10} and FC in {8, 12}.
+// {8, 10, 12, 16} and FC in {8, 12}.
 template <int NB, int FC>
 struct Tile {
   static_assert(NB >= 1 && 3 * NB <= 64, "sweep batch");
@@ -124,7 +124,6 @@ struct Tile {
   static constexpr int kFwdY = 12 * (FC + 1);        // rows of Y a chunk updates
   static constexpr int kFwdBuf = FC * kZI + kFwdY;
 };
-constexpr int kMaxNB = 10;  // the largest sweep batch instantiated
 
 // Structural zeros of A = df/dx and W at a mesh point (both models): the
 // rates do not depend on the angles, yaw does not enter the kinematics, and
@@ -1073,16 +1072,21 @@ __global__ void k_reset_counter(int32_t* counter) {
 // matches the arguments' sweep batch and forward chunk.
 template <int V>
 using Int = std::integral_constant<int, V>;
+template <int NB, class F>
+void with_chunk(const BvpArgs& a, F&& f) {
+  if (a.fc == 8)
+    f(Int<NB>{}, Int<8>{});
+  else
+    f(Int<NB>{}, Int<12>{});
+}
 template <class F>
 void with_tile(const BvpArgs& a, F&& f) {
-  if (a.nb == 10 && a.fc == 12)
-    f(Int<10>{}, Int<12>{});
-  else if (a.nb == 8 && a.fc == 8)
-    f(Int<8>{}, Int<8>{});
-  else if (a.nb == 10 && a.fc == 8)
-    f(Int<10>{}, Int<8>{});
-  else
-    f(Int<8>{}, Int<12>{});
+  switch (a.nb) {
+    case 10: with_chunk<10>(a, f); break;
+    case 12: with_chunk<12>(a, f); break;
+    case 16: with_chunk<16>(a, f); break;
+    default: with_chunk<8>(a, f); break;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_rhs(BvpArgs P, int64_t n, const double* __restrict__ y,
@@ -1137,7 +1141,8 @@ int make_bvp_args(const sgcm_problem* p, BvpArgs* a) {
   if (p->scheme != SGCM_TRAPEZOID && p->scheme != SGCM_LOBATTO4) return SGCM_EINVAL;
   if (p->scheme == SGCM_LOBATTO4 && p->precision != SGCM_FP64) return SGCM_EUNSUPPORTED;
   if (p->sweep_batch < 0 || p->forward_chunk < 0) return SGCM_EINVAL;
-  if ((p->sweep_batch != 0 && p->sweep_batch != 8 && p->sweep_batch != 10) ||
+  if ((p->sweep_batch != 0 && p->sweep_batch != 8 && p->sweep_batch != 10 && p->sweep_batch != 12 &&
+       p->sweep_batch != 16) ||
       (p->forward_chunk != 0 && p->forward_chunk != 8 && p->forward_chunk != 12))
     return SGCM_EUNSUPPORTED;
   a->model = p->model;

@@ -16,17 +16,28 @@ resident on the device, in FP64 or FP32).  The loop
     footprint: states, outputs and workspace of the launch), so that requests
     arriving while others run are admitted as slots and memory free up and
     their work overlaps on the device;
-  * retires launches whose completion event has fired and hands every request
+  * caps the streams one class of work may hold at once (two-wheel solves,
+    whose continuation can run for hundreds of Newton iterations, take at
+    most half of them), so that short work (queries, three-wheel solves)
+    always finds a stream instead of queueing behind long launches;
+  * retires launches as their completion events fire and hands every request
     its slice of the outputs.
 
-Every output of a request depends only on that request's inputs (BVPs and
-query points are independent), so a request's results are the same alone and
-in any mix; the tests check this bitwise.  Latency = completion - arrival on
-the host clock (completions are seen by polling events).
+Completions are event driven: one waiter thread per stream watches the
+completion event of each launch of its stream in launch order (launches on
+one stream complete in order; the event is queried every 50 us, since a
+blocking wait in the runtime delayed the launches issued meanwhile on other
+streams) and hands the launch to the loop, which sleeps until a completion
+or the next arrival.  Every output of
+a request depends only on that request's inputs (BVPs and query points are
+independent), so a request's results are the same alone and in any mix; the
+tests check this bitwise.  Latency = completion - arrival on the host clock.
 """
 from __future__ import annotations
 
 import dataclasses
+import queue
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -103,6 +114,15 @@ class _Launch:
     event: object
     nbytes: int
     outs: tuple
+    cls: str = ""
+
+
+def work_class(key) -> str:
+    """Class of a launch key for the stream caps: "query", "solve" (three
+    wheels) or "solve-2wheel"."""
+    if key[0] == "query":
+        return "query"
+    return "solve-2wheel" if key[1] == 2 else "solve"
 
 
 def request_size(r) -> int:
@@ -121,32 +141,51 @@ def footprint(key, n: int) -> int:
 class Admission:
     """Which pending requests start next (host-side policy).
 
-    The oldest pending request leads (first come, first served, so nothing
-    starves); later pending requests with the same key join it while the
-    merged launch stays within its size cap and the device memory of all
-    launches in flight within the budget.  If the oldest request does not fit
-    next to the launches in flight, nothing starts until memory frees up; a
-    request larger than the whole budget starts alone on an idle device."""
+    The oldest pending request whose class holds fewer streams than its cap
+    leads (first come, first served within a class, so nothing starves);
+    later pending requests with the same key join it while the merged launch
+    stays within its size cap and the device memory of all launches in
+    flight within the budget.  If the leading request does not fit next to
+    the launches in flight, nothing starts until memory frees up; a request
+    larger than the whole budget starts alone on an idle device.
+    stream_caps: class (`work_class`) -> most streams it may hold at once;
+    size_caps: class -> most states of one merged launch (below max_bvps or
+    max_points); classes not named are not capped."""
 
     def __init__(self, hbm_budget: int, max_bvps: int = 2048, max_points: int = 1 << 20,
-                 merge: bool = True, footprint=footprint):
+                 merge: bool = True, footprint=footprint, stream_caps: dict | None = None,
+                 size_caps: dict | None = None):
         self.budget = int(hbm_budget)
         self.max_bvps = max_bvps
         self.max_points = max_points
         self.merge = merge
         self.footprint = footprint
+        self.caps = dict(stream_caps or {})
+        self.size_caps = dict(size_caps or {})
 
-    def select(self, pending: list, used: int):
-        """(key, chosen requests, merged size, bytes) or None."""
-        if not pending:
+    def select(self, pending: list, used: int, busy: dict | None = None, avail=None):
+        """(key, chosen requests, merged size, bytes) or None.  busy: class ->
+        streams it holds now; avail: the classes that have a free stream now
+        (None: all)."""
+        busy = busy or {}
+        lead = None
+        for j, r in enumerate(pending):
+            c = work_class(r.key())
+            if avail is not None and c not in avail:
+                continue
+            if c not in self.caps or busy.get(c, 0) < self.caps[c]:
+                lead = j
+                break
+        if lead is None:
             return None
-        key = pending[0].key()
+        key = pending[lead].key()
         cap = self.max_bvps if key[0] == "solve" else self.max_points
-        chosen, n = [pending[0]], request_size(pending[0])
+        cap = min(cap, self.size_caps.get(work_class(key), cap))
+        chosen, n = [pending[lead]], request_size(pending[lead])
         if used > 0 and used + self.footprint(key, n) > self.budget:
             return None
         if self.merge:
-            for r in pending[1:]:
+            for r in pending[lead + 1:]:
                 if r.key() != key:
                     continue
                 k = request_size(r)
@@ -165,17 +204,24 @@ def solve_plan(key) -> S.Plan:
 
 class Server:
     def __init__(self, interpolants: dict, n_streams: int = 4, hbm_budget: int = 1 << 30,
-                 max_bvps: int = 2048, max_points: int = 1 << 20, merge: bool = True, plans: dict | None = None):
+                 max_bvps: int = 2048, max_points: int = 1 << 20, merge: bool = True, plans: dict | None = None,
+                 stream_caps: dict | None = None, size_caps: dict | None = None):
         """interpolants: level -> resident Interpolant; n_streams: launches in
         flight at once; hbm_budget: device bytes the launches in flight may
         hold; max_bvps / max_points: size cap of one merged launch;
         merge=False serves one request per launch; plans: solve key -> solve
         plan (each solve launch forms its first Newton steps from its key's
-        plan; a missing plan is made at the key's first launch)."""
+        plan; a missing plan is made at the key's first launch);
+        stream_caps: class -> most streams it may hold (default: two-wheel
+        solves at most half of the streams, at least one); size_caps: class
+        -> most states of one launch (default: none)."""
         import torch
         self.plans = {} if plans is None else dict(plans)
         self.interp = interpolants
-        self.admit = Admission(hbm_budget, max_bvps, max_points, merge)
+        if stream_caps is None:
+            stream_caps = {"solve-2wheel": max(1, n_streams // 2)}
+        self.admit = Admission(hbm_budget, max_bvps, max_points, merge, stream_caps=stream_caps,
+                               size_caps=size_caps)
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
         self.dev = torch.device("cuda")
 
@@ -213,9 +259,9 @@ class Server:
                     S.sgcm_eval_feedback(itp.grid, itp.w64, x, uq, S.FP64, stream)
                 outs = (uq.to("cpu", non_blocking=True),)
                 keep = (xh, x, uq)
-            ev = torch.cuda.Event()
+            ev = torch.cuda.Event(blocking=True)  # a host wait on it sleeps instead of spinning
             ev.record(stream)
-        L = _Launch(reqs, stream, ev, footprint(key, n), outs)
+        L = _Launch(reqs, stream, ev, footprint(key, n), outs, work_class(key))
         L.keep = keep  # device buffers stay referenced until the launch retires
         return L
 
@@ -238,6 +284,14 @@ class Server:
                 r.done = now
                 i += k
 
+    def _wait(self, L: _Launch):
+        """Return in the calling (waiter) thread once the launch has
+        completed.  The event is queried every 50 us: a blocking
+        hipEventSynchronize in the waiter threads delayed the launches the
+        loop issued meanwhile on other streams."""
+        while not L.event.query():
+            time.sleep(50e-6)
+
     def run(self, requests: list, realtime: bool = True) -> dict:
         """Serve the requests (sorted by arrival).  realtime: inject each
         request at its arrival time on the host clock; else all at once."""
@@ -245,48 +299,89 @@ class Server:
         pending, inflight = [], []
         free = list(self.streams)
         used = peak_used = peak_shared = peak_inflight = 0
+        busy = {}
         i = 0
         launches = 0
+        done = queue.Queue()  # launches whose completion event has fired
+        todo = {id(st): queue.Queue() for st in self.streams}
+
+        def wait_stream(q):
+            while True:
+                L = q.get()
+                if L is None:
+                    return
+                self._wait(L)
+                done.put((L, time.perf_counter()))
+
+        waiters = [threading.Thread(target=wait_stream, args=(todo[id(st)],), daemon=True) for st in self.streams]
+        for th in waiters:
+            th.start()
         t0 = time.perf_counter()
-        while i < len(reqs) or pending or inflight:
-            now = time.perf_counter() - t0
-            while i < len(reqs) and (not realtime or reqs[i].arrival <= now):
-                pending.append(reqs[i])
-                i += 1
-            for L in list(inflight):
-                if L.event.query():
-                    self._retire(L, time.perf_counter() - t0)
+        try:
+            while i < len(reqs) or pending or inflight:
+                now = time.perf_counter() - t0
+                while i < len(reqs) and (not realtime or reqs[i].arrival <= now):
+                    pending.append(reqs[i])
+                    i += 1
+                while free and pending:
+                    g = self.admit.select(pending, used, busy)
+                    if g is None:
+                        break
+                    key, chosen, n, _ = g
+                    L = self._launch(key, chosen, n, free.pop(0))
+                    for r in chosen:
+                        pending.remove(r)
+                    inflight.append(L)
+                    todo[id(L.stream)].put(L)
+                    busy[L.cls] = busy.get(L.cls, 0) + 1
+                    used += L.nbytes
+                    launches += 1
+                    peak_used = max(peak_used, used)
+                    peak_inflight = max(peak_inflight, len(inflight))
+                    if len(inflight) > 1:
+                        peak_shared = max(peak_shared, used)
+                # sleep until a launch completes or the next request arrives
+                timeout = None
+                if realtime and i < len(reqs):
+                    timeout = max(0.0, reqs[i].arrival - (time.perf_counter() - t0))
+                if not inflight:
+                    if timeout:
+                        time.sleep(timeout)
+                    continue
+                try:
+                    item = done.get(timeout=timeout)
+                except queue.Empty:
+                    continue
+                while item is not None:
+                    L, t_done = item
+                    self._retire(L, t_done - t0)
                     inflight.remove(L)
                     free.append(L.stream)
+                    busy[L.cls] -= 1
                     used -= L.nbytes
-            started = False
-            while free and pending:
-                g = self.admit.select(pending, used)
-                if g is None:
-                    break
-                key, chosen, n, _ = g
-                L = self._launch(key, chosen, n, free.pop(0))
-                for r in chosen:
-                    pending.remove(r)
-                inflight.append(L)
-                used += L.nbytes
-                launches += 1
-                started = True
-                peak_used = max(peak_used, used)
-                peak_inflight = max(peak_inflight, len(inflight))
-                if len(inflight) > 1:
-                    peak_shared = max(peak_shared, used)
-            if not started and not (i < len(reqs) and (not realtime or reqs[i].arrival <= now)):
-                time.sleep(20e-6)
+                    try:
+                        item = done.get_nowait()
+                    except queue.Empty:
+                        item = None
+        finally:
+            for st in self.streams:
+                todo[id(st)].put(None)
+            for th in waiters:
+                th.join()
         wall = time.perf_counter() - t0
         lat = np.array([r.done - (r.arrival if realtime else 0.0) for r in reqs]) * 1e3
+        cls = np.array([work_class(r.key()) for r in reqs])
+        by_class = {c: {"requests": int(np.sum(cls == c)),
+                        "p50": float(np.percentile(lat[cls == c], 50)),
+                        "p99": float(np.percentile(lat[cls == c], 99))}
+                    for c in ("query", "solve", "solve-2wheel") if np.any(cls == c)}
         n_bvps = sum(len(r.x0) for r in reqs if isinstance(r, SolveRequest))
         n_pts = sum(len(r.xq) for r in reqs if isinstance(r, QueryRequest))
         return {"requests": len(reqs), "launches": launches, "wall_s": wall,
                 "peak_inflight": peak_inflight, "peak_inflight_bytes": peak_used,
                 "peak_shared_bytes": peak_shared,
                 "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                               "max": float(lat.max())},
+                               "max": float(lat.max()), "by_class": by_class},
                 "throughput": {"requests_per_s": len(reqs) / wall, "bvps_per_s": n_bvps / wall,
                                "evals_per_s": n_pts / wall}}
 

@@ -40,7 +40,8 @@ class TotalError:
     ref_V: "object"     # n x 1 extrapolated reference value V(0, x), or None
     err_V: "object"     # n, or None
     stats_V: "object"   # 5, or None
-    status: "object"    # 2 x n: status of the solves on N_r and 2 N_r intervals
+    status: "object"    # 2 x n: status of the solves on N_r and 2 N_r intervals (all
+                        # CONVERGED: the estimator raises SGCM_ENOTCONVERGED otherwise)
     iters: "object"     # 2 x n
     n_ref: int = 0      # the accepted N_r
     correction: float = 0.0  # the accepted reference's estimated error (max over u and V)
@@ -94,5 +95,8 @@ class Estimator:
                 break
             n_r *= 2
             c = f
-        return TotalError(ref_u, err_u, st_u, ref_V, err_V, st_V, torch.stack([c.status, f.status]),
-                          torch.stack([c.iters, f.iters]), n_r, corr)
+        status = torch.stack([c.status, f.status])
+        bad = int((status != S.CONVERGED).sum().item())
+        if bad:  # a reference that did not converge is no reference
+            raise S.SgcmError(S.SGCM_ENOTCONVERGED, "total-error reference (%d of %d solves)" % (bad, status.numel()))
+        return TotalError(ref_u, err_u, st_u, ref_V, err_V, st_V, status, torch.stack([c.iters, f.iters]), n_r, corr)

@@ -218,12 +218,13 @@ def test_scheme_validation():
 
 
 def test_tile_validation():
-    # the tiles of the trapezoidal solve: sweep batch 8 or 10, forward chunk 8
+    # the tiles of the trapezoidal solve: sweep batch 8, 10, 12 or 16, forward chunk 8
     # or 12 (0: the defaults); they do not change the workspace
-    for nb in (0, 8, 10):
+    for nb in (0, 8, 10, 12, 16):
         for fc in (0, 8, 12):
             assert _ws(S.Problem(sweep_batch=nb, forward_chunk=fc), 5) == _ws(S.Problem(), 5), (nb, fc)
     for kw in (dict(sweep_batch=-1), dict(forward_chunk=-8)):
         assert _ws(S.Problem(**kw), 1)[0] == S.SGCM_EINVAL, kw
-    for kw in (dict(sweep_batch=9), dict(sweep_batch=16), dict(forward_chunk=10), dict(forward_chunk=16)):
+    for kw in (dict(sweep_batch=9), dict(sweep_batch=14), dict(sweep_batch=20), dict(forward_chunk=10),
+               dict(forward_chunk=16)):
         assert _ws(S.Problem(**kw), 1)[0] == S.SGCM_EUNSUPPORTED, kw

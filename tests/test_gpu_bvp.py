@@ -303,7 +303,7 @@ def test_launch_above_the_ordered_size():
     assert_parity({k: a[k][pick] for k in a}, o)
 
 
-TILES = ((8, 12), (10, 12), (8, 8), (10, 8))
+TILES = ((8, 12), (10, 12), (12, 12), (16, 12), (8, 8), (10, 8), (12, 8), (16, 8))
 
 
 @pytest.mark.parametrize("precision", [S.FP64, S.FP32])

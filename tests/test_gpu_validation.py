@@ -16,6 +16,8 @@
   and far below the error it measures, and a sample of states is checked
   against the oracle one by one.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -187,3 +189,16 @@ def test_estimate_empty_and_single_sample(n):
         # one sample: the max and the RMS are its error
         e = r.err_u.cpu().numpy()[0]
         assert su[0] == e and abs(su[1] - e) <= 1e-15 * e
+
+
+def test_estimator_refuses_non_converged_references():
+    # a reference solve that stops at max_iter is no reference: the estimator
+    # raises SGCM_ENOTCONVERGED instead of reporting statistics from it
+    grid, nodes, sol, w_u, w_V = device_interpolants(2, 64)
+    xs = W.uniform_in_box(32, seed=712)
+    p = dataclasses.replace(problem(64), max_iter=0)
+    for scheme in (S.TRAPEZOID, S.LOBATTO4):
+        est = VA.Estimator(p, 32, scheme=scheme, max_ref=128)
+        with pytest.raises(S.SgcmError) as e:
+            est(grid, w_u, gpu(xs), w_V)
+        assert e.value.code == S.SGCM_ENOTCONVERGED

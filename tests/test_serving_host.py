@@ -74,3 +74,27 @@ def test_request_stream_is_seeded_and_in_range():
             assert 1 <= len(r.xq) <= 100_000 and r.level in (3, 4, 5)
     kinds = {type(r).__name__ for r in a}
     assert kinds == {"SolveRequest", "QueryRequest"}
+
+
+def test_stream_caps_let_other_classes_lead():
+    a = SV.Admission(hbm_budget=10**9, footprint=unit_footprint, stream_caps={"solve-2wheel": 1})
+    pend = [solve(0, 4, m=2), solve(1, 3, m=2), query(2, 5), solve(3, 2)]
+    key, chosen, _, _ = a.select(pend, used=0, busy={})
+    assert SV.work_class(key) == "solve-2wheel" and [r.rid for r in chosen] == [0, 1]
+    # with the two-wheel class at its cap the oldest request of another class leads
+    key, chosen, _, _ = a.select(pend, used=0, busy={"solve-2wheel": 1})
+    assert key == ("query", 4, False) and [r.rid for r in chosen] == [2]
+    assert a.select(pend[:2], used=0, busy={"solve-2wheel": 1}) is None
+    assert SV.work_class(("solve", 3, 64, 20.0)) == "solve"
+
+
+def test_available_classes():
+    a = SV.Admission(hbm_budget=10**9, footprint=unit_footprint)
+    pend = [solve(0, 4, m=2), query(1, 5), solve(2, 3)]
+    # the two-wheel class has no free stream: the oldest request of a class that has one leads
+    key, chosen, _, _ = a.select(pend, used=0, busy={}, avail={"query", "solve"})
+    assert key == ("query", 4, False) and [r.rid for r in chosen] == [1]
+    assert a.select(pend[:1], used=0, busy={}, avail={"query", "solve"}) is None
+    b = SV.Admission(hbm_budget=10**9, footprint=unit_footprint, size_caps={"solve-2wheel": 5})
+    _, chosen, n, _ = b.select([solve(0, 4, m=2), solve(1, 3, m=2)], used=0)
+    assert [r.rid for r in chosen] == [0] and n == 4  # 4 + 3 would pass the class's size cap
