@@ -176,7 +176,15 @@ int sgcm_solve_bvps_workspace(const sgcm_problem* p, int64_t n_bvps, size_t* byt
  * the last iterate.  The call is stream-ordered on `stream`.  For
  * n_bvps <= 4096 the BVPs are handed to workgroups in decreasing order of
  * |x0|_1 (a predictor of their Newton iterations, so that the longest start
- * first); each BVP's outputs do not depend on that order. */
+ * first); each BVP's outputs do not depend on that order.
+ * First steps: the first Newton step is linear in the initial state (the
+ * residual at Y = 0 is [-x0; 0; 0] and the Jacobian does not depend on x0).
+ * With the trapezoid and n_bvps >= 64 the call therefore solves the first
+ * steps of the six unit initial states first (a launch of six workgroups, in
+ * the workspace) and forms every BVP's step as their combination; the
+ * results are those of sgcm_solve_bvps_plan with a plan of the same problem,
+ * bit for bit, and differ from a BVP's own first step by rounding only.  If
+ * those six steps are singular or not finite, every BVP takes its own. */
 int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const double* x0,
                     double* lambda0, double* u0, double* V, double* traj,
                     int32_t* status, int32_t* iters, void* workspace,

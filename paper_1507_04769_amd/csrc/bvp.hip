@@ -300,6 +300,18 @@ __device__ __forceinline__ void bvp_outputs(const BvpArgs& P, const int N, const
   }
 }
 
+// Whether the first steps of the unit initial states made inside the call
+// may be combined (the rule sgcm_plan_create checks on the host); a null
+// check stands for a plan that was checked there.
+__device__ __forceinline__ bool plan_steps_valid(const int32_t* __restrict__ chk) {
+  if (!chk) return true;
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 6; ++j)
+    ok &= (chk[j] == SGCM_BVP_CONVERGED || chk[j] == SGCM_BVP_MAXITER) && chk[6 + j] == 0;
+  return ok;
+}
+
 // Newton's method for one BVP (index b, mesh of N intervals of width h,
 // workspace ws_b) by one 64-lane workgroup.
 template <typename T, int NB, int FC>
@@ -345,7 +357,7 @@ __device__ __forceinline__ void newton_bvp(const BvpArgs& P, const int N, const 
   int it = -1, st = SGCM_BVP_MAXITER;
   if (P.resume) {
     it = 0;
-  } else if (y1) {
+  } else if (y1 && plan_steps_valid(P.y1_check)) {
     double xb[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) xb[j] = x0[b * 6 + j];
@@ -1209,6 +1221,7 @@ int make_bvp_args(const sgcm_problem* p, BvpArgs* a) {
       for (int j = 0; j < 4; ++j) a->lob[i][j] = lob[i][j];
   }
   a->y1 = nullptr;
+  a->y1_check = nullptr;
   a->max_halvings = p->max_halvings;
   a->nb = p->sweep_batch ? p->sweep_batch : 8;
   a->fc = p->forward_chunk ? p->forward_chunk : 12;
@@ -1247,12 +1260,60 @@ sgcm_problem stage_problem(const sgcm_problem* p, int k) {
 
 using namespace sgcm;
 
+// The first Newton steps made inside a call.  The step from Y = 0 is linear
+// in the initial state (the residual there is [-xbar; 0; 0] and the Jacobian
+// does not depend on xbar), so a call with many BVPs solves the six unit
+// initial states first, in a launch of six workgroups, and every BVP forms its
+// step as their combination: the long serial sweep of the first step then runs
+// once, on an idle device, instead of in every workgroup of the main launch.
+// The results are those of a solve with a plan of the same problem.
+constexpr int64_t kInCallPlanMin = 64;  // BVPs per call from which this pays
+
+struct InCallPlan {
+  size_t unit_ws, x0, y1, lam, u0, chk, total;  // byte offsets in the region, its size
+};
+
+// The region behind the BVP workspaces and the launch order, or total = 0
+// when the call takes its first steps per BVP.
+static InCallPlan in_call_plan(const sgcm_problem* p, int64_t n_bvps) {
+  InCallPlan r{};
+  if (p->scheme != SGCM_TRAPEZOID || n_bvps < kInCallPlanMin) return r;
+  sgcm_problem q = stage_problem(p, 0);
+  q.precision = SGCM_FP64;
+  q.max_iter = 0;
+  BvpArgs qa;
+  if (make_bvp_args(&q, &qa) != SGCM_OK) return r;
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  size_t o = 0;
+  r.unit_ws = o;
+  o += up((size_t)qa.per_bvp * sizeof(double) * 6 + order_bytes(6));
+  r.x0 = o;
+  o += up(36 * sizeof(double));
+  r.y1 = o;
+  o += up((size_t)6 * 12 * ((size_t)p->N + 1) * sizeof(double));
+  r.lam = o;
+  o += up(36 * sizeof(double));
+  r.u0 = o;
+  o += up(18 * sizeof(double));
+  r.chk = o;
+  o += up(12 * sizeof(int32_t));
+  r.total = o;
+  return r;
+}
+
+// The six unit initial states (rows of the 6 x 6 identity).
+__global__ void k_unit_states(double* x0) {
+  const int t = threadIdx.x;
+  if (t < 36) x0[t] = (t / 6 == t % 6) ? 1.0 : 0.0;
+}
+
 extern "C" int sgcm_solve_bvps_workspace(const sgcm_problem* p, int64_t n_bvps, size_t* bytes) {
   BvpArgs a;
   if (!bytes || n_bvps < 0) return SGCM_EINVAL;
   int rc = make_bvp_args(p, &a);
   if (rc != SGCM_OK) return rc;
-  *bytes = (size_t)a.per_bvp * sizeof(double) * (size_t)n_bvps + order_bytes(n_bvps);
+  *bytes = (size_t)a.per_bvp * sizeof(double) * (size_t)n_bvps + order_bytes(n_bvps) +
+           in_call_plan(p, n_bvps).total;
   return SGCM_OK;
 }
 
@@ -1270,7 +1331,8 @@ static int solve_bvps(const sgcm_problem* p, const double* y1, int64_t n_bvps, c
   if (!x0 || !lambda0 || !u0 || !status || !iters || !workspace) return SGCM_EINVAL;
   if (((uintptr_t)workspace & 255u) != 0) return SGCM_EINVAL;
   const size_t bvp_bytes = (size_t)a.per_bvp * sizeof(double) * (size_t)n_bvps;
-  if (ws_bytes < bvp_bytes + order_bytes(n_bvps)) return SGCM_EINVAL;
+  const InCallPlan icp = y1 ? InCallPlan{} : in_call_plan(p, n_bvps);
+  if (ws_bytes < bvp_bytes + order_bytes(n_bvps) + icp.total) return SGCM_EINVAL;
   const int K = continuation_stages(p);
   if (K > 0) {  // the torque plane needs a normal: B_1 and B_2 not parallel
     const double* B1 = p->B;
@@ -1280,6 +1342,25 @@ static int solve_bvps(const sgcm_problem* p, const double* y1, int64_t n_bvps, c
     if (!(c0 * c0 + c1 * c1 + c2 * c2 > 0.0)) return SGCM_EINVAL;
   }
   hipStream_t s = (hipStream_t)stream;
+  const int32_t* y1_check = nullptr;
+  if (icp.total > 0) {  // the first steps of the unit initial states, in this call
+    char* base = reinterpret_cast<char*>(workspace) + bvp_bytes + order_bytes(n_bvps);
+    sgcm_problem q = stage_problem(p, 0);
+    q.precision = SGCM_FP64;
+    q.max_iter = 0;
+    double* ux0 = reinterpret_cast<double*>(base + icp.x0);
+    double* uy1 = reinterpret_cast<double*>(base + icp.y1);
+    int32_t* chk = reinterpret_cast<int32_t*>(base + icp.chk);
+    hipLaunchKernelGGL(k_unit_states, dim3(1), dim3(64), 0, s, ux0);
+    rc = solve_bvps(&q, nullptr, 6, ux0, reinterpret_cast<double*>(base + icp.lam),
+                    reinterpret_cast<double*>(base + icp.u0), nullptr, uy1, chk, chk + 6, base + icp.unit_ws,
+                    icp.x0 - icp.unit_ws, stream);
+    if (rc != SGCM_OK) return rc;
+    y1 = uy1;
+    y1_check = chk;
+    a.y1 = y1;
+    a.y1_check = y1_check;
+  }
   int32_t* order = nullptr;
   if (n_bvps > 1 && n_bvps <= kOrderMax) {
     order = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(workspace) + bvp_bytes);
@@ -1293,6 +1374,7 @@ static int solve_bvps(const sgcm_problem* p, const double* y1, int64_t n_bvps, c
       rc = make_bvp_args(&q, &a);
       if (rc != SGCM_OK) return rc;
       a.y1 = k == 0 ? y1 : nullptr;
+      a.y1_check = k == 0 ? y1_check : nullptr;
       a.resume = k > 0;
       a.keep = k < K;
       a.outputs = k == K;

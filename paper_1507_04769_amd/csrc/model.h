@@ -23,6 +23,11 @@ struct BvpArgs {
   // A solve plan's first Newton steps for the six unit initial states, 6 x
   // (N + 1) x 12 (device), or null: then each BVP takes its own first step.
   const double* y1;
+  // Statuses and iteration counts (6 + 6, device) of the solves that made y1
+  // inside this call, or null (a plan checked on the host): y1 is used only
+  // if every one took its first step and nothing more (status CONVERGED or
+  // MAXITER after 0 iterations), else each BVP takes its own first step.
+  const int32_t* y1_check;
   int sinv;         // 1: S_w is invertible and Si holds its inverse
   int fp32;         // 1: Newton linear solve in FP32 (inexact Newton)
   double Si[9];

@@ -291,11 +291,12 @@ def test_results_do_not_depend_on_input_order():
 def test_launch_above_the_ordered_size():
     # a launch of more than 4096 BVPs takes them in input order (no launch
     # order is formed); each BVP's outputs must equal those of the same BVP
-    # in ordered launches of at most 4096, and the oracle's on a sample
+    # in ordered launches of at most 4096 (both of at least 64 BVPs, so that
+    # all three form the first steps in the call), and the oracle's on a sample
     gp, op = problems(N=8, T=2.0)
     x0 = W.uniform_in_box(4100, seed=118)
     a = gpu_solve(gp, x0)
-    b0, b1 = gpu_solve(gp, x0[:4096]), gpu_solve(gp, x0[4096:])
+    b0, b1 = gpu_solve(gp, x0[:4036]), gpu_solve(gp, x0[4036:])
     for k in ("lambda0", "u0", "V", "traj", "status", "iters"):
         assert np.array_equal(a[k], np.concatenate([b0[k], b1[k]])), k
     pick = np.r_[0:8, 4090:4100]

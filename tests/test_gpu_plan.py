@@ -153,3 +153,30 @@ def test_plan_reuse_streams_and_determinism():
     a, b = solve(gp, xa, plan=plan, stream=s1), solve(gp, xb, plan=plan, stream=s2)
     for k in KEYS:
         assert np.array_equal(a[k], ref_a[k]) and np.array_equal(b[k], ref_b[k]), k
+
+
+def test_in_call_first_steps_equal_an_explicit_plan():
+    # from 64 BVPs a call solves the first steps of the six unit initial
+    # states itself and combines them: the results are those of the same
+    # solve with a plan of the problem, bit for bit (FP64 and FP32, a ragged
+    # mesh, two wheels with continuation, a non-finite initial state); one
+    # BVP fewer, each BVP takes its own first step (same statuses and
+    # iterations, values equal to rounding)
+    import dataclasses
+    cases = [(problems(N=100, T=20.0)[0], W.uniform_in_box(64, seed=161)),
+             (problems(N=37, T=5.0, precision=S.FP32)[0], W.uniform_in_box(70, seed=162)),
+             (dataclasses.replace(problems(m=2, N=40, T=20.0, max_iter=60)[0], continuation=3),
+              W.uniform_in_box(64, seed=163))]
+    for gp, x0 in cases:
+        x0 = x0.copy()
+        x0[5, 1] = np.nan
+        a = solve(gp, x0)
+        b = solve(gp, x0, plan=S.Plan(gp))
+        for k in KEYS:
+            assert np.array_equal(a[k], b[k], equal_nan=True), k
+        assert a["status"][5] == S.NONFINITE
+    gp, op = problems(N=64, T=20.0)
+    x0 = W.uniform_in_box(64, seed=164)
+    a, c = solve(gp, x0), solve(gp, x0[:63])
+    assert_same_as_unplanned({k: v[:63] for k, v in a.items()}, c)
+    assert_parity(a, O.solve_bvps(op, x0, want_traj=True))
