@@ -235,6 +235,17 @@ def batched_leg(dev, reps: int) -> dict:
             "speedup_vs_unbatched": ubms / bms}
 
 
+def swept_steps_roofline(N: int, iters: np.ndarray, n_bvps: int, ms: float) -> dict:
+    """The one-shot solve counted by the interval steps it sweeps: with 64 or
+    more BVPs the call solves the first steps of the six unit initial states
+    and every BVP combines them, so it sweeps N (sum of iterations + 6)
+    steps; below 64 every BVP sweeps its own first step too."""
+    steps = float(N * (np.sum(iters) + 6)) if n_bvps >= 64 else float(np.sum(N * (iters + 1.0)))
+    flops = FLOPS_PER_INTERVAL_STEP * steps
+    achieved = flops / (ms / 1e3) / 1e12
+    return {"interval_steps": steps, "flops": flops, "achieved": achieved, "frac": achieved / PEAK_FP64_TFLOPS}
+
+
 def tile_info(nb: int, fc: int, src) -> dict:
     """The solver tile a leg ran with (intervals per sweep batch and per
     forward-pass chunk; 0 is the library default) and where it came from."""
@@ -645,6 +656,10 @@ def main():
                      "traffic": measured_traffic() if wl.name == W.FULL.name else None,
                      "algorithmic_flops_per_launch": flops,
                      "interval_steps_per_launch": float(np.sum(wl.n_intervals * (iters + 1.0))),
+                     # the steps the call actually sweeps when it forms the
+                     # first steps from the six unit states (the survey's
+                     # count above charges every BVP its own first step)
+                     "swept": swept_steps_roofline(wl.n_intervals, iters, M, float(np.mean(solve_ms))),
                      "tile": tile_info(nb, fc, tile_src),
                      "kernel_count": {"flops_per_launch": builder_flops,
                                       "achieved": builder_flops / (float(np.mean(solve_ms)) / 1e3) / 1e12}},
