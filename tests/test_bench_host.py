@@ -72,3 +72,16 @@ def test_eval_flops_per_query_survey_counts():
 def test_cpu_model_is_named():
     B = load_bench()
     assert isinstance(B.cpu_model(), str) and B.cpu_model()
+
+
+def test_swept_steps_by_hand():
+    B = load_bench()
+    iters = np.array([0, 2, 3, 4] * 16)  # 64 BVPs: the call forms the first steps from six unit solves
+    r = B.swept_steps_roofline(256, iters, len(iters), 1.0)
+    assert r["interval_steps"] == 256 * (iters.sum() + 6)
+    assert np.isclose(r["flops"], 6500.0 * r["interval_steps"])
+    assert np.isclose(r["achieved"], r["flops"] / 1e-3 / 1e12) and np.isclose(r["frac"], r["achieved"] / 78.6)
+    # below 64 BVPs every BVP sweeps its own first step: the survey count
+    small = B.swept_steps_roofline(256, iters[:63], 63, 1.0)
+    assert small["interval_steps"] == 256 * (iters[:63] + 1).sum()
+    assert np.isclose(small["flops"], B.newton_flops(256, iters[:63]))
