@@ -657,8 +657,8 @@ def main():
                      "algorithmic_flops_per_launch": flops,
                      "interval_steps_per_launch": float(np.sum(wl.n_intervals * (iters + 1.0))),
                      # the steps the call actually sweeps when it forms the
-                     # first steps from the six unit states (the survey's
-                     # count above charges every BVP its own first step)
+                     # first steps from the six unit states (the count above,
+                     # 6.5 kflop per step, charges every BVP its own first step)
                      "swept": swept_steps_roofline(wl.n_intervals, iters, M, float(np.mean(solve_ms))),
                      "tile": tile_info(nb, fc, tile_src),
                      "kernel_count": {"flops_per_launch": builder_flops,

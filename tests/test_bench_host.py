@@ -58,7 +58,7 @@ def test_newton_flops_per_interval_step():
     assert B.newton_flops(np.array([64, 128]), np.array([0, 2])) == 6500.0 * (64 + 128 * 3)
 
 
-def test_eval_flops_per_query_survey_counts():
+def test_eval_flops_per_query_algorithmic_counts():
     # 2 m M + sum over nodes of (non-trivial dimensions - 1) + 6 x 5 flops per
     # point of X^2..X^{level+1}: 810, 3,344, 12,242 and 40,928 flops per query
     # (m = 3) at levels 2..5
@@ -81,7 +81,7 @@ def test_swept_steps_by_hand():
     assert r["interval_steps"] == 256 * (iters.sum() + 6)
     assert np.isclose(r["flops"], 6500.0 * r["interval_steps"])
     assert np.isclose(r["achieved"], r["flops"] / 1e-3 / 1e12) and np.isclose(r["frac"], r["achieved"] / 78.6)
-    # below 64 BVPs every BVP sweeps its own first step: the survey count
+    # below 64 BVPs every BVP sweeps its own first step: the per-BVP count
     small = B.swept_steps_roofline(256, iters[:63], 63, 1.0)
     assert small["interval_steps"] == 256 * (iters[:63] + 1).sum()
     assert np.isclose(small["flops"], B.newton_flops(256, iters[:63]))
