@@ -550,7 +550,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-validation", action="store_true", help="skip the total-error estimate leg")
     ap.add_argument("--serving-requests", type=int, default=2000)
-    ap.add_argument("--serving-rate", type=float, default=500.0, help="requests per second")
+    ap.add_argument("--serving-rate", type=float, default=250.0, help="requests per second")
     ap.add_argument("--no-plan-compare", action="store_true",
                     help="skip the step with a solve plan (profiling runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
