@@ -202,7 +202,7 @@ int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const double* x0,
  * looked up on the first call on a device).  A call whose workspace
  * (sgcm_solve_bvps_workspace of the same problem and count) exceeds it
  * returns SGCM_EUNSUPPORTED before any device work: at N = 256 that allows
- * about 180 BVPs per call.  Arguments, outputs and the other errors as for
+ * about 174 BVPs per call.  Arguments, outputs and the other errors as for
  * sgcm_solve_bvps.  Every call on a device uses the same array: calls that
  * overlap on one device (other streams, other threads) race and give wrong
  * results; order them.  No part of the array needs clearing between calls
