@@ -164,6 +164,7 @@ def test_in_call_first_steps_equal_an_explicit_plan():
     # iterations, values equal to rounding)
     import dataclasses
     cases = [(problems(N=100, T=20.0)[0], W.uniform_in_box(64, seed=161)),
+             (problems(N=1, T=0.5, max_iter=0)[0], W.uniform_in_box(65, seed=165)),
              (problems(N=37, T=5.0, precision=S.FP32)[0], W.uniform_in_box(70, seed=162)),
              (dataclasses.replace(problems(m=2, N=40, T=20.0, max_iter=60)[0], continuation=3),
               W.uniform_in_box(64, seed=163))]
