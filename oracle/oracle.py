@@ -92,7 +92,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        _lib = ctypes.CDLL(build())
+        # SGCM_ORACLE_LIB: another build of the same source (the host
+        # sanitizer test loads an AddressSanitizer build this way)
+        _lib = ctypes.CDLL(os.environ.get("SGCM_ORACLE_LIB") or build())
         P = ctypes.POINTER(_Problem)
         d = ctypes.POINTER(ctypes.c_double)
         i32 = ctypes.POINTER(ctypes.c_int32)
