@@ -72,7 +72,9 @@ def build(verbose: bool = False, jobs: int = 4, incremental: bool = False) -> st
         msg = "\n".join("== %s ==\n%s" % f for f in failed)
         raise RuntimeError("libsgcm build failed:\n" + msg)
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+    cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + [
+        "-L" + rocm_lib, "-Wl,-rpath," + rocm_lib, "-lrocprofiler-sdk-roctx"]  # roctx ranges of the C-ABI calls
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

@@ -47,6 +47,7 @@
 
 #include "model.h"
 #include "sgcm_internal.h"
+#include "trace.h"
 
 namespace sgcm {
 namespace {
@@ -1401,6 +1402,7 @@ static int solve_bvps(const sgcm_problem* p, const double* y1, int64_t n_bvps, c
 extern "C" int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const double* x0, double* lambda0,
                                double* u0, double* V, double* traj, int32_t* status, int32_t* iters,
                                void* workspace, size_t ws_bytes, void* stream) {
+  sgcm::CallRange range("sgcm_solve_bvps");
   return solve_bvps(p, nullptr, n_bvps, x0, lambda0, u0, V, traj, status, iters, workspace, ws_bytes, stream);
 }
 
@@ -1494,6 +1496,7 @@ static int first_steps(const sgcm_problem* p, double* y1, hipStream_t s) {
 }
 
 extern "C" int sgcm_plan_create(const sgcm_problem* p, void* stream, sgcm_plan** out) {
+  sgcm::CallRange range("sgcm_plan_create");
   if (!out) return SGCM_EINVAL;
   *out = nullptr;
   BvpArgs a;
@@ -1528,6 +1531,7 @@ extern "C" int sgcm_plan_create(const sgcm_problem* p, void* stream, sgcm_plan**
 extern "C" int sgcm_solve_bvps_plan(const sgcm_plan* plan, int64_t n_bvps, const double* x0, double* lambda0,
                                     double* u0, double* V, double* traj, int32_t* status, int32_t* iters,
                                     void* workspace, size_t ws_bytes, void* stream) {
+  sgcm::CallRange range("sgcm_solve_bvps_plan");
   if (!plan) return SGCM_EINVAL;
   if (n_bvps > 0) {
     int dev = -1;
@@ -1546,6 +1550,7 @@ extern "C" void sgcm_plan_destroy(sgcm_plan* plan) {
 
 extern "C" int sgcm_characteristic_rhs(const sgcm_problem* p, int64_t n_points, const double* y, double* phi,
                                        double* dphi, void* stream) {
+  sgcm::CallRange range("sgcm_characteristic_rhs");
   BvpArgs a;
   if (n_points < 0) return SGCM_EINVAL;
   int rc = make_bvp_args(p, &a);
@@ -1583,6 +1588,7 @@ struct sgcm_batch {
 
 extern "C" int sgcm_batch_create(const sgcm_problem* p, int64_t n_bvps, const int32_t* N, const double* T,
                                  const sgcm_schedule* sched, sgcm_batch** out) {
+  sgcm::CallRange range("sgcm_batch_create");
   if (!out) return SGCM_EINVAL;
   *out = nullptr;
   if (!p || n_bvps < 1 || n_bvps > 0x7fffffffLL || !N || !T) return SGCM_EINVAL;
@@ -1694,6 +1700,7 @@ extern "C" int sgcm_batch_workspace(const sgcm_batch* b, size_t* bytes) {
 extern "C" int sgcm_solve_bvps_batch(const sgcm_batch* b, const double* x0, double* lambda0, double* u0,
                                      double* V, int32_t* status, int32_t* iters, void* workspace,
                                      size_t ws_bytes, void* stream) {
+  sgcm::CallRange range("sgcm_solve_bvps_batch");
   if (!b || !x0 || !lambda0 || !u0 || !status || !iters || !workspace) return SGCM_EINVAL;
   if (((uintptr_t)workspace & 255u) != 0 || ws_bytes < b->ws_doubles * sizeof(double)) return SGCM_EINVAL;
   int dev = -1;

@@ -21,6 +21,7 @@
 #include <cstdio>
 
 #include "sgcm_internal.h"
+#include "trace.h"
 
 namespace sgcm {
 namespace {
@@ -737,6 +738,7 @@ using namespace sgcm;
 
 extern "C" int sgcm_build_interpolant(const sgcm_grid* gh, int32_t m, const double* values,
                                       double* surplus, void* stream) {
+  sgcm::CallRange range("sgcm_build_interpolant");
   if (!gh || m < 1 || m > 64 || !values || !surplus || values == surplus) return SGCM_EINVAL;
   Grid& G = const_cast<Grid&>(gh->g);
   int dev = 0;
@@ -763,6 +765,7 @@ extern "C" int sgcm_build_interpolant(const sgcm_grid* gh, int32_t m, const doub
 
 extern "C" int sgcm_eval_feedback(const sgcm_grid* gh, int32_t m, const double* surplus, int64_t n_q,
                                   const double* xq, double* uq, int32_t precision, void* stream) {
+  sgcm::CallRange range("sgcm_eval_feedback");
   if (!gh || m < 1 || m > 64 || n_q < 0) return SGCM_EINVAL;
   if (precision != SGCM_FP64 && precision != SGCM_FP32) return SGCM_EINVAL;
   if (precision != SGCM_FP64) return SGCM_EUNSUPPORTED;
@@ -787,6 +790,7 @@ extern "C" int sgcm_eval_feedback(const sgcm_grid* gh, int32_t m, const double* 
 
 extern "C" int sgcm_eval_feedback_f32(const sgcm_grid* gh, int32_t m, const float* surplus, int64_t n_q,
                                       const float* xq, float* uq, void* stream) {
+  sgcm::CallRange range("sgcm_eval_feedback_f32");
   if (!gh || m < 1 || m > 64 || n_q < 0) return SGCM_EINVAL;
   if (n_q == 0) return SGCM_OK;
   if (!surplus || !xq || !uq) return SGCM_EINVAL;
@@ -803,6 +807,7 @@ extern "C" int sgcm_eval_feedback_f32(const sgcm_grid* gh, int32_t m, const floa
 }
 
 extern "C" int sgcm_grid_upload(sgcm_grid* gh, void* stream) {
+  sgcm::CallRange range("sgcm_grid_upload");
   if (!gh) return SGCM_EINVAL;
   int dev = 0;
   const int rc = current_device(&dev);

@@ -15,6 +15,7 @@
 #include <cmath>
 
 #include "sgcm_internal.h"
+#include "trace.h"
 
 namespace sgcm {
 namespace {
@@ -98,6 +99,7 @@ __global__ __launch_bounds__(kThreads) void k_total_error(int64_t n, int m, doub
 
 extern "C" int sgcm_total_error(int64_t n, int32_t m, int32_t order, const double* interp, const double* coarse,
                                 const double* fine, double* ref, double* err, double* stats, void* stream) {
+  sgcm::CallRange range("sgcm_total_error");
   if (n < 0 || m < 1 || m > 64 || !stats) return SGCM_EINVAL;
   if (order < 1 || order > 16) return SGCM_EINVAL;
   if (n > 0 && (!interp || !coarse || !fine || !ref || !err)) return SGCM_EINVAL;
