@@ -190,6 +190,66 @@ def cpu_baseline(args, nodes: np.ndarray, xq: np.ndarray) -> dict:
                          "sample": "%d seeded BVPs of the grid and %d queries, median of 3 runs" % (len(pick), nq1)}}
 
 
+def small_leg(dev, steps: int, warmup: int, with_cpu: bool) -> dict:
+    """The small workload (level-2 grid, 85 BVPs, N = 64, 1e3 queries): the
+    same one-shot step on the GPU, and the oracle on all of it (all host
+    threads and one thread, median of 3 runs)."""
+    import torch
+    import paper_1507_04769_amd as S
+    from paper_1507_04769_amd import workloads as W
+    wl = W.SMALL
+    prob = S.Problem(m=wl.m, J=W.J_DIAG, B=W.input_matrix(wl.m), q_w=W.Q_W, r_w=W.R_W, p_w=W.P_W,
+                     T=wl.horizon, N=wl.n_intervals, tol=W.TOL, max_iter=W.MAX_ITER, max_halvings=W.MAX_HALVINGS)
+    grid = S.Grid(6, wl.level, W.BOX_LO, W.BOX_HI)
+    nodes = grid.nodes()
+    M = len(grid)
+    xq_host = W.query_points(wl)
+    x0, xq = torch.tensor(nodes, device=dev), torch.tensor(xq_host, device=dev)
+    lam = torch.empty((M, 6), dtype=torch.float64, device=dev)
+    u0 = torch.empty((M, wl.m), dtype=torch.float64, device=dev)
+    V = torch.empty((M,), dtype=torch.float64, device=dev)
+    traj = torch.empty((M, wl.n_intervals + 1, 12), dtype=torch.float64, device=dev)
+    st = torch.empty((M,), dtype=torch.int32, device=dev)
+    it = torch.empty((M,), dtype=torch.int32, device=dev)
+    ws = torch.empty((S.sgcm_solve_bvps_workspace(prob, M) // 8 + 32,), dtype=torch.float64, device=dev)
+    surplus = torch.empty((M, wl.m), dtype=torch.float64, device=dev)
+    uq = torch.empty((len(xq_host), wl.m), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    grid.upload(stream)
+
+    def step(ev):
+        if ev is not None:
+            ev[0].record(stream)
+        S.sgcm_solve_bvps(prob, x0, lam, u0, V, traj, st, it, ws, stream)
+        S.sgcm_build_interpolant(grid, u0, surplus, stream)
+        S.sgcm_eval_feedback(grid, surplus, xq, uq, S.FP64, stream)
+        if ev is not None:
+            ev[1].record(stream)
+
+    events, _ = timed_steps(step, steps, warmup, stream, 2)
+    ms = np.array([e[0].elapsed_time(e[1]) for e in events])
+    conv = int((st == S.CONVERGED).sum().item())
+    out = {"workload": wl.name, "grid_nodes": M, "intervals": wl.n_intervals, "queries": len(xq_host),
+           "value": conv * steps / (float(np.sum(ms)) / 1e3), "unit": "BVPs/s", "ms_per_step": float(np.mean(ms)),
+           "converged": conv}
+    if with_cpu:
+        from oracle import oracle as O
+        op = O.Problem(N=wl.n_intervals, T=wl.horizon, max_halvings=W.MAX_HALVINGS)
+        cpu = {}
+        for name, threads in (("all_threads", O.default_threads()), ("one_core", 1)):
+            t = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                r = O.solve_bvps(op, nodes, nthreads=threads)
+                w = O.build_surplus(6, wl.level, r.u0, nthreads=threads)
+                O.eval_hier(6, wl.level, w, xq_host, W.BOX_LO, W.BOX_HI, nthreads=threads)
+                t.append(time.perf_counter() - t0)
+            cpu[name] = {"cores": threads, "ms_per_step": float(np.median(t)) * 1e3,
+                         "bvps_per_s": int(np.sum(r.status == O.CONVERGED)) / float(np.median(t))}
+        out["cpu_oracle"] = cpu
+    return out
+
+
 def batched_leg(dev, reps: int) -> dict:
     """The mixed batch (3072 level-5 nodes + 1024 uniform states, N in
     {64..512}, T in {10, 20, 40}): one persistent launch with the autotuned
@@ -544,6 +604,7 @@ def main():
     ap.add_argument("--workload", choices=["full", "small"], default="full")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pipelined", action="store_true", help="skip the two-stream pipelined steps")
+    ap.add_argument("--no-small", action="store_true", help="skip the small-workload line")
     ap.add_argument("--cpu-queries", type=int, default=20000)
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-batch leg")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32 and underactuated legs")
@@ -670,6 +731,10 @@ def main():
         ref_u0, ref_uq = u0.clone(), uq.clone()
         pipelined = pipelined_leg(prob, grid, x0, xq, wl.m, args.steps, args.warmup, ref_u0, ref_uq)
 
+    small = None
+    if args.workload == "full" and not args.no_small:
+        small = small_leg(dev, args.steps, args.warmup, not args.no_cpu_baseline)
+
     batched = None if args.no_batched or args.workload != "full" else batched_leg(dev, 5)
     precision = underactuated = None
     if not args.no_precision and args.workload == "full":
@@ -737,6 +802,8 @@ def main():
         out["with_plan"] = with_plan
     if pipelined is not None:
         out["pipelined"] = pipelined
+    if small is not None:
+        out["small_workload"] = small
     if batched is not None:
         out["batched"] = batched
     if precision is not None:
