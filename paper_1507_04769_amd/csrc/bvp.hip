@@ -1263,15 +1263,16 @@ using namespace sgcm;
 
 // The first Newton steps made inside a call.  The step from Y = 0 is linear
 // in the initial state (the residual there is [-xbar; 0; 0] and the Jacobian
-// does not depend on xbar), so a call with many BVPs solves the six unit
-// initial states first, in a launch of six workgroups, and every BVP forms its
-// step as their combination: the long serial sweep of the first step then runs
-// once, on an idle device, instead of in every workgroup of the main launch.
-// The results are those of a solve with a plan of the same problem.
+// does not depend on xbar), so a call with many BVPs first computes the steps
+// of the six unit initial states by doubling (about log2 N dependent steps of
+// 6 x 6 algebra, first_steps.hip), and every BVP forms its step as their
+// combination: no workgroup of the main launch takes the long serial sweep of
+// that step.  The results are those of a solve with a plan of the same
+// problem.
 constexpr int64_t kInCallPlanMin = 64;  // BVPs per call from which this pays
 
 struct InCallPlan {
-  size_t unit_ws, x0, y1, lam, u0, chk, total;  // byte offsets in the region, its size
+  size_t table, y1, chk, total;  // byte offsets in the region, its size
 };
 
 // The region behind the BVP workspaces and the launch order, or total = 0
@@ -1279,33 +1280,24 @@ struct InCallPlan {
 static InCallPlan in_call_plan(const sgcm_problem* p, int64_t n_bvps) {
   InCallPlan r{};
   if (p->scheme != SGCM_TRAPEZOID || n_bvps < kInCallPlanMin) return r;
-  sgcm_problem q = stage_problem(p, 0);
-  q.precision = SGCM_FP64;
-  q.max_iter = 0;
-  BvpArgs qa;
-  if (make_bvp_args(&q, &qa) != SGCM_OK) return r;
   auto up = [](size_t b) { return (b + 255) / 256 * 256; };
   size_t o = 0;
-  r.unit_ws = o;
-  o += up((size_t)qa.per_bvp * sizeof(double) * 6 + order_bytes(6));
-  r.x0 = o;
-  o += up(36 * sizeof(double));
+  r.table = o;
+  o += up((size_t)first_step_table_doubles(p->N) * sizeof(double));
   r.y1 = o;
   o += up((size_t)6 * 12 * ((size_t)p->N + 1) * sizeof(double));
-  r.lam = o;
-  o += up(36 * sizeof(double));
-  r.u0 = o;
-  o += up(18 * sizeof(double));
   r.chk = o;
   o += up(12 * sizeof(int32_t));
   r.total = o;
   return r;
 }
 
-// The six unit initial states (rows of the 6 x 6 identity).
-__global__ void k_unit_states(double* x0) {
-  const int t = threadIdx.x;
-  if (t < 36) x0[t] = (t / 6 == t % 6) ? 1.0 : 0.0;
+// The arguments of the problem whose first steps a call or a plan takes:
+// the first continuation stage, in FP64.
+static int first_step_args(const sgcm_problem* p, BvpArgs* qa) {
+  sgcm_problem q = stage_problem(p, 0);
+  q.precision = SGCM_FP64;
+  return make_bvp_args(&q, qa);
 }
 
 extern "C" int sgcm_solve_bvps_workspace(const sgcm_problem* p, int64_t n_bvps, size_t* bytes) {
@@ -1346,16 +1338,12 @@ static int solve_bvps(const sgcm_problem* p, const double* y1, int64_t n_bvps, c
   const int32_t* y1_check = nullptr;
   if (icp.total > 0) {  // the first steps of the unit initial states, in this call
     char* base = reinterpret_cast<char*>(workspace) + bvp_bytes + order_bytes(n_bvps);
-    sgcm_problem q = stage_problem(p, 0);
-    q.precision = SGCM_FP64;
-    q.max_iter = 0;
-    double* ux0 = reinterpret_cast<double*>(base + icp.x0);
+    BvpArgs qa;
+    rc = first_step_args(p, &qa);
+    if (rc != SGCM_OK) return rc;
     double* uy1 = reinterpret_cast<double*>(base + icp.y1);
     int32_t* chk = reinterpret_cast<int32_t*>(base + icp.chk);
-    hipLaunchKernelGGL(k_unit_states, dim3(1), dim3(64), 0, s, ux0);
-    rc = solve_bvps(&q, nullptr, 6, ux0, reinterpret_cast<double*>(base + icp.lam),
-                    reinterpret_cast<double*>(base + icp.u0), nullptr, uy1, chk, chk + 6, base + icp.unit_ws,
-                    icp.x0 - icp.unit_ws, stream);
+    rc = launch_first_steps(qa, p->N, reinterpret_cast<double*>(base + icp.table), uy1, chk, s);
     if (rc != SGCM_OK) return rc;
     y1 = uy1;
     y1_check = chk;
@@ -1457,35 +1445,23 @@ struct sgcm_plan {
 };
 
 // The first Newton step of the six unit initial states of problem p into y1
-// (device, 6 x (N + 1) x 12), solved by the same kernel with max_iter = 0 in
-// FP64 (the trajectory output is that step), on stream s, which is then
-// synchronized.  SGCM_EUNSUPPORTED when the step is singular or not finite.
+// (device, 6 x (N + 1) x 12), on stream s, which is then synchronized.
+// SGCM_EUNSUPPORTED when the step is not finite (a singular linearised
+// system).
 static int first_steps(const sgcm_problem* p, double* y1, hipStream_t s) {
-  sgcm_problem q = stage_problem(p, 0);  // a continuation starts from its first stage
-  q.precision = SGCM_FP64;
-  q.max_iter = 0;
-  size_t ws_bytes = 0;
-  int rc = sgcm_solve_bvps_workspace(&q, 6, &ws_bytes);
+  BvpArgs qa;
+  int rc = first_step_args(p, &qa);
   if (rc != SGCM_OK) return rc;
-  // scratch: workspace (256-byte aligned first), identity x0, lambda0, u0, status, iters
-  const size_t tmp_bytes = ws_bytes + 256 + (36 + 36 + 18) * sizeof(double) + 12 * sizeof(int32_t);
-  char* tmp = nullptr;
-  if (hipMalloc((void**)&tmp, tmp_bytes) != hipSuccess) {
+  const size_t tab_bytes = (size_t)first_step_table_doubles(p->N) * sizeof(double);
+  char* tmp = nullptr;  // the element table, then the 12 statuses and iteration counts
+  if (hipMalloc((void**)&tmp, tab_bytes + 12 * sizeof(int32_t)) != hipSuccess) {
     (void)hipGetLastError();
     return SGCM_ENOMEM;
   }
-  double* ws = reinterpret_cast<double*>(tmp);
-  double* x0 = reinterpret_cast<double*>(tmp + (ws_bytes + 255) / 256 * 256);
-  double* lam = x0 + 36;
-  double* u0 = lam + 36;
-  int32_t* st = reinterpret_cast<int32_t*>(u0 + 18);
-  int32_t* its = st + 6;
-  double eye[36] = {};
-  for (int j = 0; j < 6; ++j) eye[j * 6 + j] = 1.0;
+  int32_t* chk = reinterpret_cast<int32_t*>(tmp + tab_bytes);
   int32_t hst[12];
-  if (hipMemcpyAsync(x0, eye, sizeof(eye), hipMemcpyHostToDevice, s) != hipSuccess) rc = SGCM_EDEVICE;
-  if (rc == SGCM_OK) rc = solve_bvps(&q, nullptr, 6, x0, lam, u0, nullptr, y1, st, its, ws, ws_bytes, s);
-  if (rc == SGCM_OK && hipMemcpyAsync(hst, st, sizeof(hst), hipMemcpyDeviceToHost, s) != hipSuccess)
+  rc = launch_first_steps(qa, p->N, reinterpret_cast<double*>(tmp), y1, chk, s);
+  if (rc == SGCM_OK && hipMemcpyAsync(hst, chk, sizeof(hst), hipMemcpyDeviceToHost, s) != hipSuccess)
     rc = SGCM_EDEVICE;
   if (rc == SGCM_OK && hipStreamSynchronize(s) != hipSuccess) rc = SGCM_EDEVICE;
   (void)hipFree(tmp);  // waits for the device

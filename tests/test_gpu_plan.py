@@ -20,6 +20,11 @@ pytestmark = pytest.mark.gpu
 REL = 1e-8
 REL_PLAN = 1e-9
 REL_FP32 = 1e-7  # the FP32 inexact Newton's bar, as for the solve without a plan
+# First Newton steps from the six unit-state steps made by doubling, against
+# the oracle's banded LU of the same linear equations: both solve them to
+# rounding; the two-wheel linearisation (not stabilisable) is worse
+# conditioned, as the two direct solves of the oracle's own pins show.
+REL_FIRST = {3: 1e-12, 2: 1e-9}
 KEYS = ("lambda0", "u0", "V", "traj", "status", "iters")
 
 
@@ -181,3 +186,25 @@ def test_in_call_first_steps_equal_an_explicit_plan():
     a, c = solve(gp, x0), solve(gp, x0[:63])
     assert_same_as_unplanned({k: v[:63] for k, v in a.items()}, c)
     assert_parity(a, O.solve_bvps(op, x0, want_traj=True))
+
+
+def test_first_steps_by_doubling_match_the_oracle():
+    # from 64 BVPs a call forms each BVP's first Newton step from the steps
+    # of the six unit initial states, which it computes by doubling; with
+    # max_iter = 0 the trajectory is that step (then tested): it equals the
+    # oracle's first step for meshes of 1 to 512 intervals (powers of two
+    # and not), short and long horizons, three wheels, two wheels and the
+    # linear model, and the per-BVP first step of a call of 63 BVPs
+    cases = [(S.MODEL_RIGID_BODY, 3, 1, 0.5), (S.MODEL_RIGID_BODY, 3, 2, 20.0), (S.MODEL_RIGID_BODY, 3, 3, 5.0),
+             (S.MODEL_RIGID_BODY, 3, 37, 5.0), (S.MODEL_RIGID_BODY, 3, 100, 20.0),
+             (S.MODEL_RIGID_BODY, 3, 256, 20.0), (S.MODEL_RIGID_BODY, 3, 512, 40.0),
+             (S.MODEL_LINEARISED, 3, 255, 10.0), (S.MODEL_RIGID_BODY, 2, 64, 20.0), (S.MODEL_RIGID_BODY, 2, 129, 5.0)]
+    for model, m, N, T in cases:
+        gp, op = problems(model=model, m=m, N=N, T=T, max_iter=0)
+        x0 = W.uniform_in_box(64, seed=170 + N)
+        g = solve(gp, x0)
+        o = O.solve_bvps(op, x0, want_traj=True)
+        assert np.array_equal(g["status"], o.status) and np.array_equal(g["iters"], o.iters), (model, m, N, T)
+        assert np.max(rel_err(g["traj"], o.traj)) <= REL_FIRST[m], (model, m, N, T)
+        c = solve(gp, x0[:63])  # each BVP takes its own first step
+        assert np.max(rel_err(g["traj"][:63], c["traj"])) <= REL_FIRST[m], (model, m, N, T)
