@@ -1272,7 +1272,7 @@ using namespace sgcm;
 constexpr int64_t kInCallPlanMin = 64;  // BVPs per call from which this pays
 
 struct InCallPlan {
-  size_t table, y1, chk, total;  // byte offsets in the region, its size
+  size_t y1, chk, total;  // byte offsets in the region, its size
 };
 
 // The region behind the BVP workspaces and the launch order, or total = 0
@@ -1282,8 +1282,6 @@ static InCallPlan in_call_plan(const sgcm_problem* p, int64_t n_bvps) {
   if (p->scheme != SGCM_TRAPEZOID || n_bvps < kInCallPlanMin) return r;
   auto up = [](size_t b) { return (b + 255) / 256 * 256; };
   size_t o = 0;
-  r.table = o;
-  o += up((size_t)first_step_table_doubles(p->N) * sizeof(double));
   r.y1 = o;
   o += up((size_t)6 * 12 * ((size_t)p->N + 1) * sizeof(double));
   r.chk = o;
@@ -1343,7 +1341,7 @@ static int solve_bvps(const sgcm_problem* p, const double* y1, int64_t n_bvps, c
     if (rc != SGCM_OK) return rc;
     double* uy1 = reinterpret_cast<double*>(base + icp.y1);
     int32_t* chk = reinterpret_cast<int32_t*>(base + icp.chk);
-    rc = launch_first_steps(qa, p->N, reinterpret_cast<double*>(base + icp.table), uy1, chk, s);
+    rc = launch_first_steps(qa, p->N, uy1, chk, s);
     if (rc != SGCM_OK) return rc;
     y1 = uy1;
     y1_check = chk;
@@ -1452,19 +1450,17 @@ static int first_steps(const sgcm_problem* p, double* y1, hipStream_t s) {
   BvpArgs qa;
   int rc = first_step_args(p, &qa);
   if (rc != SGCM_OK) return rc;
-  const size_t tab_bytes = (size_t)first_step_table_doubles(p->N) * sizeof(double);
-  char* tmp = nullptr;  // the element table, then the 12 statuses and iteration counts
-  if (hipMalloc((void**)&tmp, tab_bytes + 12 * sizeof(int32_t)) != hipSuccess) {
+  int32_t* chk = nullptr;  // the 12 statuses and iteration counts
+  if (hipMalloc((void**)&chk, 12 * sizeof(int32_t)) != hipSuccess) {
     (void)hipGetLastError();
     return SGCM_ENOMEM;
   }
-  int32_t* chk = reinterpret_cast<int32_t*>(tmp + tab_bytes);
   int32_t hst[12];
-  rc = launch_first_steps(qa, p->N, reinterpret_cast<double*>(tmp), y1, chk, s);
+  rc = launch_first_steps(qa, p->N, y1, chk, s);
   if (rc == SGCM_OK && hipMemcpyAsync(hst, chk, sizeof(hst), hipMemcpyDeviceToHost, s) != hipSuccess)
     rc = SGCM_EDEVICE;
   if (rc == SGCM_OK && hipStreamSynchronize(s) != hipSuccess) rc = SGCM_EDEVICE;
-  (void)hipFree(tmp);  // waits for the device
+  (void)hipFree(chk);  // waits for the device
   for (int j = 0; rc == SGCM_OK && j < 6; ++j)
     if ((hst[j] != SGCM_BVP_CONVERGED && hst[j] != SGCM_BVP_MAXITER) || hst[6 + j] != 0) rc = SGCM_EUNSUPPORTED;
   if (rc != SGCM_OK) (void)hipGetLastError();

@@ -21,12 +21,20 @@
 // each BVP's first sweep would compute, in about log2(N) dependent steps of
 // 6 x 6 algebra instead of N.  The forms avoid powers of the interval map,
 // whose growth over long horizons would ruin them.
+//
+// One workgroup of three wavefronts per mesh point: the first makes the
+// elements E_b one level after the other, the second applies each level to
+// P and the third to the element of [0, k] as soon as it is made.  In the
+// 6 x 6 algebra a lane holds one column of a matrix: a product is a
+// matrix-vector product per lane (the other matrix read from LDS), and the
+// elimination broadcasts the pivot column from its lane (readlane), so no
+// step waits on a barrier.
 #include "model.h"
 
 namespace sgcm {
 namespace {
 
-constexpr int kEl = 4 * 36;  // doubles of one element: A, B, C, D (6 x 6 row-major each)
+constexpr int kEl = 4 * 36;     // doubles of one element: A, B, C, D (6 x 6 row-major each)
 constexpr int kMaxLevels = 17;  // 2^16 intervals, the largest mesh
 
 // Levels b of the elements E_b a mesh of N intervals needs (2^b <= N).
@@ -36,139 +44,218 @@ __host__ __device__ inline int first_step_levels(int N) {
   return l;
 }
 
-// Entry t (row t / 6, column t % 6) of the product of two 6 x 6 matrices in
-// LDS with row strides la and lb.
-__device__ __forceinline__ double mm6(const double* A, int la, const double* B, int lb, int t) {
-  const int i = t / 6, j = t - 6 * (t / 6);
-  double s = A[i * la] * B[j];
-#pragma unroll
-  for (int l = 1; l < 6; ++l) s = fma(A[i * la + l], B[l * lb + j], s);
-  return s;
+// x of lane `from` (a wavefront constant).
+__device__ __forceinline__ double bcast(double x, int from) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, from);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), from);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Gauss-Jordan elimination with partial pivoting of the n x w matrix M in
-// LDS (row-major): afterwards its first n columns hold the identity and the
-// other w - n columns the solution of M_left X = M_right.  A zero pivot
-// leaves non-finite values.  Every thread of the (one-wave) workgroup takes
-// part.
-template <int n, int w>
-__device__ void gauss_jordan(double* M) {
-  constexpr int kPer = (n * w + 63) / 64;
-  const int lane = threadIdx.x;
+// Gauss-Jordan elimination with partial pivoting of an n-row augmented matrix
+// whose column l is v in lane l (lanes 0..n-1: the square part): afterwards
+// the lanes of the other columns hold the solution's columns.  A zero pivot
+// leaves non-finite values.  Every lane of the wavefront takes part.
+template <int n>
+__device__ __forceinline__ void gauss_jordan(double (&v)[n]) {
+#pragma unroll
   for (int c = 0; c < n; ++c) {
+    double col[n];
+#pragma unroll
+    for (int i = 0; i < n; ++i) col[i] = bcast(v[i], c);
     int p = c;
-    double best = fabs(M[c * w + c]);
-    for (int r = c + 1; r < n; ++r) {
-      const double v = fabs(M[r * w + c]);
-      if (v > best) {
-        best = v;
-        p = r;
+    double best = fabs(col[c]);
+#pragma unroll
+    for (int i = c + 1; i < n; ++i) {
+      const double a = fabs(col[i]);
+      if (a > best) {
+        best = a;
+        p = i;
       }
     }
-    const double rp = 1.0 / M[p * w + c];
-    double out[kPer];
+    // rows c and p trade places
+    const double cc = col[c], vc = v[c];
+    double cp = cc, vp = vc;
 #pragma unroll
-    for (int s = 0; s < kPer; ++s) {
-      const int e = lane + 64 * s;
-      out[s] = 0.0;
-      if (e < n * w) {
-        const int i = e / w, j = e - w * (e / w);
-        const double pr = M[p * w + j] * rp;  // row c after the swap, scaled
-        const int src = i == p ? c : i;       // rows c and p trade places
-        out[s] = i == c ? pr : fma(-M[src * w + c], pr, M[src * w + j]);
+    for (int i = c + 1; i < n; ++i)
+      if (p == i) {
+        cp = col[i];
+        vp = v[i];
+        col[i] = cc;
+        v[i] = vc;
       }
-    }
-    __syncthreads();
+    const double nv = vp * (1.0 / cp);
 #pragma unroll
-    for (int s = 0; s < kPer; ++s) {
-      const int e = lane + 64 * s;
-      if (e < n * w) M[e] = out[s];
-    }
-    __syncthreads();
+    for (int i = 0; i < n; ++i)
+      if (i != c) v[i] = fma(-col[i], nv, v[i]);
+    v[c] = nv;
   }
 }
 
-// LDS scratch of the element algebra.
-struct ElemScratch {
-  double aug[6 * 18];  // augmented systems
-  double s1[36], s2[36];
-};
+// y = M x for a 6 x 6 row-major M in LDS.
+__device__ __forceinline__ void matvec(const double* M, const double (&x)[6], double (&y)[6]) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double s = M[i * 6] * x[0];
+#pragma unroll
+    for (int l = 1; l < 6; ++l) s = fma(M[i * 6 + l], x[l], s);
+    y[i] = s;
+  }
+}
+
+__device__ __forceinline__ void load_col(const double* M, int j, double (&x)[6]) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) x[i] = M[i * 6 + j];
+}
+
+__device__ __forceinline__ void store_col(double* M, int j, const double (&x)[6]) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) M[i * 6 + j] = x[i];
+}
 
 // E = E1 * E2, the element of span 1 followed by span 2 (E may be E1, not
-// E2): with Z = (I - B1 C2)^{-1},
+// E2), by one wavefront: with Z = (I - B1 C2)^{-1},
 //   A = A2 Z A1,  B = B2 + A2 Z B1 D2,  C = C1 + D1 C2 Z A1,
 //   D = D1 (D2 + C2 Z B1 D2).
-__device__ void star(const double* E1, const double* E2, double* E, ElemScratch& w) {
+// Lanes 0..5 hold the columns of I - B1 C2, lanes 6..11 those of A1 (then
+// of Z A1), lanes 12..17 those of B1 D2 (then of Z B1 D2).
+__device__ __forceinline__ void star(const double* E1, const double* E2, double* E) {
   const double *A1 = E1, *B1 = E1 + 36, *C1 = E1 + 72, *D1 = E1 + 108;
   const double *A2 = E2, *B2 = E2 + 36, *C2 = E2 + 72, *D2 = E2 + 108;
-  const int t = threadIdx.x;
-  if (t < 36) {
-    const int i = t / 6, j = t - 6 * (t / 6);
-    const double bc = mm6(B1, 6, C2, 6, t), bd = mm6(B1, 6, D2, 6, t);
-    w.aug[i * 18 + j] = (i == j ? 1.0 : 0.0) - bc;
-    w.aug[i * 18 + 6 + j] = A1[t];
-    w.aug[i * 18 + 12 + j] = bd;
+  const int lane = threadIdx.x & 63;
+  const int g = lane < 6 ? 0 : (lane < 12 ? 1 : 2);  // lanes from 18 on repeat group 2
+  const int j = lane < 18 ? lane - 6 * g : 0;
+  double v[6], t[6];
+  if (g == 1) {
+    load_col(A1, j, v);
+  } else {
+    load_col(g == 0 ? C2 : D2, j, t);
+    matvec(B1, t, v);
+    if (g == 0) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) v[i] = (i == j ? 1.0 : 0.0) - v[i];
+    }
   }
-  __syncthreads();
-  gauss_jordan<6, 18>(w.aug);  // columns 6..11: Z A1, 12..17: Z B1 D2
-  double a2u = 0.0, a2v = 0.0, c2u = 0.0, c2v = 0.0;
-  if (t < 36) {
-    a2u = mm6(A2, 6, w.aug + 6, 18, t);
-    a2v = mm6(A2, 6, w.aug + 12, 18, t);
-    c2u = mm6(C2, 6, w.aug + 6, 18, t);
-    c2v = mm6(C2, 6, w.aug + 12, 18, t);
+  gauss_jordan<6>(v);
+  if (lane >= 6 && lane < 18) {
+    double a[6], c[6], d[6];
+    matvec(A2, v, a);
+    matvec(C2, v, c);
+    if (g == 2) {
+      double d2[6];
+      load_col(D2, j, d2);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) c[i] += d2[i];
+    }
+    matvec(D1, c, d);
+    double o[6];
+    load_col(g == 1 ? C1 : B2, j, o);
+    if (g == 1) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) o[i] += d[i];
+      store_col(E, j, a);       // A
+      store_col(E + 72, j, o);  // C
+    } else {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) o[i] += a[i];
+      store_col(E + 36, j, o);   // B
+      store_col(E + 108, j, d);  // D
+    }
   }
-  __syncthreads();
-  if (t < 36) {
-    w.s1[t] = c2u;
-    w.s2[t] = D2[t] + c2v;
-    E[t] = a2u;
-    E[36 + t] = B2[t] + a2v;
-  }
-  __syncthreads();
-  double dc = 0.0, dd = 0.0;
-  if (t < 36) {
-    dc = mm6(D1, 6, w.s1, 6, t);
-    dd = mm6(D1, 6, w.s2, 6, t);
-  }
-  __syncthreads();
-  if (t < 36) {
-    E[72 + t] = C1[t] + dc;
-    E[108 + t] = dd;
-  }
-  __syncthreads();
+  wave_lds_sync();
 }
 
-// P <- C + D P (I - B P)^{-1} A: the Riccati matrix at the left end of the
-// span of element E from P at its right end.
-__device__ void terminal(const double* E, double* P, ElemScratch& w) {
+// P <- C + D P (I - B P)^{-1} A, the Riccati matrix at the left end of the
+// span of element E from P at its right end, by one wavefront; DP: LDS
+// scratch of 36 doubles.  Lanes 0..5 hold the columns of I - B P, lanes 6..11
+// those of A (then of X = (I - B P)^{-1} A), lanes 12..17 form D P.
+__device__ __forceinline__ void terminal(const double* E, double* P, double* DP) {
   const double *A = E, *B = E + 36, *C = E + 72, *D = E + 108;
-  const int t = threadIdx.x;
-  if (t < 36) {
-    const int i = t / 6, j = t - 6 * (t / 6);
-    const double bp = mm6(B, 6, P, 6, t), dp = mm6(D, 6, P, 6, t);
-    w.aug[i * 12 + j] = (i == j ? 1.0 : 0.0) - bp;
-    w.aug[i * 12 + 6 + j] = A[t];
-    w.s1[t] = dp;
+  const int lane = threadIdx.x & 63;
+  const int g = lane < 6 ? 0 : (lane < 12 ? 1 : 2);
+  const int j = lane < 18 ? lane - 6 * g : 0;
+  double v[6], t[6];
+  if (g == 1) {
+    load_col(A, j, v);
+  } else {
+    load_col(P, j, t);
+    matvec(g == 0 ? B : D, t, v);
+    if (g == 0) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) v[i] = (i == j ? 1.0 : 0.0) - v[i];
+    } else if (lane < 18) {
+      store_col(DP, j, v);
+    }
   }
-  __syncthreads();
-  gauss_jordan<6, 12>(w.aug);
-  if (t < 36) P[t] = C[t] + mm6(w.s1, 6, w.aug + 6, 12, t);
-  __syncthreads();
+  lds_handoff();
+  gauss_jordan<6>(v);
+  if (g == 1) {
+    double o[6], c[6];
+    matvec(DP, v, o);
+    load_col(C, j, c);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) c[i] += o[i];
+    store_col(P, j, c);
+  }
+  wave_lds_sync();
 }
 
-// The elements E_b (b < levels) of problem P's trapezoidal intervals at
-// Y = 0 into tab (levels x kEl doubles); chk (12) gets the statuses and
-// iteration counts a solve with max_iter = 0 reports for the steps
-// (SGCM_BVP_MAXITER, 0), or SGCM_BVP_NONFINITE if the table is not finite.
-// One 64-thread workgroup.
-__global__ void __launch_bounds__(64) k_first_table(const BvpArgs P, int levels, double* __restrict__ tab,
-                                                     int32_t* __restrict__ chk) {
-  __shared__ double aug[12 * 24];
-  __shared__ double GA[36], GW[36];
-  __shared__ double E[kMaxLevels * kEl];
-  __shared__ ElemScratch w;
+// The element E_0 of one interval at Y = 0 into E, by one wavefront: from
+// the interval equations, Q [x_k; lambda_{k-1}] = R [x_{k-1}; lambda_k] with
+//   Q = [I - aA, aS; -aW, -(I - aA^T)],  R = [I + aA, -aS; aW, -(I + aA^T)],
+// so [A0 B0; C0 D0] = Q^{-1} R.  Lane l < 24 holds column l of [Q | R].
+__device__ __forceinline__ void interval_element(const BvpArgs& P, const double* GA, const double* GW, double* E) {
+  const int lane = threadIdx.x & 63;
+  const int c = lane < 24 ? lane : 0;
+  const int cc = c < 12 ? c : c - 12;
+  const bool cx = cc < 6;
+  const int j = cx ? cc : cc - 6;
+  const double sg = c < 12 ? -1.0 : 1.0;  // the sign of a in Q, R
+  const double a = P.alpha;
+  double v[12];
+#pragma unroll
+  for (int r = 0; r < 12; ++r) {
+    const bool rx = r < 6;
+    const int i = rx ? r : r - 6;
+    const double id = i == j ? 1.0 : 0.0;
+    double x;
+    if (rx && cx) x = id + sg * a * GA[i * 6 + j];
+    else if (rx) x = -sg * a * ((i >= 3 && j >= 3) ? P.Sw[(i - 3) * 3 + (j - 3)] : 0.0);
+    else if (cx) x = sg * a * GW[i * 6 + j];
+    else x = -(id + sg * a * GA[j * 6 + i]);
+    v[r] = x;
+  }
+  gauss_jordan<12>(v);
+  if (lane >= 12 && lane < 24) {
+    const int q = lane - 12, jj = q < 6 ? q : q - 6;
+    double* top = E + (q < 6 ? 0 : 36);    // A0 or B0
+    double* bot = E + (q < 6 ? 72 : 108);  // C0 or D0
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      top[i * 6 + jj] = v[i];
+      bot[i * 6 + jj] = v[6 + i];
+    }
+  }
+  wave_lds_sync();
+}
+
+// Statuses and iteration counts of the six steps as a solve with
+// max_iter = 0 reports them when they are finite.
+__global__ void k_first_check(int32_t* __restrict__ chk) {
   const int t = threadIdx.x;
+  if (t < 12) chk[t] = t < 6 ? SGCM_BVP_MAXITER : 0;
+}
+
+// Mesh point k = blockIdx.x of the six steps, y1[j][k] = [X_k e_j; P_k X_k
+// e_j] (y1 is 6 x (N + 1) x 12); a non-finite value marks the steps invalid
+// in chk.  Three wavefronts: the elements, the P chain, the [0, k] chain.
+__global__ void __launch_bounds__(192) k_first_steps(const BvpArgs P, int N, int levels, double* __restrict__ y1,
+                                                     int32_t* __restrict__ chk) {
+  __shared__ double E[kMaxLevels * kEl];
+  __shared__ double GA[36], GW[36], Pk[36], DP[36], El[kEl];
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int k = blockIdx.x;
+  const int L = N - k;
   if (t == 0) {
     double y[12] = {};
     double phi[12], A[36], W[36];
@@ -179,105 +266,69 @@ __global__ void __launch_bounds__(64) k_first_table(const BvpArgs P, int levels,
       GW[e] = W[e];
     }
   }
+  if (wave == 1 && lane < 36) Pk[lane] = (lane / 6 == lane - 6 * (lane / 6)) ? P.pw : 0.0;
   __syncthreads();
-  // [Q | R]: Q [x_k; lambda_{k-1}] = R [x_{k-1}; lambda_k], from the
-  // interval equations, with
-  //   Q = [I - aA, aS; -aW, -(I - aA^T)],  R = [I + aA, -aS; aW, -(I + aA^T)].
-  const double a = P.alpha;
-  for (int e = t; e < 12 * 24; e += 64) {
-    const int r = e / 24, c = e - 24 * (e / 24);
-    const int cc = c < 12 ? c : c - 12;
-    const bool rx = r < 6, cx = cc < 6;
-    const int i = rx ? r : r - 6, j = cx ? cc : cc - 6;
-    const double id = i == j ? 1.0 : 0.0;
-    const double sg = c < 12 ? -1.0 : 1.0;  // the sign of a in Q, R
-    double v;
-    if (rx && cx) v = id + sg * a * GA[i * 6 + j];
-    else if (rx) v = -sg * a * ((i >= 3 && j >= 3) ? P.Sw[(i - 3) * 3 + (j - 3)] : 0.0);
-    else if (cx) v = sg * a * GW[i * 6 + j];
-    else v = -(id + sg * a * GA[j * 6 + i]);
-    aug[e] = v;
-  }
-  __syncthreads();
-  gauss_jordan<12, 24>(aug);
-  for (int e = t; e < kEl; e += 64) {
-    const int blk = e / 36, q = e - 36 * (e / 36);
-    const int i = q / 6, j = q - 6 * (q / 6);
-    const int r = (blk >= 2 ? 6 : 0) + i, c = 12 + (blk & 1 ? 6 : 0) + j;
-    E[e] = aug[r * 24 + c];
-  }
-  __syncthreads();
-  for (int b = 1; b < levels; ++b) star(E + (b - 1) * kEl, E + (b - 1) * kEl, E + b * kEl, w);
-  bool fin = true;
-  for (int e = t; e < levels * kEl; e += 64) {
-    tab[e] = E[e];
-    fin &= isfinite(E[e]);
-  }
-  const bool all = __syncthreads_and(fin);
-  if (t < 12) chk[t] = t < 6 ? (all ? SGCM_BVP_MAXITER : SGCM_BVP_NONFINITE) : 0;
-}
-
-// Mesh point k = blockIdx.x of the six steps: y1[j][k] = [X_k e_j; P_k X_k
-// e_j] (y1 is 6 x (N + 1) x 12); a non-finite value marks the steps invalid
-// in chk.  One 64-thread workgroup per point.
-__global__ void __launch_bounds__(64) k_first_points(int N, double pw, int levels, const double* __restrict__ tab,
-                                                      double* __restrict__ y1, int32_t* __restrict__ chk) {
-  __shared__ double E[kMaxLevels * kEl];
-  __shared__ double Pk[36], El[kEl];
-  __shared__ ElemScratch w;
-  const int t = threadIdx.x;
-  const int k = blockIdx.x;
-  for (int e = t; e < levels * kEl; e += 64) E[e] = tab[e];
-  if (t < 36) Pk[t] = (t / 6 == t - 6 * (t / 6)) ? pw : 0.0;
-  __syncthreads();
-  const int L = N - k;
-  for (int b = 0; b < levels; ++b)
-    if ((L >> b) & 1) terminal(E + b * kEl, Pk, w);
-  // the element of [0, k]
-  bool have = false;
+  bool have = false;  // the [0, k] chain has an element
   for (int b = 0; b < levels; ++b) {
-    if (!((k >> b) & 1)) continue;
-    if (!have) {
-      for (int e = t; e < kEl; e += 64) El[e] = E[b * kEl + e];
-      __syncthreads();
+    if (wave == 0) {
+      if (b == 0) interval_element(P, GA, GW, E);
+      else star(E + (b - 1) * kEl, E + (b - 1) * kEl, E + b * kEl);
+    }
+    __syncthreads();  // E_b is made; the chains apply it while E_{b+1} is made
+    if (wave == 1 && ((L >> b) & 1)) terminal(E + b * kEl, Pk, DP);
+    if (wave == 2 && ((k >> b) & 1)) {
+      if (!have) {
+        for (int e = lane; e < kEl; e += 64) El[e] = E[b * kEl + e];
+        wave_lds_sync();
+      } else {
+        star(El, E + b * kEl, El);
+      }
       have = true;
-    } else {
-      star(El, E + b * kEl, El, w);
     }
   }
-  // X = (I - B P)^{-1} A (the identity at k = 0), then P X
-  if (t < 36) {
-    const int i = t / 6, j = t - 6 * (t / 6);
-    const double id = i == j ? 1.0 : 0.0;
-    w.aug[i * 12 + j] = have ? id - mm6(El + 36, 6, Pk, 6, t) : id;
-    w.aug[i * 12 + 6 + j] = have ? El[t] : id;
-  }
   __syncthreads();
-  gauss_jordan<6, 12>(w.aug);
-  double px = 0.0;
-  if (t < 36) px = mm6(Pk, 6, w.aug + 6, 12, t);
-  bool fin = true;
-  if (t < 36) {
-    const int i = t / 6, j = t - 6 * (t / 6);  // entry (i, j): component i of step j
-    const double x = w.aug[i * 12 + 6 + j];
-    const int64_t o = (int64_t)j * 12 * (N + 1) + (int64_t)k * 12;
-    y1[o + i] = x;
-    y1[o + 6 + i] = px;
-    fin = isfinite(x) && isfinite(px);
+  if (wave != 1) return;
+  // X = (I - B P)^{-1} A for the element (A, B) of [0, k] (the identity at
+  // k = 0), then P X: lanes 0..5 hold the columns of I - B P, lanes 6..11
+  // those of A (then of X).
+  const int g = lane < 6 ? 0 : 1;
+  const int j = lane < 12 ? lane - 6 * g : 0;
+  double v[6];
+  if (g == 0) {
+    double pc[6];
+    load_col(Pk, j, pc);
+    if (k > 0) matvec(El + 36, pc, v);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) v[i] = (i == j ? 1.0 : 0.0) - (k > 0 ? v[i] : 0.0);
+  } else if (k > 0) {
+    load_col(El, j, v);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) v[i] = i == j ? 1.0 : 0.0;
   }
-  const bool all = __syncthreads_and(fin);
-  if (!all && t < 6) chk[t] = SGCM_BVP_NONFINITE;
+  gauss_jordan<6>(v);
+  bool fin = true;
+  if (lane >= 6 && lane < 12) {
+    double px[6];
+    matvec(Pk, v, px);
+    double* out = y1 + (int64_t)j * 12 * (N + 1) + (int64_t)k * 12;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      out[i] = v[i];
+      out[6 + i] = px[i];
+      fin = fin && isfinite(v[i]) && isfinite(px[i]);
+    }
+  }
+  if (!__all(fin) && lane < 6) chk[lane] = SGCM_BVP_NONFINITE;
 }
 
 }  // namespace
 
-int64_t first_step_table_doubles(int N) { return (int64_t)first_step_levels(N) * kEl; }
-
-int launch_first_steps(const BvpArgs& a, int N, double* table, double* y1, int32_t* chk, hipStream_t s) {
+int launch_first_steps(const BvpArgs& a, int N, double* y1, int32_t* chk, hipStream_t s) {
   const int levels = first_step_levels(N);
   if (N < 1 || levels > kMaxLevels) return SGCM_EINVAL;
-  hipLaunchKernelGGL(k_first_table, dim3(1), dim3(64), 0, s, a, levels, table, chk);
-  hipLaunchKernelGGL(k_first_points, dim3((unsigned)N + 1), dim3(64), 0, s, N, a.pw, levels, table, y1, chk);
+  hipLaunchKernelGGL(k_first_check, dim3(1), dim3(64), 0, s, chk);
+  hipLaunchKernelGGL(k_first_steps, dim3((unsigned)N + 1), dim3(192), 0, s, a, N, levels, y1, chk);
   return hipGetLastError() == hipSuccess ? SGCM_OK : SGCM_EDEVICE;
 }
 

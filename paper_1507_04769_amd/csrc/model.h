@@ -206,16 +206,12 @@ __device__ __forceinline__ void lds_handoff() {
 
 // ---- the first Newton steps of the unit initial states (first_steps.hip) -----
 
-// Doubles of the element table of a mesh of N intervals.
-int64_t first_step_table_doubles(int N);
-
 // The first Newton step from Y = 0 of the trapezoidal solve of problem a
 // (FP64; mesh of N intervals of width a.h) for the six unit initial states,
 // into y1 (device, 6 x (N + 1) x 12), with the statuses and iteration counts
 // (device, 6 + 6) of a solve with max_iter = 0: SGCM_BVP_MAXITER and 0, or
-// SGCM_BVP_NONFINITE when the steps are not finite.  table: device scratch of
-// first_step_table_doubles(N) doubles.  Two launches on stream s.
-int launch_first_steps(const BvpArgs& a, int N, double* table, double* y1, int32_t* chk, hipStream_t s);
+// SGCM_BVP_NONFINITE when the steps are not finite.  Two launches on stream s.
+int launch_first_steps(const BvpArgs& a, int N, double* y1, int32_t* chk, hipStream_t s);
 
 // ---- four-point Lobatto IIIA collocation (lobatto.hip) ----------------------
 
