@@ -41,9 +41,9 @@ __host__ __device__ constexpr int upto(int b) { return b <= 0 ? 1 : (1 << b) + 1
 // from prefix and suffix products of (xi - x_s) over X^I.
 // F is the arithmetic type (double; float for the FP32 evaluation path, whose
 // point and scale tables are rounded from the FP64 ones).
-template <int L, int I, typename F = double>
+template <int L, int I, typename F = double, int IMAX = L + 1>
 __device__ __forceinline__ void level_basis(const GridArgs& g, F xi, F (&out)[kMaxPoints]) {
-  if constexpr (I <= L + 1) {
+  if constexpr (I <= IMAX) {
     constexpr int n = (1 << (I - 1)) + 1;
     constexpr int stride = 1 << (L + 1 - I);
     // suffix products suf[s] = prod_{s' > s} (xi - x_s'), then one forward
@@ -65,7 +65,7 @@ __device__ __forceinline__ void level_basis(const GridArgs& g, F xi, F (&out)[kM
       }
       pre *= xi - (F)g.X[s * stride];
     }
-    level_basis<L, I + 1, F>(g, xi, out);
+    level_basis<L, I + 1, F, IMAX>(g, xi, out);
   }
 }
 
@@ -109,6 +109,13 @@ template <int L, typename F = double>
 __device__ __forceinline__ void basis_row_l(const GridArgs& g, F xi, F (&out)[kMaxPoints]) {
   out[0] = F(1);
   level_basis<L, 2, F>(g, xi, out);
+}
+
+// The values of the points below the finest level (out[0 .. upto(L - 1))).
+template <int L, typename F>
+__device__ __forceinline__ void basis_row_below(const GridArgs& g, F xi, F (&out)[kMaxPoints]) {
+  out[0] = F(1);
+  level_basis<L, 2, F, L>(g, xi, out);
 }
 
 __device__ __forceinline__ void basis_row(const GridArgs& g, double xi, double (&out)[kMaxPoints]) {
@@ -362,6 +369,110 @@ __device__ __forceinline__ void fast_point(const GridArgs& g, const F* __restric
   owalk<D, L, M, KO, KU, 0, false, F>(g, w, L, 0, F(1), acc, bv, lds_lane, F(0));
 }
 
+// ---- the evaluation walk with the finest level formed where it is used -------
+//
+// A point of the finest level of a dimension has the whole excess budget, so
+// it appears in exactly one trie path per evaluation point: the one where
+// every other dimension sits at its level-1 point.  Its basis value is then
+// formed where that path reaches it (basis_point: the same bits as the row
+// computation) instead of being kept for the whole walk: per lane only the
+// values below the finest level stay in registers (the inner dimensions) and
+// LDS (the outer ones but the first, whose values are all used once and all
+// formed where reached), which leaves room for more wavefronts per SIMD.
+// That pays where the registers bound the kernel at one wavefront per SIMD
+// (FP64 at level 5: two instead of one, half the time); at the lower levels
+// and in FP32 the values formed again cost more than the occupancy gains.
+
+// Basis value of point E of inner dimension J.
+template <int L, int KU, int J, int E, typename F>
+__device__ __forceinline__ F ubasis(const GridArgs& g, const F (&bv)[KU][upto(L - 1)], const F (&xin)[KU]) {
+  if constexpr (E < upto(L - 1)) {
+    return bv[J][E];
+  } else {
+    return basis_point<L, E, F>(g, xin[J]);
+  }
+}
+
+// t += sum over points Q..N-1 of the last dimension of b[Q] w[OFF + Q].
+template <int L, int KU, int M, int Q, int N, int OFF, typename F>
+__device__ __forceinline__ void utail(const GridArgs& g, const F (&bv)[KU][upto(L - 1)], const F (&xin)[KU],
+                                      const F* __restrict__ w, F (&t)[M]) {
+  if constexpr (Q < N) {
+    const F b = ubasis<L, KU, KU - 1, Q, F>(g, bv, xin);
+#pragma unroll
+    for (int c = 0; c < M; ++c) t[c] = fma(b, w[(OFF + Q) * M + c], t[c]);
+    utail<L, KU, M, Q + 1, N, OFF, F>(g, bv, xin, w, t);
+  }
+}
+
+// uwalk with the finest level formed where reached.
+template <int L, int KU, int M, int R, int B, int OFF, int E, typename F>
+__device__ __forceinline__ void uwalk_f(const GridArgs& g, const F (&bv)[KU][upto(L - 1)], const F (&xin)[KU],
+                                        const F* __restrict__ w, F p, F (&acc)[M]) {
+  if constexpr (E < upto(B)) {
+    constexpr int ex = excess_of(E);
+    constexpr int off = OFF + child_off(R, B, E);
+    if constexpr (R == 1) {
+      const F pe = p * ubasis<L, KU, KU - 1, E, F>(g, bv, xin);
+#pragma unroll
+      for (int c = 0; c < M; ++c) acc[c] = fma(pe, w[off * M + c], acc[c]);
+    } else if constexpr (R == 2) {
+      constexpr int n = upto(B - ex);
+      const F pe = p * ubasis<L, KU, KU - 2, E, F>(g, bv, xin);
+      if constexpr (n == 1) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) acc[c] = fma(pe, w[off * M + c], acc[c]);
+      } else {
+        F t[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) t[c] = w[off * M + c];
+        utail<L, KU, M, 1, n, off, F>(g, bv, xin, w, t);
+#pragma unroll
+        for (int c = 0; c < M; ++c) acc[c] = fma(pe, t[c], acc[c]);
+      }
+    } else {
+      uwalk_f<L, KU, M, R - 1, B - ex, off, 0, F>(g, bv, xin, w, p * ubasis<L, KU, KU - R, E, F>(g, bv, xin), acc);
+    }
+    uwalk_f<L, KU, M, R, B, OFF, E + 1, F>(g, bv, xin, w, p, acc);
+  }
+}
+
+template <int L, int KU, int M, int BB, typename F>
+__device__ __forceinline__ void uwalk_f_budget(int b, const F (&bv)[KU][upto(L - 1)], const F (&xin)[KU],
+                                               const GridArgs& g, const F* __restrict__ w, F p, F (&acc)[M]) {
+  if (b == BB) {
+    uwalk_f<L, KU, M, KU, BB, 0, 0, F>(g, bv, xin, w, p, acc);
+  } else if constexpr (BB > 0) {
+    uwalk_f_budget<L, KU, M, BB - 1, F>(b, bv, xin, g, w, p, acc);
+  }
+}
+
+// The outer dimensions: dimension 0's values formed where reached (each is
+// used once), those of dimensions 1..KO-1 below the finest level in LDS at
+// lds_lane[((K - 1) * upto(L - 1) + e) * 64].
+template <int D, int L, int M, int KO, int KU, int K, typename F>
+__device__ __forceinline__ void owalk_f(const GridArgs& g, const F* __restrict__ w, int bL, int64_t base, F p,
+                                        F (&acc)[M], const F (&bv)[KU][upto(L - 1)], const F (&xin)[KU],
+                                        const F (&xout)[KO], const F* lds_lane) {
+  constexpr int P = upto(L), PL = upto(L - 1);
+  if constexpr (K == KO) {
+    uwalk_f_budget<L, KU, M, L, F>(bL, bv, xin, g, w + base * M, p, acc);
+  } else {
+    const int cE = upto(bL);
+    const int32_t* offrow = g.off + ((D - K - 1) * (L + 1) + bL) * P;
+    for (int e = 0; e < cE; ++e) {
+      const int ex = g.excess[e];
+      F pk;
+      if constexpr (K == 0) {
+        pk = basis_point_rt<L, 0, P, F>(g, xout[0], e);
+      } else {
+        pk = p * (e < PL ? lds_lane[((K - 1) * PL + e) * 64] : basis_point_rt<L, PL, P, F>(g, xout[K], e));
+      }
+      owalk_f<D, L, M, KO, KU, K + 1, F>(g, w, bL - ex, base + offrow[e], pk, acc, bv, xin, xout, lds_lane);
+    }
+  }
+}
+
 // Whether the evaluation kernel forms dimension 0's lower-level basis values
 // when reached instead of keeping them in LDS: in FP64 up to level 4, where the
 // LDS bounds the waves per compute unit (at level 4: 9 workgroups of 17 KB,
@@ -370,6 +481,13 @@ __device__ __forceinline__ void fast_point(const GridArgs& g, const F* __restric
 template <int L, typename F>
 __host__ __device__ constexpr bool eval_low0() {
   return sizeof(F) == 8 && L <= 4;
+}
+
+// Whether the evaluation takes k_eval_fine (the finest level formed where
+// used): FP64 at level 5, where k_eval_fast needs 256 registers.
+template <int L, typename F>
+__host__ __device__ constexpr bool eval_fine() {
+  return sizeof(F) == 8 && L >= 5;
 }
 
 // F = double: the FP64 path.  F = float: the FP32 path (surplus, states and
@@ -413,6 +531,50 @@ __global__ __launch_bounds__(64) void k_eval_fast(GridArgs g, const F* __restric
 #pragma unroll
   for (int c = 0; c < M; ++c) acc[c] = F(0);
   owalk<D, L, M, KO, KU, 0, LOW0, F>(g, w, L, 0, F(1), acc, bv, lds_lane, xi0);
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < M; ++c) uq[q * M + c] = acc[c];
+  }
+}
+
+// The evaluation kernel with the walk of owalk_f (same results, bit for bit).
+template <int D, int L, int M, typename F = double>
+__global__ __launch_bounds__(64) void k_eval_fine(GridArgs g, const F* __restrict__ w, int64_t nq,
+                                                  const F* __restrict__ xq, F* __restrict__ uq) {
+  constexpr int PL = upto(L - 1);
+  constexpr int KU = D < 4 ? D : 4;
+  constexpr int KO = D - KU;
+  static_assert(KO >= 1, "the evaluation kernel walks at least one outer dimension");
+  extern __shared__ double lds_d[];
+  F* lds = reinterpret_cast<F*>(lds_d);
+  const int lane = threadIdx.x;
+  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+  const bool active = q < nq;
+  F* lds_lane = lds + lane;
+  F bv[KU][PL], xin[KU], xout[KO];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const F xi = active ? (F)(((double)xq[q * D + k] - g.lo[k]) * g.inv_width[k]) : F(0.5);
+    if (k == 0) {
+      xout[0] = xi;
+      continue;
+    }
+    F row[kMaxPoints];
+    basis_row_below<L, F>(g, xi, row);
+    if (k < KO) {
+      xout[k] = xi;
+#pragma unroll
+      for (int e = 0; e < PL; ++e) lds_lane[((k - 1) * PL + e) * 64] = row[e];
+    } else {
+      xin[k - KO] = xi;
+#pragma unroll
+      for (int e = 0; e < PL; ++e) bv[k - KO][e] = row[e];
+    }
+  }
+  F acc[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) acc[c] = F(0);
+  owalk_f<D, L, M, KO, KU, 0, F>(g, w, L, 0, F(1), acc, bv, xin, xout, lds_lane);
   if (active) {
 #pragma unroll
     for (int c = 0; c < M; ++c) uq[q * M + c] = acc[c];
@@ -594,7 +756,12 @@ hipError_t launch_fast(const GridArgs& a, int64_t nq, const F* w, const F* xq, F
   const size_t lds = (eval_low0<L, F>() ? (size_t)((D - 5) * upto(L) + upto(L) - upto(L - 1))
                                         : (size_t)(D - 4) * upto(L)) * 64 * sizeof(F);
   const int64_t blocks = (nq + 63) / 64;
-  hipLaunchKernelGGL((k_eval_fast<D, L, M, F>), dim3((unsigned)blocks), dim3(64), lds, s, a, w, nq, xq, uq);
+  if constexpr (eval_fine<L, F>()) {
+    const size_t lds_f = (size_t)(D - 5) * upto(L - 1) * 64 * sizeof(F);  // see owalk_f
+    hipLaunchKernelGGL((k_eval_fine<D, L, M, F>), dim3((unsigned)blocks), dim3(64), lds_f, s, a, w, nq, xq, uq);
+  } else {
+    hipLaunchKernelGGL((k_eval_fast<D, L, M, F>), dim3((unsigned)blocks), dim3(64), lds, s, a, w, nq, xq, uq);
+  }
   return hipGetLastError();
 }
 
