@@ -18,7 +18,9 @@
 // conflict free.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
+#include <vector>
 
 #include "sgcm_internal.h"
 #include "trace.h"
@@ -630,6 +632,78 @@ __global__ __launch_bounds__(64) void k_surplus_fast(GridArgs g, const double* _
   }
 }
 
+// The subtrees of the pairs (e0, e1) of points of the two outermost
+// dimensions that wavefront s of k_surplus_split walks: o[e0 * 17 + e1] == s
+// (-1: no such pair).  Made on the host by a longest-first assignment.
+struct SplitOwners {
+  int8_t o[17 * 17];
+};
+
+// k_surplus_fast with the walk of each group of 64 nodes split over S
+// wavefronts of one workgroup: wavefront s sums the subtrees of the pairs
+// (e0, e1) it owns, and the S partial sums are added in wavefront order.  At
+// the levels where a build launch holds a few dozen wavefronts on the whole
+// device, this divides the length of its serial walk (the largest subtree,
+// that of e0 = e1 = 0, is about a third of the walk at level 3).
+template <int D, int L, int M, int S>
+__global__ __launch_bounds__(64 * S) void k_surplus_split(GridArgs g, const double* __restrict__ wsub, int64_t n,
+                                                          const int32_t* __restrict__ nodes,
+                                                          const double* __restrict__ node_xi,
+                                                          const double* __restrict__ f, double* __restrict__ w,
+                                                          SplitOwners own) {
+  static_assert(D == 6 && L >= 1 && L <= 4, "the split build covers d = 6, levels 1..4");
+  constexpr int P = upto(L), KU = 4, KO = D - KU;
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+  const bool active = q < n;
+  const int64_t node = active ? nodes[q] : 0;
+  double* lds_lane = lds + wave * (KO * P * 64) + lane;
+  double bv[KU][P];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double xi = active ? node_xi[node * D + k] : 0.5;
+    double row[kMaxPoints];
+    basis_row_l<L, double>(g, xi, row);
+    if (k < KO) {
+#pragma unroll
+      for (int e = 0; e < P; ++e) lds_lane[(k * P + e) * 64] = row[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < P; ++e) bv[k - KO][e] = row[e];
+    }
+  }
+  double acc[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) acc[c] = 0.0;
+  const int32_t* off0 = g.off + ((D - 1) * (L + 1) + L) * P;
+  for (int e0 = 0; e0 < P; ++e0) {
+    const int b1 = L - g.excess[e0];
+    const int64_t base0 = off0[e0];
+    const double p0 = lds_lane[e0 * 64];
+    const int32_t* off1 = g.off + ((D - 2) * (L + 1) + b1) * P;
+    const int c1 = upto(b1);
+    for (int e1 = 0; e1 < c1; ++e1) {
+      if (own.o[e0 * 17 + e1] != wave) continue;
+      const double p1 = p0 * lds_lane[(P + e1) * 64];
+      uwalk_budget<KU, P, M, L, double>(b1 - g.excess[e1], bv, wsub + (base0 + off1[e1]) * M, p1, acc);
+    }
+  }
+  double* part = lds + S * KO * P * 64;  // S x 64 x M partial sums
+#pragma unroll
+  for (int c = 0; c < M; ++c) part[(wave * 64 + lane) * M + c] = acc[c];
+  __syncthreads();
+  if (wave == 0 && active) {
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      double t = part[lane * M + c];
+#pragma unroll
+      for (int r = 1; r < S; ++r) t += part[(r * 64 + lane) * M + c];
+      w[node * M + c] = f[node * M + c] - t;
+    }
+  }
+}
+
 // ---- host side -------------------------------------------------------------
 
 void release(GridDevice& gd) {
@@ -800,13 +874,61 @@ hipError_t launch_surplus_fast(const GridArgs& a, const double* wsub, int64_t n,
   return hipGetLastError();
 }
 
+constexpr int kSplitWaves = 4;  // wavefronts per group of 64 nodes in k_surplus_split
+
+// The owners of the (e0, e1) subtrees of a level-L grid (d = 6) among S
+// wavefronts: longest first (the inner nodes below the pair), each to the
+// least loaded wavefront (ties: the lower index, then the canonical order).
+SplitOwners split_owners(int L, int S) {
+  SplitOwners r;
+  for (int i = 0; i < 17 * 17; ++i) r.o[i] = -1;
+  struct Item {
+    int size, e0, e1;
+  };
+  std::vector<Item> items;
+  for (int e0 = 0; e0 < upto(L); ++e0)
+    for (int e1 = 0; e1 < upto(L - excess_of(e0)); ++e1)
+      items.push_back({subgrid(4, L - excess_of(e0) - excess_of(e1)), e0, e1});
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.size > b.size; });
+  std::vector<int> load(S, 0);
+  for (const Item& it : items) {
+    int best = 0;
+    for (int k = 1; k < S; ++k)
+      if (load[k] < load[best]) best = k;
+    load[best] += it.size;
+    r.o[it.e0 * 17 + it.e1] = (int8_t)best;
+  }
+  return r;
+}
+
+template <int L, int M>
+hipError_t launch_surplus_split(const GridArgs& a, const double* wsub, int64_t n, const int32_t* nodes,
+                                const double* node_xi, const double* f, double* w, hipStream_t s) {
+  constexpr int D = 6, S = kSplitWaves;
+  static const SplitOwners own = split_owners(L, S);
+  const size_t lds = ((size_t)S * (D - 4) * upto(L) * 64 + (size_t)S * 64 * M) * sizeof(double);
+  const int64_t blocks = (n + 63) / 64;
+  hipLaunchKernelGGL((k_surplus_split<D, L, M, S>), dim3((unsigned)blocks), dim3(64 * S), lds, s, a, wsub, n,
+                     nodes, node_xi, f, w, own);
+  return hipGetLastError();
+}
+
+// Level 1 (13 nodes walked per node) keeps the one-wavefront kernel.
 template <int L>
 hipError_t surplus_fast_m(int m, const GridArgs& a, const double* wsub, int64_t n, const int32_t* nodes,
                           const double* node_xi, const double* f, double* w, hipStream_t s) {
-  switch (m) {
-    case 1: return launch_surplus_fast<L, 1>(a, wsub, n, nodes, node_xi, f, w, s);
-    case 2: return launch_surplus_fast<L, 2>(a, wsub, n, nodes, node_xi, f, w, s);
-    default: return launch_surplus_fast<L, 3>(a, wsub, n, nodes, node_xi, f, w, s);
+  if constexpr (L >= 2) {
+    switch (m) {
+      case 1: return launch_surplus_split<L, 1>(a, wsub, n, nodes, node_xi, f, w, s);
+      case 2: return launch_surplus_split<L, 2>(a, wsub, n, nodes, node_xi, f, w, s);
+      default: return launch_surplus_split<L, 3>(a, wsub, n, nodes, node_xi, f, w, s);
+    }
+  } else {
+    switch (m) {
+      case 1: return launch_surplus_fast<L, 1>(a, wsub, n, nodes, node_xi, f, w, s);
+      case 2: return launch_surplus_fast<L, 2>(a, wsub, n, nodes, node_xi, f, w, s);
+      default: return launch_surplus_fast<L, 3>(a, wsub, n, nodes, node_xi, f, w, s);
+    }
   }
 }
 
