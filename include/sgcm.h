@@ -179,12 +179,14 @@ int sgcm_solve_bvps_workspace(const sgcm_problem* p, int64_t n_bvps, size_t* byt
  * first); each BVP's outputs do not depend on that order.
  * First steps: the first Newton step is linear in the initial state (the
  * residual at Y = 0 is [-x0; 0; 0] and the Jacobian does not depend on x0).
- * With the trapezoid and n_bvps >= 64 the call therefore solves the first
- * steps of the six unit initial states first (a launch of six workgroups, in
- * the workspace) and forms every BVP's step as their combination; the
- * results are those of sgcm_solve_bvps_plan with a plan of the same problem,
- * bit for bit, and differ from a BVP's own first step by rounding only.  If
- * those six steps are singular or not finite, every BVP takes its own. */
+ * With the trapezoid and n_bvps >= 64 the call therefore computes the first
+ * steps of the six unit initial states first, in the workspace (at Y = 0
+ * every interval has the same equations, so they are made by doubling, in
+ * about log2 N dependent steps), and forms every BVP's step as their
+ * combination; the results are those of sgcm_solve_bvps_plan with a plan of
+ * the same problem, bit for bit, and differ from a BVP's own first step by
+ * rounding only.  If those six steps are not finite (a singular linearised
+ * system), every BVP takes its own. */
 int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const double* x0,
                     double* lambda0, double* u0, double* V, double* traj,
                     int32_t* status, int32_t* iters, void* workspace,
@@ -202,7 +204,7 @@ int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const double* x0,
  * looked up on the first call on a device).  A call whose workspace
  * (sgcm_solve_bvps_workspace of the same problem and count) exceeds it
  * returns SGCM_EUNSUPPORTED before any device work: at N = 256 that allows
- * about 174 BVPs per call.  Arguments, outputs and the other errors as for
+ * about 180 BVPs per call.  Arguments, outputs and the other errors as for
  * sgcm_solve_bvps.  Every call on a device uses the same array: calls that
  * overlap on one device (other streams, other threads) race and give wrong
  * results; order them.  No part of the array needs clearing between calls
@@ -232,14 +234,14 @@ int sgcm_characteristic_rhs(const sgcm_problem* p, int64_t n_points, const doubl
  * serial linear solve fewer per BVP. */
 typedef struct sgcm_plan sgcm_plan;
 
-/* Create a plan for problem p (copied).  The six steps are solved on `stream`
+/* Create a plan for problem p (copied).  The six steps are computed on `stream`
  * in FP64 whatever p->precision (which applies to the solves with the plan),
  * and the call synchronizes the stream.  With continuation they are the first
  * steps of its first stage.  On success *out owns 6 x (N+1) x 12
  * doubles of device memory on the current device.  Returns SGCM_EINVAL for an
  * invalid problem or out == NULL, SGCM_ENOMEM, SGCM_EDEVICE, and
- * SGCM_EUNSUPPORTED when the linearised step is singular or not finite (then
- * sgcm_solve_bvps reports that per BVP). */
+ * SGCM_EUNSUPPORTED when the linearised step is not finite (a singular
+ * linearised system; then sgcm_solve_bvps reports that per BVP). */
 int sgcm_plan_create(const sgcm_problem* p, void* stream, sgcm_plan** out);
 
 /* sgcm_solve_bvps for the plan's problem, each BVP's first Newton step formed
