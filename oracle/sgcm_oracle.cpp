@@ -114,7 +114,7 @@ typedef struct {
   double tol;        // Newton stopping tolerance on max|F|
   int32_t max_iter;  // Newton iterations after the first (linearised) step
   int32_t max_halvings;  // backtracking cap H of each Newton step (0: full steps)
-  int32_t continuation;  // K > 0 (two controls only): continuation stages, see solve_bvp
+  int32_t continuation;  // K > 0: continuation stages (two controls, or Example III), see solve_bvp
   int32_t scheme;        // ORC_TRAPEZOID or ORC_LOBATTO4 (collocation formula)
 } oracle_problem;
 
@@ -703,7 +703,27 @@ int64_t collocation_dim(const oracle_problem& p) {
 // final stage K, the two-control problem itself) from the solution of the one
 // before.  The status is that of the last stage solved (a failed stage ends
 // the continuation) and the iteration count is the total over the stages.
+//
+// Example III with K > 0 continues in the initial state instead: stage
+// k = 1..K solves the BVP from (k / K) xbar, the first from Y = 0 and each
+// later one from the solution of the one before (the corners of the box,
+// where the linearised first step is far from the solution, converge this
+// way); the same status and iteration rules.
 int solve_bvp(const oracle_problem& p, const double* xbar, double* Y, int* iters_out, double* fnorm_out) {
+  if (p.model == ORC_EXAMPLE3 && p.continuation > 0) {
+    int total = 0, st = ORC_CONVERGED;
+    for (int k = 1; k <= p.continuation; ++k) {
+      const double s = (double)k / p.continuation;
+      double xk[3];
+      for (int i = 0; i < 3; ++i) xk[i] = s * xbar[i];
+      int it = 0;
+      st = newton_solve(p, xk, Y, k == 1, &it, fnorm_out);
+      total += it;
+      if (st != ORC_CONVERGED) break;
+    }
+    *iters_out = total;
+    return st;
+  }
   if (p.continuation <= 0 || p.m != 2) return newton_solve(p, xbar, Y, true, iters_out, fnorm_out);
   const double* B1 = p.B;
   const double* B2 = p.B + 3;

@@ -287,6 +287,34 @@ def test_example3_closed_form_second_order(T):
     assert e_l[-1] < 3e-3 and e_u[-1] < 3e-3
 
 
+def test_example3_state_continuation():
+    # Newton from the linearised first step stalls at corners of the box for
+    # some horizons (here T = 2.5); the continuation in the initial state
+    # (stages (k / K) x0, each from the one before) converges there, to the
+    # same discrete solution wherever the plain iteration converges too, and
+    # to the closed form at second order
+    corners = np.array([[-2.0, -2.0, -2.0], [-2.0, -2.0, 2.0], [-2.0, 2.0, 2.0], [2.0, 2.0, 2.0]])
+    import dataclasses
+    plain = O.solve_bvps(example3(N=64, T=2.5), corners)
+    assert np.all(plain.status == O.MAXITER)
+    V_ref, u_ref, g_ref = example3_exact(corners, 2.5)
+    e_v, e_l = [], []
+    for N in (64, 128, 256):
+        r = O.solve_bvps(dataclasses.replace(example3(N=N, T=2.5), continuation=2), corners)
+        assert np.all(r.status == O.CONVERGED)
+        e_v.append(np.max(np.abs(r.V - V_ref)))
+        e_l.append(np.max(np.abs(r.lambda0 - g_ref)))
+    for e in (e_v, e_l):
+        orders = np.log2(np.array(e[:-1]) / np.array(e[1:]))
+        assert np.all(np.abs(orders - 2.0) < 0.25), (e, orders)
+    x0 = np.random.default_rng(33).uniform(-2.0, 2.0, (8, 3))
+    a = O.solve_bvps(example3(N=64, T=1.0), x0, want_traj=True)
+    b = O.solve_bvps(dataclasses.replace(example3(N=64, T=1.0), continuation=3), x0, want_traj=True)
+    assert np.all(a.status == O.CONVERGED) and np.all(b.status == O.CONVERGED)
+    assert np.max(np.abs(a.traj - b.traj)) <= 1e-11 * np.max(np.abs(a.traj))
+    assert np.all(b.iters >= 3)  # each of the three stages takes at least one step
+
+
 # ---------------------------------------------------------------------------
 # nonlinear rigid body: same discrete solution by other algorithms
 # ---------------------------------------------------------------------------
