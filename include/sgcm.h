@@ -67,7 +67,24 @@ typedef enum {
  *                        [0, s_phi/c_th, c_phi/c_th]].
  *   LINEARISED:  the same system linearised about x = 0: v' = w, J w' = B u
  *                (used to pin the solver by the Riccati closed form). */
-typedef enum { SGCM_MODEL_RIGID_BODY = 0, SGCM_MODEL_LINEARISED = 1 } sgcm_model;
+typedef enum {
+  SGCM_MODEL_RIGID_BODY = 0,
+  SGCM_MODEL_LINEARISED = 1,
+  /* Example III (Sec. 5.3): n = 3, m = 1,
+   *   x1' = -x1 + x2,  x2' = -x2 + g,  x3' = (q + 2 x2 g) g + s u,
+   *   cost 0.5 * integral of (g^2 + u^2) dt, no final cost,
+   * with s = 1 + x1^2 + x2^2, g = x3 / s, q = -2 x1^2 + 2 x1 x2 - 2 x2^2;
+   * u* = -s lambda3.  J, B, q_w, r_w and p_w are ignored.  FP64 and the
+   * trapezoid only; no plans or batches (SGCM_EUNSUPPORTED).  Continuation
+   * K > 0 runs in the initial state: stage k = 1..K solves the BVP from
+   * (k / K) x0, the first from the zero trajectory and each later one from
+   * the previous stage's solution (Newton's iteration from the linearised
+   * step stalls at corners of the box for some horizons); statuses and
+   * iteration counts as for the two-control continuation.  x0 and lambda0
+   * have 3 columns, u0 one, traj (N+1) x 6.  With the time variable as a
+   * grid dimension see sgcm_solve_bvps_tx. */
+  SGCM_MODEL_EXAMPLE3 = 2
+} sgcm_model;
 
 typedef enum { SGCM_FP64 = 0, SGCM_FP32 = 1 } sgcm_precision;
 
@@ -111,7 +128,7 @@ typedef enum { SGCM_TRAPEZOID = 0, SGCM_LOBATTO4 = 1 } sgcm_scheme;
  * total over the stages and max_iter applies to each. */
 typedef struct sgcm_problem {
   int32_t model;     /* sgcm_model                                            */
-  int32_t n;         /* state dimension: must be 6                            */
+  int32_t n;         /* state dimension: 6 (3 for SGCM_MODEL_EXAMPLE3)        */
   int32_t m;         /* number of controls: 1, 2 or 3                         */
   double J[3];       /* diagonal of the inertia matrix, all > 0               */
   double B[9];       /* 3 x m input matrix, column-major: B[i + 3*j]          */
@@ -129,7 +146,8 @@ typedef struct sgcm_problem {
   int32_t max_halvings; /* backtracking cap H of each counted Newton step,
                         0..60 (0: full steps; see below)                      */
   int32_t continuation; /* two controls: K > 0 continuation stages (0..64; see
-                        below); ignored for one or three controls             */
+                        below); ignored for one or three controls; for
+                        SGCM_MODEL_EXAMPLE3 stages in the initial state    */
   int32_t scheme;    /* sgcm_scheme of the collocation                       */
   int32_t sweep_batch;   /* tile of the trapezoidal solve: intervals per
                         backward-sweep batch, 8, 10, 12 or 16 (0: 8)         */
@@ -191,6 +209,25 @@ int sgcm_solve_bvps(const sgcm_problem* p, int64_t n_bvps, const double* x0,
                     double* lambda0, double* u0, double* V, double* traj,
                     int32_t* status, int32_t* iters, void* workspace,
                     size_t ws_bytes, void* stream);
+
+/* The time variable as a dimension of the sparse grid (Sec. 3.3 after
+ * Steps I-III; Sec. 5.3): the characteristic BVPs from the points
+ * (t0, x0) of a grid in (t, x), each over [t0, T] with x(t0) = x0 and the
+ * final condition at T = p->T, on p->N uniform intervals of [t0, T].  For the
+ * autonomous models here this is the BVP of the horizon T - t0 from x0, so
+ * V(t0, x0), lambda(t0) and u*(t0, x0) are the values from which the (t, x)
+ * interpolant of the value function and of the feedback is built (with
+ * sgcm_build_interpolant on the grid in (t, x)).
+ *   tx       device, n_bvps x (1 + n): rows (t0, x0), t0 <= T; a row with
+ *            t0 > T or a non-finite t0 gets SGCM_BVP_NONFINITE
+ *   (other arguments, workspace and outputs as for sgcm_solve_bvps; the
+ *   outputs are at t0, and traj holds the mesh values of [t0, T])
+ * A row with t0 = T is the final condition itself (lambda = 0, V = 0 for
+ * Example III): the mesh has zero width and the first step solves it.
+ * Supported for SGCM_MODEL_EXAMPLE3 (others: SGCM_EUNSUPPORTED). */
+int sgcm_solve_bvps_tx(const sgcm_problem* p, int64_t n_bvps, const double* tx, double* lambda0, double* u0,
+                       double* V, double* traj, int32_t* status, int32_t* iters, void* workspace,
+                       size_t ws_bytes, void* stream);
 
 /* Device scratch, in bytes, that the library holds per device for
  * sgcm_solve_bvps_static. */

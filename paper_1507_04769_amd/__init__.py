@@ -23,12 +23,13 @@ LIB_PATH = os.path.join(_HERE, "libsgcm.so")
 
 SGCM_OK, SGCM_EINVAL, SGCM_ENOMEM, SGCM_EDEVICE, SGCM_EUNSUPPORTED, SGCM_ENOTCONVERGED = 0, -1, -2, -3, -4, -5
 CONVERGED, MAXITER, SINGULAR, NONFINITE = 0, 1, 2, 3
-MODEL_RIGID_BODY, MODEL_LINEARISED = 0, 1
+MODEL_RIGID_BODY, MODEL_LINEARISED, MODEL_EXAMPLE3 = 0, 1, 2
 FP64, FP32 = 0, 1
 TRAPEZOID, LOBATTO4 = 0, 1  # collocation formulas (sgcm_scheme)
 
 # every extern "C" symbol declared in include/sgcm.h
 EXPORTS = ("sgcm_strerror", "sgcm_version", "sgcm_solve_bvps_workspace", "sgcm_solve_bvps", "sgcm_solve_bvps_static",
+           "sgcm_solve_bvps_tx",
            "sgcm_characteristic_rhs", "sgcm_plan_create", "sgcm_solve_bvps_plan", "sgcm_plan_destroy",
            "sgcm_batch_create", "sgcm_batch_workspace", "sgcm_solve_bvps_batch",
            "sgcm_batch_destroy", "sgcm_grid_create", "sgcm_grid_upload", "sgcm_grid_size", "sgcm_grid_nodes",
@@ -118,6 +119,7 @@ def lib() -> ctypes.CDLL:
         "sgcm_solve_bvps_workspace": (ctypes.c_int, [P, i64, ctypes.POINTER(ctypes.c_size_t)]),
         "sgcm_solve_bvps": (ctypes.c_int, [P, i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
         "sgcm_solve_bvps_static": (ctypes.c_int, [P, i64, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "sgcm_solve_bvps_tx": (ctypes.c_int, [P, i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
         "sgcm_characteristic_rhs": (ctypes.c_int, [P, i64, vp, vp, vp, vp]),
         "sgcm_plan_create": (ctypes.c_int, [P, vp, ctypes.POINTER(vp)]),
         "sgcm_solve_bvps_plan": (ctypes.c_int, [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
@@ -196,16 +198,18 @@ def sgcm_solve_bvps_workspace(problem: Problem, n_bvps: int) -> int:
     return int(out.value)
 
 
-def _solve_args(problem: Problem, x0, lambda0, u0, V, traj, status, iters, workspace, stream):
+def _solve_args(problem: Problem, x0, lambda0, u0, V, traj, status, iters, workspace, stream, cols=None):
     import torch
     f64, i32 = torch.float64, torch.int32
+    ns = int(problem.n)
+    cols = ns if cols is None else cols
     n = x0.shape[0] if x0 is not None else 0
-    if x0 is not None and (x0.dim() != 2 or x0.shape[1] != 6):
-        raise ValueError("x0 must be n x 6")
+    if x0 is not None and (x0.dim() != 2 or x0.shape[1] != cols):
+        raise ValueError("the initial points must be n x %d" % cols)
     ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
     m, NP = int(problem.m), int(problem.N) + 1
-    return (int(n), _ptr(x0, f64, "x0"), _ptr(lambda0, f64, "lambda0", 6 * n), _ptr(u0, f64, "u0", m * n),
-            _ptr(V, f64, "V", n), _ptr(traj, f64, "traj", 12 * NP * n), _ptr(status, i32, "status", n),
+    return (int(n), _ptr(x0, f64, "x0"), _ptr(lambda0, f64, "lambda0", ns * n), _ptr(u0, f64, "u0", m * n),
+            _ptr(V, f64, "V", n), _ptr(traj, f64, "traj", 2 * ns * NP * n), _ptr(status, i32, "status", n),
             _ptr(iters, i32, "iters", n), _ptr(workspace, None, "workspace"), ctypes.c_size_t(ws_bytes),
             _stream(stream))
 
@@ -216,6 +220,12 @@ def sgcm_solve_bvps(problem: Problem, x0, lambda0, u0, V, traj, status, iters, w
 
 
 STATIC_SCRATCH_BYTES = 64 << 20  # SGCM_STATIC_SCRATCH_BYTES
+
+
+def sgcm_solve_bvps_tx(problem: Problem, tx, lambda0, u0, V, traj, status, iters, workspace, stream=None):
+    """The BVPs from the (t0, x0) rows of tx (n x (1 + problem.n)), each over [t0, T]."""
+    args = _solve_args(problem, tx, lambda0, u0, V, traj, status, iters, workspace, stream, cols=1 + int(problem.n))
+    _check(lib().sgcm_solve_bvps_tx(ctypes.byref(problem.c()), *args), "sgcm_solve_bvps_tx")
 
 
 def sgcm_solve_bvps_static(problem: Problem, x0, lambda0, u0, V, traj, status, iters, stream=None):
@@ -256,12 +266,13 @@ def sgcm_solve_bvps_plan(plan: Plan, x0, lambda0, u0, V, traj, status, iters, wo
 
 def sgcm_characteristic_rhs(problem: Problem, y, phi, dphi=None, stream=None):
     import torch
-    if y.dim() != 2 or y.shape[1] != 12:
-        raise ValueError("y must be n x 12")
+    ny = 2 * int(problem.n)
+    if y.dim() != 2 or y.shape[1] != ny:
+        raise ValueError("y must be n x %d" % ny)
     n = y.shape[0]
     rc = lib().sgcm_characteristic_rhs(ctypes.byref(problem.c()), int(n), _ptr(y, torch.float64, "y"),
-                                       _ptr(phi, torch.float64, "phi", 12 * n),
-                                       _ptr(dphi, torch.float64, "dphi", 144 * n), _stream(stream))
+                                       _ptr(phi, torch.float64, "phi", ny * n),
+                                       _ptr(dphi, torch.float64, "dphi", ny * ny * n), _stream(stream))
     _check(rc, "sgcm_characteristic_rhs")
 
 
@@ -441,11 +452,11 @@ def solve_bvps(problem: Problem, x0, want_traj: bool = False, want_V: bool = Tru
     if plan is not None:
         problem = plan.problem
     dev = x0.device
-    n = x0.shape[0]
-    lam = torch.empty((n, 6), dtype=torch.float64, device=dev)
+    n, ns = x0.shape[0], int(problem.n)
+    lam = torch.empty((n, ns), dtype=torch.float64, device=dev)
     u0 = torch.empty((n, problem.m), dtype=torch.float64, device=dev)
     V = torch.empty((n,), dtype=torch.float64, device=dev) if want_V else None
-    traj = torch.empty((n, problem.N + 1, 12), dtype=torch.float64, device=dev) if want_traj else None
+    traj = torch.empty((n, problem.N + 1, 2 * ns), dtype=torch.float64, device=dev) if want_traj else None
     st = torch.empty((n,), dtype=torch.int32, device=dev)
     it = torch.empty((n,), dtype=torch.int32, device=dev)
     if workspace is None:
@@ -455,6 +466,27 @@ def solve_bvps(problem: Problem, x0, want_traj: bool = False, want_V: bool = Tru
         sgcm_solve_bvps_plan(plan, x0, lam, u0, V, traj, st, it, workspace, stream)
     else:
         sgcm_solve_bvps(problem, x0, lam, u0, V, traj, st, it, workspace, stream)
+    return BVPSolution(lam, u0, V, traj, st, it)
+
+
+def solve_bvps_tx(problem: Problem, tx, want_traj: bool = False, want_V: bool = True, workspace=None,
+                  stream=None) -> BVPSolution:
+    """The BVPs from the points (t0, x0) of a grid in (t, x) (rows of tx,
+    n x (1 + problem.n), device), each over [t0, problem.T]: the time
+    variable as a grid dimension (Sec. 5.3)."""
+    import torch
+    dev = tx.device
+    n, ns = tx.shape[0], int(problem.n)
+    lam = torch.empty((n, ns), dtype=torch.float64, device=dev)
+    u0 = torch.empty((n, problem.m), dtype=torch.float64, device=dev)
+    V = torch.empty((n,), dtype=torch.float64, device=dev) if want_V else None
+    traj = torch.empty((n, problem.N + 1, 2 * ns), dtype=torch.float64, device=dev) if want_traj else None
+    st = torch.empty((n,), dtype=torch.int32, device=dev)
+    it = torch.empty((n,), dtype=torch.int32, device=dev)
+    if workspace is None:
+        nbytes = sgcm_solve_bvps_workspace(problem, n)
+        workspace = torch.empty((max(nbytes, 256) + 255) // 256 * 32, dtype=torch.float64, device=dev)
+    sgcm_solve_bvps_tx(problem, tx, lam, u0, V, traj, st, it, workspace, stream)
     return BVPSolution(lam, u0, V, traj, st, it)
 
 
@@ -481,8 +513,9 @@ def solve_bvps_batch(batch: Batch, x0, want_V: bool = True, workspace=None, stre
 
 def characteristic_rhs(problem: Problem, y, jacobian: bool = True, stream=None):
     import torch
+    ny = 2 * int(problem.n)
     phi = torch.empty_like(y)
-    dphi = torch.empty((y.shape[0], 12, 12), dtype=torch.float64, device=y.device) if jacobian else None
+    dphi = torch.empty((y.shape[0], ny, ny), dtype=torch.float64, device=y.device) if jacobian else None
     sgcm_characteristic_rhs(problem, y, phi, dphi, stream)
     return phi, dphi
 

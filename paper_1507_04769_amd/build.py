@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsgcm.so")
-SOURCES = ["grid.cpp", "capi.cpp", "bvp.hip", "first_steps.hip", "lobatto.hip", "interp.hip", "validate.hip"]
+SOURCES = ["grid.cpp", "capi.cpp", "bvp.hip", "first_steps.hip", "example3.hip", "lobatto.hip", "interp.hip", "validate.hip"]
 ARCH = os.environ.get("SGCM_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled for all device code.

@@ -1137,6 +1137,7 @@ int64_t bvp_doubles(int64_t N, int fp32) {
 // Validate a problem and derive the kernel arguments.
 int make_bvp_args(const sgcm_problem* p, BvpArgs* a) {
   if (!p) return SGCM_EINVAL;
+  if (p->model == SGCM_MODEL_EXAMPLE3) return SGCM_EUNSUPPORTED;  // its own solver (example3.hip)
   if (p->model != SGCM_MODEL_RIGID_BODY && p->model != SGCM_MODEL_LINEARISED) return SGCM_EINVAL;
   if (p->n != 6 || p->m < 1 || p->m > 3) return SGCM_EINVAL;
   for (int i = 0; i < 3; ++i)
@@ -1301,6 +1302,7 @@ static int first_step_args(const sgcm_problem* p, BvpArgs* qa) {
 extern "C" int sgcm_solve_bvps_workspace(const sgcm_problem* p, int64_t n_bvps, size_t* bytes) {
   BvpArgs a;
   if (!bytes || n_bvps < 0) return SGCM_EINVAL;
+  if (p && p->model == SGCM_MODEL_EXAMPLE3) return ex3_workspace(p, n_bvps, bytes);
   int rc = make_bvp_args(p, &a);
   if (rc != SGCM_OK) return rc;
   *bytes = (size_t)a.per_bvp * sizeof(double) * (size_t)n_bvps + order_bytes(n_bvps) +
@@ -1314,6 +1316,8 @@ static int solve_bvps(const sgcm_problem* p, const double* y1, int64_t n_bvps, c
                size_t ws_bytes, void* stream) {
   BvpArgs a;
   if (n_bvps < 0) return SGCM_EINVAL;
+  if (p && p->model == SGCM_MODEL_EXAMPLE3 && !y1)
+    return ex3_solve(p, n_bvps, x0, 0, lambda0, u0, V, traj, status, iters, workspace, ws_bytes, stream);
   int rc = make_bvp_args(p, &a);
   if (rc != SGCM_OK) return rc;
   a.y1 = y1;
@@ -1525,6 +1529,7 @@ extern "C" int sgcm_characteristic_rhs(const sgcm_problem* p, int64_t n_points, 
   sgcm::CallRange range("sgcm_characteristic_rhs");
   BvpArgs a;
   if (n_points < 0) return SGCM_EINVAL;
+  if (p && p->model == SGCM_MODEL_EXAMPLE3) return ex3_characteristic_rhs(p, n_points, y, phi, dphi, stream);
   int rc = make_bvp_args(p, &a);
   if (rc != SGCM_OK) return rc;
   if (n_points == 0) return SGCM_OK;

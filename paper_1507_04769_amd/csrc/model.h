@@ -213,6 +213,18 @@ __device__ __forceinline__ void lds_handoff() {
 // SGCM_BVP_NONFINITE when the steps are not finite.  Two launches on stream s.
 int launch_first_steps(const BvpArgs& a, int N, double* y1, int32_t* chk, hipStream_t s);
 
+// ---- Example III and the time dimension (example3.hip) ----------------------
+
+// Workspace, solve and characteristic right-hand side for the model
+// SGCM_MODEL_EXAMPLE3 (its own solver).  ex3_solve: rows are (t0, x0) (tx = 1)
+// or x0 (tx = 0, t0 = 0); arguments and errors as for sgcm_solve_bvps.
+int ex3_workspace(const sgcm_problem* p, int64_t n_bvps, size_t* bytes);
+int ex3_solve(const sgcm_problem* p, int64_t n_bvps, const double* rows, int tx, double* lambda0, double* u0,
+              double* V, double* traj, int32_t* status, int32_t* iters, void* workspace, size_t ws_bytes,
+              void* stream);
+int ex3_characteristic_rhs(const sgcm_problem* p, int64_t n_points, const double* y, double* phi, double* dphi,
+                           void* stream);
+
 // ---- four-point Lobatto IIIA collocation (lobatto.hip) ----------------------
 
 // Workspace of one BVP of the Lobatto solver, in doubles (a multiple of 32).

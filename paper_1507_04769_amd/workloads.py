@@ -133,3 +133,24 @@ def sample_indices(total: int, k: int, seed: int) -> np.ndarray:
     """k distinct indices of range(total), sorted, PCG64(seed)."""
     k = min(k, total)
     return np.sort(np.random.default_rng(seed).choice(total, size=k, replace=False))
+
+
+# Example III of Sec. 5.3 with the time variable as a grid dimension: the
+# sparse grid in (t, x) over [0, 5] x [-2, 2]^3 (the paper's region D), the
+# final time T = 5 (the paper does not state T; the closed form holds for any
+# T >= 5), N = 64 intervals on every [t0, T], continuation in the initial
+# state in two stages, and the paper's 1200 uniform validation points in D.
+EX3_LO = np.array([0.0, -2.0, -2.0, -2.0])
+EX3_HI = np.array([5.0, 2.0, 2.0, 2.0])
+EX3_T = 5.0
+EX3_N = 64
+EX3_CONTINUATION = 2
+EX3_LEVEL = 5
+EX3_SAMPLES = 1200
+EX3_SAMPLE_SEED = 53
+
+
+def ex3_samples(n: int = EX3_SAMPLES, seed: int = EX3_SAMPLE_SEED) -> np.ndarray:
+    """n points (t, x) uniform in the region D of Example III."""
+    return uniform_in_box(n, seed, EX3_LO, EX3_HI)
+

@@ -228,3 +228,32 @@ def test_tile_validation():
     for kw in (dict(sweep_batch=9), dict(sweep_batch=14), dict(sweep_batch=20), dict(forward_chunk=10),
                dict(forward_chunk=16)):
         assert _ws(S.Problem(**kw), 1)[0] == S.SGCM_EUNSUPPORTED, kw
+
+
+def _ex3(**kw):
+    base = dict(model=S.MODEL_EXAMPLE3, n=3, m=1, T=5.0, N=64, tol=1e-10, max_iter=20)
+    base.update(kw)
+    return S.Problem(**base)
+
+
+def test_example3_validation():
+    # Example III (Sec. 5.3): its own workspace (Y, trial point, step and
+    # residual, Phi and its Jacobian per mesh point, 24 sweep values per
+    # interval, rounded up to 32 doubles), validated before device work
+    NP = 65
+    per = (NP * 6 * 4 + NP * 6 + NP * 36 + 64 * 24 + 31) // 32 * 32
+    assert _ws(_ex3(), 7) == (S.SGCM_OK, 7 * per * 8)
+    assert _ws(_ex3(continuation=2), 1) == (S.SGCM_OK, per * 8)
+    for kw in (dict(n=6), dict(m=3), dict(T=0.0), dict(N=0), dict(max_iter=-1), dict(continuation=65)):
+        assert _ws(_ex3(**kw), 1)[0] == S.SGCM_EINVAL, kw
+    for kw in (dict(precision=S.FP32), dict(scheme=S.LOBATTO4)):
+        assert _ws(_ex3(**kw), 1)[0] == S.SGCM_EUNSUPPORTED, kw
+    L = S.lib()
+    p = _ex3()
+    args = (None,) * 8 + (0, None)
+    assert L.sgcm_solve_bvps_tx(ctypes.byref(p.c()), 0, *args) == S.SGCM_OK
+    assert L.sgcm_solve_bvps_tx(ctypes.byref(p.c()), 3, *args) == S.SGCM_EINVAL
+    # the (t, x) solve covers Example III only; plans and batches none of it
+    assert L.sgcm_solve_bvps_tx(ctypes.byref(S.Problem().c()), 3, *args) == S.SGCM_EUNSUPPORTED
+    h = ctypes.c_void_p()
+    assert L.sgcm_plan_create(ctypes.byref(p.c()), None, ctypes.byref(h)) == S.SGCM_EUNSUPPORTED
