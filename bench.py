@@ -250,6 +250,82 @@ def small_leg(dev, steps: int, warmup: int, with_cpu: bool) -> dict:
     return out
 
 
+def time_dimension_leg(dev, steps: int, warmup: int, with_cpu: bool) -> dict:
+    """Example III with the time variable as a grid dimension (Sec. 5.3):
+    the level-5 grid in (t, x) over [0, 5] x [-2, 2]^3, one step = the BVPs of
+    every node over [t0, T] (sgcm_solve_bvps_tx), the interpolants of V and
+    u* on that grid, and their evaluation at the paper's 1200 validation
+    points; errors against the closed form there (the paper reports the MAE
+    of V on its level-8 grid)."""
+    import torch
+    import paper_1507_04769_amd as S
+    from paper_1507_04769_amd import workloads as W
+    prob = S.Problem(model=S.MODEL_EXAMPLE3, n=3, m=1, T=W.EX3_T, N=W.EX3_N, tol=W.TOL, max_iter=W.MAX_ITER,
+                     max_halvings=W.MAX_HALVINGS, continuation=W.EX3_CONTINUATION)
+    grid = S.Grid(4, W.EX3_LEVEL, W.EX3_LO, W.EX3_HI)
+    nodes = grid.nodes()
+    M = len(grid)
+    q_host = W.ex3_samples()
+    tx, q = torch.tensor(nodes, device=dev), torch.tensor(q_host, device=dev)
+    lam = torch.empty((M, 3), dtype=torch.float64, device=dev)
+    V = torch.empty((M,), dtype=torch.float64, device=dev)
+    u0 = torch.empty((M, 1), dtype=torch.float64, device=dev)
+    st = torch.empty((M,), dtype=torch.int32, device=dev)
+    it = torch.empty((M,), dtype=torch.int32, device=dev)
+    ws = torch.empty((S.sgcm_solve_bvps_workspace(prob, M) // 8 + 32,), dtype=torch.float64, device=dev)
+    wV = torch.empty((M, 1), dtype=torch.float64, device=dev)
+    wu = torch.empty((M, 1), dtype=torch.float64, device=dev)
+    qV = torch.empty((len(q_host), 1), dtype=torch.float64, device=dev)
+    qu = torch.empty((len(q_host), 1), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    grid.upload(stream)
+
+    def step(ev):
+        if ev is not None:
+            ev[0].record(stream)
+        S.sgcm_solve_bvps_tx(prob, tx, lam, u0, V, None, st, it, ws, stream)
+        if ev is not None:
+            ev[1].record(stream)
+        S.sgcm_build_interpolant(grid, V.view(M, 1), wV, stream)
+        S.sgcm_build_interpolant(grid, u0, wu, stream)
+        S.sgcm_eval_feedback(grid, wV, q, qV, S.FP64, stream)
+        S.sgcm_eval_feedback(grid, wu, q, qu, S.FP64, stream)
+        if ev is not None:
+            ev[2].record(stream)
+
+    events, _ = timed_steps(step, steps, warmup, stream, 3)
+    solve_ms = np.array([e[0].elapsed_time(e[1]) for e in events])
+    rest_ms = np.array([e[1].elapsed_time(e[2]) for e in events])
+    conv = int((st == S.CONVERGED).sum().item())
+    s = 1.0 + q_host[:, 1] ** 2 + q_host[:, 2] ** 2
+    y = q_host[:, 3] / s
+    th = np.tanh(W.EX3_T - q_host[:, 0])
+    V_ex, u_ex = 0.5 * y * y * th, -y * th
+    eV, eu = qV.cpu().numpy()[:, 0] - V_ex, qu.cpu().numpy()[:, 0] - u_ex
+    its = it.cpu().numpy()
+    out = {"workload": "example3-tx-L%d-N%d" % (W.EX3_LEVEL, W.EX3_N), "grid": "(t, x) in [0, 5] x [-2, 2]^3, d = 4",
+           "grid_nodes": M, "intervals": W.EX3_N, "T": W.EX3_T, "continuation_stages": W.EX3_CONTINUATION,
+           "converged": conv, "iters_max": int(its.max()), "iters_mean": float(its.mean()),
+           "solve_ms": float(np.median(solve_ms)), "bvps_per_s": conv / (float(np.median(solve_ms)) / 1e3),
+           "build_and_eval_ms": float(np.median(rest_ms)), "samples": len(q_host),
+           "V_error": {"mae": float(np.mean(np.abs(eV))), "max": float(np.max(np.abs(eV))), "var": float(np.var(eV))},
+           "u_error": {"mae": float(np.mean(np.abs(eu))), "max": float(np.max(np.abs(eu)))}}
+    if with_cpu:
+        from oracle import oracle as O
+        t = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            for tv in np.unique(nodes[:, 0]):
+                idx = np.where(nodes[:, 0] == tv)[0]
+                op = O.Problem(model=O.EXAMPLE3, n=3, m=1, T=W.EX3_T - tv, N=W.EX3_N, tol=W.TOL,
+                               max_iter=W.MAX_ITER, max_halvings=W.MAX_HALVINGS, continuation=W.EX3_CONTINUATION)
+                O.solve_bvps(op, nodes[idx, 1:])
+            t.append(time.perf_counter() - t0)
+        out["cpu_oracle_solve"] = {"cores": O.default_threads(), "ms": float(np.median(t)) * 1e3,
+                                   "bvps_per_s": M / float(np.median(t))}
+    return out
+
+
 def batched_leg(dev, reps: int) -> dict:
     """The mixed batch (3072 level-5 nodes + 1024 uniform states, N in
     {64..512}, T in {10, 20, 40}): one persistent launch with the autotuned
@@ -605,6 +681,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pipelined", action="store_true", help="skip the two-stream pipelined steps")
     ap.add_argument("--no-small", action="store_true", help="skip the small-workload line")
+    ap.add_argument("--no-time-dimension", action="store_true",
+                    help="skip the Example III leg with the time variable as a grid dimension")
     ap.add_argument("--cpu-queries", type=int, default=20000)
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-batch leg")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32 and underactuated legs")
@@ -735,6 +813,10 @@ def main():
     if args.workload == "full" and not args.no_small:
         small = small_leg(dev, args.steps, args.warmup, not args.no_cpu_baseline)
 
+    time_dim = None
+    if args.workload == "full" and not args.no_time_dimension:
+        time_dim = time_dimension_leg(dev, args.steps, args.warmup, not args.no_cpu_baseline)
+
     batched = None if args.no_batched or args.workload != "full" else batched_leg(dev, 5)
     precision = underactuated = None
     if not args.no_precision and args.workload == "full":
@@ -804,6 +886,8 @@ def main():
         out["pipelined"] = pipelined
     if small is not None:
         out["small_workload"] = small
+    if time_dim is not None:
+        out["time_dimension"] = time_dim
     if batched is not None:
         out["batched"] = batched
     if precision is not None:
