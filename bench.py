@@ -373,10 +373,11 @@ def batched_leg(dev, reps: int) -> dict:
 
 def swept_steps_roofline(N: int, iters: np.ndarray, n_bvps: int, ms: float) -> dict:
     """The one-shot solve counted by the interval steps it sweeps: with 64 or
-    more BVPs the call solves the first steps of the six unit initial states
-    and every BVP combines them, so it sweeps N (sum of iterations + 6)
-    steps; below 64 every BVP sweeps its own first step too."""
-    steps = float(N * (np.sum(iters) + 6)) if n_bvps >= 64 else float(np.sum(N * (iters + 1.0)))
+    more BVPs the call computes the first steps of the six unit initial
+    states by doubling (no sweep) and every BVP combines them, so it sweeps
+    N x (sum of iterations) steps; below 64 every BVP sweeps its own first
+    step too."""
+    steps = float(N * np.sum(iters)) if n_bvps >= 64 else float(np.sum(N * (iters + 1.0)))
     flops = FLOPS_PER_INTERVAL_STEP * steps
     achieved = flops / (ms / 1e3) / 1e12
     return {"interval_steps": steps, "flops": flops, "achieved": achieved, "frac": achieved / PEAK_FP64_TFLOPS}
@@ -604,7 +605,7 @@ def pipelined_leg(prob, grid, x0, xq, m: int, steps: int, warmup: int, ref_u0, r
     sets of solve outputs, so that a solve never overwrites node values that
     a build still reads).  The short evaluation launch fills the compute
     units that the solve's longest BVPs leave idle near its end, and the
-    six-workgroup launch of the unit first steps.  Throughput = steps / host
+    first steps' launch.  Throughput = steps / host
     wall time between two device synchronisations; every step's results are
     checked against the sequential step's."""
     import torch
@@ -748,7 +749,7 @@ def main():
         return step
 
     # the headline: one-shot steps (nothing made beforehand; from 64 BVPs the
-    # call solves the six unit initial states' first steps and combines them)
+    # call computes the six unit initial states' first steps and combines them)
     events, wall = timed_steps(make_step(lambda: S.sgcm_solve_bvps(prob, x0, lam, u0, V, traj, st, it, ws,
                                                                    stream)), args.steps, args.warmup, stream, 4)
     step_ms = np.array([e[0].elapsed_time(e[3]) for e in events])
@@ -857,7 +858,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "grid_level": wl.level, "grid_nodes": M, "state_dim": 6,
                    "controls": wl.m, "intervals": wl.n_intervals, "horizon": wl.horizon, "tol": W.TOL,
-                   "queries": len(xq_host), "query_seed": wl.query_seed, "first_newton_step": ("combined from the six unit-state first steps solved inside the call"
+                   "queries": len(xq_host), "query_seed": wl.query_seed, "first_newton_step": ("combined from the six unit-state first steps computed by doubling inside the call"
                                          if M >= 64 else "solved per BVP")},
         "feedback_evals_per_s": len(xq_host) / (float(np.mean(eval_ms)) / 1e3),
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
@@ -866,7 +867,7 @@ def main():
         "converged": converged,
         "newton_iters_hist": np.bincount(iters).tolist(),
         "wall_s_timed": wall,
-        "roofline": {"kernel": "k_newton (sgcm_solve_bvps: the unit first steps, k_order and the main launch)", "bound": "alu", "achieved": achieved,
+        "roofline": {"kernel": "k_newton (sgcm_solve_bvps: the first steps by doubling, k_order and the main launch)", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": measured_traffic() if wl.name == W.FULL.name else None,
                      "algorithmic_flops_per_launch": flops,

@@ -76,9 +76,9 @@ def test_cpu_model_is_named():
 
 def test_swept_steps_by_hand():
     B = load_bench()
-    iters = np.array([0, 2, 3, 4] * 16)  # 64 BVPs: the call forms the first steps from six unit solves
+    iters = np.array([0, 2, 3, 4] * 16)  # 64 BVPs: the first steps from the six unit states' (by doubling)
     r = B.swept_steps_roofline(256, iters, len(iters), 1.0)
-    assert r["interval_steps"] == 256 * (iters.sum() + 6)
+    assert r["interval_steps"] == 256 * iters.sum()
     assert np.isclose(r["flops"], 6500.0 * r["interval_steps"])
     assert np.isclose(r["achieved"], r["flops"] / 1e-3 / 1e12) and np.isclose(r["frac"], r["achieved"] / 78.6)
     # below 64 BVPs every BVP sweeps its own first step: the per-BVP count
