@@ -17,8 +17,9 @@
 // and the linear solve a backward Riccati sweep over the intervals.  Each
 // interval's equations, written as an affine map of (dx_{k-1}, dlambda_k) to
 // (dx_k, dlambda_{k-1}), come from one 6 x 6 elimination (one matrix column
-// per lane); the 3 x 3 Riccati step dlambda_k = P_k dx_k + p_k then runs in
-// every lane alike, and a forward pass recovers dx_k and dlambda_k.
+// per lane, four intervals at a time: they do not depend on the sweep); the
+// 3 x 3 Riccati step dlambda_k = P_k dx_k + p_k then runs in every lane alike,
+// and a forward pass recovers dx_k and dlambda_k.
 #include <cmath>
 #include <cstdint>
 
@@ -116,10 +117,11 @@ struct Ex3Args {
 
 // Workspace of one BVP, in doubles: Y, the trial point, the Newton step and
 // the residual ((N + 1) x 6 each), Phi and its Jacobian at the mesh points
-// ((N + 1) x 6 and (N + 1) x 36), and the sweep's 24 values per interval.
+// ((N + 1) x 6 and (N + 1) x 36), the sweep's 24 values per interval and
+// the interval elements (6 x 7 per interval).
 __host__ __device__ inline int64_t ex3_doubles(int N) {
   const int64_t NP = (int64_t)N + 1;
-  const int64_t d = NP * 6 * 4 + NP * 6 + NP * 36 + (int64_t)N * 24;
+  const int64_t d = NP * 6 * 4 + NP * 6 + NP * 36 + (int64_t)N * 24 + (int64_t)N * 42;
   return (d + 31) / 32 * 32;
 }
 
@@ -180,21 +182,19 @@ __device__ double ex3_residual(const Ex3Args& A, double alpha, const double* xba
 // The Newton step d solving F'(Z) d = -F (F, PH, DJ at Z), by the backward
 // Riccati sweep and the forward pass; false on a zero pivot.
 __device__ bool ex3_newton_step(const Ex3Args& A, double alpha, const double* DJ, const double* F, double* SW,
-                                double* d, double* lds) {
+                                double* SWE, double* d) {
   const int lane = threadIdx.x, N = A.N;
-  // P and p at the right end: dlambda_N = 0 dx_N - F_N
-  double P[9], p[3];
-#pragma unroll
-  for (int e = 0; e < 9; ++e) P[e] = 0.0;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) p[i] = -F[3 + 6 * N + i];
   bool regular = true;
-  for (int k = N; k >= 1; --k) {
-    // [Q | R_x | -L_lambda | -r] with L = I - alpha J_k, R = I + alpha J_{k-1}:
-    // column l of the augmented matrix in lane l (l < 13)
+  // The interval elements do not depend on the Riccati matrix: all of them
+  // first, four intervals at a time (one per group of 16 lanes).  Interval
+  // k's augmented matrix [Q | R_x | -L_lambda | -r], L = I - alpha J_k,
+  // R = I + alpha J_{k-1}: column l in the group's lane l (l < 13).
+  const int grp = lane >> 4, l0 = lane & 15;
+  for (int kb = 1; kb <= N; kb += 4) {
+    const int k = kb + grp <= N ? kb + grp : N;  // groups past N repeat interval N
     const double* J1 = DJ + 36 * k;
     const double* J0 = DJ + 36 * (k - 1);
-    const int l = lane < 13 ? lane : 12;
+    const int l = l0 < 13 ? l0 : 12;
     double v[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
@@ -206,16 +206,27 @@ __device__ bool ex3_newton_step(const Ex3Args& A, double alpha, const double* DJ
       else x = -F[3 + 6 * (k - 1) + i];
       v[i] = x;
     }
-    regular = gauss_jordan<6>(v) && regular;
-    // the element: lanes 6..8 [A; C], 9..11 [B; D], 12 [a; c]; to LDS
-    if (lane >= 6 && lane < 13) {
+    regular = gauss_jordan<6, 16>(v) && regular;
+    // the element (6 x 7, row-major): the group's lanes 6..8 hold [A; C],
+    // 9..11 [B; D], 12 [a; c]
+    if (kb + grp <= N && l0 >= 6 && l0 < 13) {
+      double* E = SWE + 42 * (int64_t)(k - 1);
 #pragma unroll
-      for (int i = 0; i < 6; ++i) lds[i * 7 + (lane - 6)] = v[i];
+      for (int i = 0; i < 6; ++i) E[i * 7 + (l0 - 6)] = v[i];
     }
-    wave_lds_sync();
-    // element blocks, read from LDS where used: A, B (rows 0..2), C, D (rows
-    // 3..5), a, c (column 6)
-    const double* E = lds;
+  }
+  wave_mem_sync();
+  regular = __all(regular);
+  // P and p at the right end: dlambda_N = 0 dx_N - F_N
+  double P[9], p[3];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) P[e] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) p[i] = -F[3 + 6 * N + i];
+  for (int k = N; k >= 1; --k) {
+    // element blocks, read where used: A, B (rows 0..2), C, D (rows 3..5),
+    // a, c (column 6)
+    const double* E = SWE + 42 * (int64_t)(k - 1);
 #define EA(i, j) E[(i) * 7 + (j)]
 #define EB(i, j) E[(i) * 7 + 3 + (j)]
 #define EC(i, j) E[(3 + (i)) * 7 + (j)]
@@ -312,7 +323,6 @@ __device__ bool ex3_newton_step(const Ex3Args& A, double alpha, const double* DJ
 #undef EB
 #undef EC
 #undef ED
-    lds_handoff();  // the next interval's element overwrites E
   }
   wave_mem_sync();
   // forward: dx_0 = -F_0, dlambda_k = P_k dx_k + p_k, dx_k = MA_k dx_{k-1} + Mb_k
@@ -367,7 +377,7 @@ __device__ bool ex3_newton_step(const Ex3Args& A, double alpha, const double* DJ
 // the first step in full (from_zero), else from Y with its test.  Returns the
 // status and writes the iteration count.
 __device__ int ex3_newton(const Ex3Args& A, double alpha, const double* xbar, bool from_zero, double* Y,
-                          double* Yt, double* D, double* F, double* PH, double* DJ, double* SW, double* lds,
+                          double* Yt, double* D, double* F, double* PH, double* DJ, double* SW, double* SWE,
                           int* iters) {
   const int lane = threadIdx.x, NP = A.N + 1;
   *iters = 0;
@@ -375,7 +385,7 @@ __device__ int ex3_newton(const Ex3Args& A, double alpha, const double* xbar, bo
     for (int i = lane; i < 6 * NP; i += 64) Y[i] = 0.0;
     wave_mem_sync();
     (void)ex3_residual(A, alpha, xbar, Y, PH, DJ, true, F);
-    if (!ex3_newton_step(A, alpha, DJ, F, SW, D, lds)) return SGCM_BVP_SINGULAR;
+    if (!ex3_newton_step(A, alpha, DJ, F, SW, SWE, D)) return SGCM_BVP_SINGULAR;
     for (int i = lane; i < 6 * NP; i += 64) Y[i] += D[i];
     wave_mem_sync();
   }
@@ -386,7 +396,7 @@ __device__ int ex3_newton(const Ex3Args& A, double alpha, const double* xbar, bo
     if (fn <= A.tol) return SGCM_BVP_CONVERGED;
     if (it == A.max_iter) return SGCM_BVP_MAXITER;
     (void)ex3_residual(A, alpha, xbar, Y, PH, DJ, true, F);
-    if (!ex3_newton_step(A, alpha, DJ, F, SW, D, lds)) return SGCM_BVP_SINGULAR;
+    if (!ex3_newton_step(A, alpha, DJ, F, SW, SWE, D)) return SGCM_BVP_SINGULAR;
     double t = 1.0;
     for (int j = 0;; ++j) {
       for (int i = lane; i < 6 * NP; i += 64) Yt[i] = Y[i] + t * D[i];
@@ -407,7 +417,6 @@ __global__ __launch_bounds__(64) void k_ex3_newton(Ex3Args A, const double* __re
                                                    double* __restrict__ Vout, double* __restrict__ traj,
                                                    int32_t* __restrict__ status, int32_t* __restrict__ iters,
                                                    double* __restrict__ ws) {
-  __shared__ double lds[6 * 7];
   const int lane = threadIdx.x;
   const int64_t b = blockIdx.x;
   const int N = A.N, NP = N + 1;
@@ -418,6 +427,7 @@ __global__ __launch_bounds__(64) void k_ex3_newton(Ex3Args A, const double* __re
   double* PH = F + 6 * (int64_t)NP;
   double* DJ = PH + 6 * (int64_t)NP;
   double* SW = DJ + 36 * (int64_t)NP;
+  double* SWE = SW + 24 * (int64_t)N;
   const int rs = A.tx ? 4 : 3;
   const double t0 = A.tx ? rows[b * rs] : 0.0;
   double xbar[3];
@@ -440,7 +450,7 @@ __global__ __launch_bounds__(64) void k_ex3_newton(Ex3Args A, const double* __re
 #pragma unroll
       for (int i = 0; i < 3; ++i) xk[i] = A.K > 0 ? sk * xbar[i] : xbar[i];
       int its = 0;
-      st = ex3_newton(A, alpha, xk, k == 1, Y, Yt, D, F, PH, DJ, SW, lds, &its);
+      st = ex3_newton(A, alpha, xk, k == 1, Y, Yt, D, F, PH, DJ, SW, SWE, &its);
       it += its;
       if (st != SGCM_BVP_CONVERGED) break;
     }

@@ -19,17 +19,19 @@ __device__ __forceinline__ double bcast(double x, int from) {
 // Gauss-Jordan elimination with partial pivoting of an n-row augmented matrix
 // whose column l is v in lane l (lanes 0..n-1: the square part): afterwards
 // the lanes of the other columns hold the solution's columns.  A zero pivot
-// leaves non-finite values.  Every lane of the wavefront takes part.
-// Returns false when a pivot was exactly zero (the values are then not
-// finite).
-template <int n>
+// leaves non-finite values.  Every lane of the wavefront takes part.  With
+// W < 64 every group of W consecutive lanes eliminates a matrix of its own
+// (column l in the group's lane l; the pivot column is then read with a lane
+// permute instead of readlane).  Returns false when a pivot was exactly zero
+// (the values are then not finite).
+template <int n, int W = 64>
 __device__ __forceinline__ bool gauss_jordan(double (&v)[n]) {
   bool regular = true;
 #pragma unroll
   for (int c = 0; c < n; ++c) {
     double col[n];
 #pragma unroll
-    for (int i = 0; i < n; ++i) col[i] = bcast(v[i], c);
+    for (int i = 0; i < n; ++i) col[i] = W == 64 ? bcast(v[i], c) : __shfl(v[i], c, W);
     int p = c;
     double best = fabs(col[c]);
 #pragma unroll
