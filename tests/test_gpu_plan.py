@@ -192,15 +192,22 @@ def test_first_steps_by_doubling_match_the_oracle():
     # from 64 BVPs a call forms each BVP's first Newton step from the steps
     # of the six unit initial states, which it computes by doubling; with
     # max_iter = 0 the trajectory is that step (then tested): it equals the
-    # oracle's first step for meshes of 1 to 512 intervals (powers of two
-    # and not), short and long horizons, three wheels, two wheels and the
-    # linear model, and the per-BVP first step of a call of 63 BVPs
+    # oracle's first step for meshes of 1 to 4096 intervals (powers of two
+    # and not), horizons from 1e-3 to 40, three wheels, two wheels, the
+    # linear model and no final cost, and the per-BVP first step of a call
+    # of 63 BVPs
     cases = [(S.MODEL_RIGID_BODY, 3, 1, 0.5), (S.MODEL_RIGID_BODY, 3, 2, 20.0), (S.MODEL_RIGID_BODY, 3, 3, 5.0),
              (S.MODEL_RIGID_BODY, 3, 37, 5.0), (S.MODEL_RIGID_BODY, 3, 100, 20.0),
              (S.MODEL_RIGID_BODY, 3, 256, 20.0), (S.MODEL_RIGID_BODY, 3, 512, 40.0),
-             (S.MODEL_LINEARISED, 3, 255, 10.0), (S.MODEL_RIGID_BODY, 2, 64, 20.0), (S.MODEL_RIGID_BODY, 2, 129, 5.0)]
-    for model, m, N, T in cases:
-        gp, op = problems(model=model, m=m, N=N, T=T, max_iter=0)
+             (S.MODEL_LINEARISED, 3, 255, 10.0), (S.MODEL_RIGID_BODY, 2, 64, 20.0), (S.MODEL_RIGID_BODY, 2, 129, 5.0),
+             (S.MODEL_RIGID_BODY, 3, 4096, 40.0), (S.MODEL_RIGID_BODY, 3, 100, 1e-3)]
+    import dataclasses
+    for model, m, N, T in cases + [("p_w = 0", 3, 64, 20.0)]:
+        if model == "p_w = 0":  # no final cost: P_N = 0 in the doubling's Riccati matrices
+            gp, op = problems(N=N, T=T, max_iter=0)
+            gp, op = dataclasses.replace(gp, p_w=0.0), dataclasses.replace(op, p_w=0.0)
+        else:
+            gp, op = problems(model=model, m=m, N=N, T=T, max_iter=0)
         x0 = W.uniform_in_box(64, seed=170 + N)
         g = solve(gp, x0)
         o = O.solve_bvps(op, x0, want_traj=True)
