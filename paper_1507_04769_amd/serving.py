@@ -27,8 +27,13 @@ Completions are event driven: one waiter thread per stream watches the
 completion event of each launch of its stream in launch order (launches on
 one stream complete in order; the event is queried every 50 us, since a
 blocking wait in the runtime delayed the launches issued meanwhile on other
-streams) and hands the launch to the loop, which sleeps until a completion
-or the next arrival.  Every output of
+streams), then copies the launch's outputs to the host and hands the launch
+to the loop, which sleeps until a completion or the next arrival.  The output
+copies are issued only once the launch's kernels have completed: the runtime
+carries out the copies of all streams in the order they were issued, so an
+output copy queued behind a two-wheel solve (tens of ms) held up the input
+copy, and so the kernels, of every launch issued after it on any stream
+(queries waited up to 90 ms for a kernel of 0.1 ms).  Every output of
 a request depends only on that request's inputs (BVPs and query points are
 independent), so a request's results are the same alone and in any mix; the
 tests check this bitwise.  Latency = completion - arrival on the host clock.
@@ -111,10 +116,11 @@ def build_interpolant(level: int, N: int = 64):
 class _Launch:
     reqs: list
     stream: object
-    event: object
+    event: object       # the launch's kernels have completed
     nbytes: int
-    outs: tuple
+    dev_outs: tuple     # device outputs, copied to the host once `event` fires
     cls: str = ""
+    outs: tuple = ()    # host outputs
 
 
 def work_class(key) -> str:
@@ -243,8 +249,8 @@ class Server:
                 st = torch.empty((n,), dtype=torch.int32, device=self.dev)
                 it = torch.empty((n,), dtype=torch.int32, device=self.dev)
                 S.sgcm_solve_bvps_plan(self.plans[key], x, lam, u0, V, None, st, it, ws, stream)
-                outs = tuple(t.to("cpu", non_blocking=True) for t in (lam, u0, V, st, it))
-                keep = (xh, x, ws, lam, u0, V, st, it)
+                outs = (lam, u0, V, st, it)
+                keep = (xh, x, ws)
             else:
                 itp = self.interp[key[1]]
                 fp32 = key[2]
@@ -257,8 +263,8 @@ class Server:
                 else:
                     uq = torch.empty((n, itp.w64.shape[1]), dtype=torch.float64, device=self.dev)
                     S.sgcm_eval_feedback(itp.grid, itp.w64, x, uq, S.FP64, stream)
-                outs = (uq.to("cpu", non_blocking=True),)
-                keep = (xh, x, uq)
+                outs = (uq,)
+                keep = (xh, x)
             ev = torch.cuda.Event(blocking=True)  # a host wait on it sleeps instead of spinning
             ev.record(stream)
         L = _Launch(reqs, stream, ev, footprint(key, n), outs, work_class(key))
@@ -284,13 +290,26 @@ class Server:
                 r.done = now
                 i += k
 
-    def _wait(self, L: _Launch):
-        """Return in the calling (waiter) thread once the launch has
-        completed.  The event is queried every 50 us: a blocking
-        hipEventSynchronize in the waiter threads delayed the launches the
-        loop issued meanwhile on other streams."""
-        while not L.event.query():
+    @staticmethod
+    def _wait(event):
+        """Return in the calling (waiter) thread once the event has fired.
+        It is queried every 50 us: a blocking hipEventSynchronize in the
+        waiter threads delayed the launches the loop issued meanwhile on
+        other streams."""
+        while not event.query():
             time.sleep(50e-6)
+
+    def _complete(self, L: _Launch):
+        """In the launch's waiter thread: wait for its kernels, then copy its
+        outputs to the host on its own stream (idle by then) and wait for the
+        copies."""
+        import torch
+        self._wait(L.event)
+        with torch.cuda.stream(L.stream):
+            L.outs = tuple(t.to("cpu", non_blocking=True) for t in L.dev_outs)
+            copied = torch.cuda.Event()
+            copied.record(L.stream)
+        self._wait(copied)
 
     def run(self, requests: list, realtime: bool = True) -> dict:
         """Serve the requests (sorted by arrival).  realtime: inject each
@@ -310,7 +329,11 @@ class Server:
                 L = q.get()
                 if L is None:
                     return
-                self._wait(L)
+                try:
+                    self._complete(L)
+                except BaseException as e:  # handed to the loop, which raises it
+                    done.put((L, e))
+                    return
                 done.put((L, time.perf_counter()))
 
         waiters = [threading.Thread(target=wait_stream, args=(todo[id(st)],), daemon=True) for st in self.streams]
@@ -354,6 +377,8 @@ class Server:
                     continue
                 while item is not None:
                     L, t_done = item
+                    if isinstance(t_done, BaseException):
+                        raise t_done
                     self._retire(L, t_done - t0)
                     inflight.remove(L)
                     free.append(L.stream)
