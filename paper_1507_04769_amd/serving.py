@@ -17,9 +17,9 @@ resident on the device, in FP64 or FP32).  The loop
     arriving while others run are admitted as slots and memory free up and
     their work overlaps on the device;
   * caps the streams one class of work may hold at once (two-wheel solves,
-    whose continuation can run for hundreds of Newton iterations, take at
-    most half of them), so that short work (queries, three-wheel solves)
-    always finds a stream instead of queueing behind long launches;
+    whose continuation can run for hundreds of Newton iterations, take all
+    but one), so that short work (queries, three-wheel solves) always finds
+    a stream instead of queueing behind long launches;
   * retires launches as their completion events fire and hands every request
     its slice of the outputs.
 
@@ -219,13 +219,13 @@ class Server:
         plan (each solve launch forms its first Newton steps from its key's
         plan; a missing plan is made at the key's first launch);
         stream_caps: class -> most streams it may hold (default: two-wheel
-        solves at most half of the streams, at least one); size_caps: class
+        solves all streams but one, at least one); size_caps: class
         -> most states of one launch (default: none)."""
         import torch
         self.plans = {} if plans is None else dict(plans)
         self.interp = interpolants
         if stream_caps is None:
-            stream_caps = {"solve-2wheel": max(1, n_streams // 2)}
+            stream_caps = {"solve-2wheel": max(1, n_streams - 1)}
         self.admit = Admission(hbm_budget, max_bvps, max_points, merge, stream_caps=stream_caps,
                                size_caps=size_caps)
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
