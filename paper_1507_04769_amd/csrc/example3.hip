@@ -121,11 +121,18 @@ struct Ex3Args {
 // the interval elements (6 x 7 per interval).
 __host__ __device__ inline int64_t ex3_doubles(int N) {
   const int64_t NP = (int64_t)N + 1;
-  const int64_t d = NP * 6 * 4 + NP * 6 + NP * 36 + (int64_t)N * 24 + (int64_t)N * 42;
+  const int64_t d = NP * 6 * 4 + NP * 6 + NP * 36 + (int64_t)N * 42;
   return (d + 31) / 32 * 32;
 }
 
 constexpr double kSigma = 1e-4;  // sufficient-decrease constant (as the main solver)
+
+// Meshes of up to this many intervals keep the interval elements (and then
+// the forward pass's values, in the same slots) in LDS: 42 N doubles, 21.5 KB
+// at N = 64, so seven BVPs still share a compute unit; the serial Riccati and
+// forward steps then wait on LDS instead of on the memory hierarchy.  Larger
+// meshes keep them in the workspace.
+constexpr int kEx3LdsMaxN = 64;
 
 // Residual F of point Z (N + 1 points of 6) into F; Phi at Z in PH (and the
 // Jacobian blocks in DJ when jac); returns max|F|, or NaN when a value is not
@@ -180,9 +187,14 @@ __device__ double ex3_residual(const Ex3Args& A, double alpha, const double* xba
 }
 
 // The Newton step d solving F'(Z) d = -F (F, PH, DJ at Z), by the backward
-// Riccati sweep and the forward pass; false on a zero pivot.
-__device__ bool ex3_newton_step(const Ex3Args& A, double alpha, const double* DJ, const double* F, double* SW,
-                                double* SWE, double* d) {
+// Riccati sweep and the forward pass; false on a zero pivot.  Interval k's
+// slot of 42 doubles (in LDS with LDSE, else at SWEg) holds its element until
+// the sweep has used it, then the forward pass's values of the interval.
+template <bool LDSE>
+__device__ bool ex3_newton_step(const Ex3Args& A, double alpha, const double* DJ, const double* F, double* SWEg,
+                                double* d) {
+  extern __shared__ double ex3_lds[];
+  double* const SWE = LDSE ? ex3_lds : SWEg;
   const int lane = threadIdx.x, N = A.N;
   bool regular = true;
   // The interval elements do not depend on the Riccati matrix: all of them
@@ -195,16 +207,18 @@ __device__ bool ex3_newton_step(const Ex3Args& A, double alpha, const double* DJ
     const double* J1 = DJ + 36 * k;
     const double* J0 = DJ + 36 * (k - 1);
     const int l = l0 < 13 ? l0 : 12;
+    // every lane loads both Jacobians' column and selects (no divergent
+    // branches, whose loads would each wait in turn): with c = l mod 6,
+    // L_k[:, c] = e_c - alpha J_k[:, c] and R_k[:, c] = e_c + alpha J_{k-1}[:, c]
+    const int c = l < 6 ? l : (l < 12 ? l - 6 : 0);
     double v[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      double x;
-      if (l < 3) x = (i == l ? 1.0 : 0.0) - alpha * J1[i * 6 + l];           // L_k[:, l]
-      else if (l < 6) x = -((i == l ? 1.0 : 0.0) + alpha * J0[i * 6 + l]);  // -R_k[:, l]
-      else if (l < 9) x = (i == l - 6 ? 1.0 : 0.0) + alpha * J0[i * 6 + (l - 6)];  // R_k[:, l-6]
-      else if (l < 12) x = -((i == l - 6 ? 1.0 : 0.0) - alpha * J1[i * 6 + (l - 6)]);  // -L_k[:, l-6]
-      else x = -F[3 + 6 * (k - 1) + i];
-      v[i] = x;
+      const double e = i == c ? 1.0 : 0.0;
+      const double lk = e - alpha * J1[i * 6 + c];
+      const double rk = e + alpha * J0[i * 6 + c];
+      const double fk = -F[3 + 6 * (k - 1) + i];
+      v[i] = l < 3 ? lk : (l < 6 ? -rk : (l < 9 ? rk : (l < 12 ? -lk : fk)));
     }
     regular = gauss_jordan<6, 16>(v) && regular;
     // the element (6 x 7, row-major): the group's lanes 6..8 hold [A; C],
@@ -226,7 +240,7 @@ __device__ bool ex3_newton_step(const Ex3Args& A, double alpha, const double* DJ
   for (int k = N; k >= 1; --k) {
     // element blocks, read where used: A, B (rows 0..2), C, D (rows 3..5),
     // a, c (column 6)
-    const double* E = SWE + 42 * (int64_t)(k - 1);
+    double* E = SWE + 42 * (int64_t)(k - 1);
 #define EA(i, j) E[(i) * 7 + (j)]
 #define EB(i, j) E[(i) * 7 + 3 + (j)]
 #define EC(i, j) E[(3 + (i)) * 7 + (j)]
@@ -268,20 +282,6 @@ __device__ bool ex3_newton_step(const Ex3Args& A, double alpha, const double* DJ
         MA[i * 3 + j] = u;
       }
     }
-    // the forward pass's values of interval k: MA, Mb, P_k, p_k
-    double* sw = SW + 24 * (int64_t)(k - 1);
-    if (lane == 0) {  // the values are the same in every lane
-#pragma unroll
-      for (int e = 0; e < 9; ++e) {
-        sw[e] = MA[e];
-        sw[12 + e] = P[e];
-      }
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        sw[9 + i] = Mb[i];
-        sw[21 + i] = p[i];
-      }
-    }
     // P_{k-1} = C + D P MA,  p_{k-1} = D (P Mb + p) + c
     double DP[9];
 #pragma unroll
@@ -315,6 +315,21 @@ __device__ bool ex3_newton_step(const Ex3Args& A, double alpha, const double* DJ
         Pn[i * 3 + j] = u;
       }
     }
+    // the element is used: the slot takes the forward pass's values of
+    // interval k (MA, Mb, P_k, p_k; the same in every lane)
+    if (lane == 0) {
+      double* sw = E;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) {
+        sw[e] = MA[e];
+        sw[12 + e] = P[e];
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        sw[9 + i] = Mb[i];
+        sw[21 + i] = p[i];
+      }
+    }
 #pragma unroll
     for (int e = 0; e < 9; ++e) P[e] = Pn[e];
 #pragma unroll
@@ -344,7 +359,7 @@ __device__ bool ex3_newton_step(const Ex3Args& A, double alpha, const double* DJ
     }
   }
   for (int k = 1; k <= N; ++k) {
-    const double* sw = SW + 24 * (int64_t)(k - 1);
+    const double* sw = SWE + 42 * (int64_t)(k - 1);
     double nx[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -376,16 +391,16 @@ __device__ bool ex3_newton_step(const Ex3Args& A, double alpha, const double* DJ
 // Newton's iteration on the collocation equations from xbar: from Y = 0 with
 // the first step in full (from_zero), else from Y with its test.  Returns the
 // status and writes the iteration count.
+template <bool LDSE>
 __device__ int ex3_newton(const Ex3Args& A, double alpha, const double* xbar, bool from_zero, double* Y,
-                          double* Yt, double* D, double* F, double* PH, double* DJ, double* SW, double* SWE,
-                          int* iters) {
+                          double* Yt, double* D, double* F, double* PH, double* DJ, double* SWE, int* iters) {
   const int lane = threadIdx.x, NP = A.N + 1;
   *iters = 0;
   if (from_zero) {
     for (int i = lane; i < 6 * NP; i += 64) Y[i] = 0.0;
     wave_mem_sync();
     (void)ex3_residual(A, alpha, xbar, Y, PH, DJ, true, F);
-    if (!ex3_newton_step(A, alpha, DJ, F, SW, SWE, D)) return SGCM_BVP_SINGULAR;
+    if (!ex3_newton_step<LDSE>(A, alpha, DJ, F, SWE, D)) return SGCM_BVP_SINGULAR;
     for (int i = lane; i < 6 * NP; i += 64) Y[i] += D[i];
     wave_mem_sync();
   }
@@ -396,7 +411,7 @@ __device__ int ex3_newton(const Ex3Args& A, double alpha, const double* xbar, bo
     if (fn <= A.tol) return SGCM_BVP_CONVERGED;
     if (it == A.max_iter) return SGCM_BVP_MAXITER;
     (void)ex3_residual(A, alpha, xbar, Y, PH, DJ, true, F);
-    if (!ex3_newton_step(A, alpha, DJ, F, SW, SWE, D)) return SGCM_BVP_SINGULAR;
+    if (!ex3_newton_step<LDSE>(A, alpha, DJ, F, SWE, D)) return SGCM_BVP_SINGULAR;
     double t = 1.0;
     for (int j = 0;; ++j) {
       for (int i = lane; i < 6 * NP; i += 64) Yt[i] = Y[i] + t * D[i];
@@ -411,7 +426,9 @@ __device__ int ex3_newton(const Ex3Args& A, double alpha, const double* xbar, bo
   }
 }
 
-// One BVP per 64-lane workgroup (BVP blockIdx.x).
+// One BVP per 64-lane workgroup (BVP blockIdx.x); with LDSE, 42 N doubles of
+// dynamic LDS (N <= kEx3LdsMaxN).
+template <bool LDSE>
 __global__ __launch_bounds__(64) void k_ex3_newton(Ex3Args A, const double* __restrict__ rows,
                                                    double* __restrict__ lam0, double* __restrict__ u0,
                                                    double* __restrict__ Vout, double* __restrict__ traj,
@@ -426,8 +443,7 @@ __global__ __launch_bounds__(64) void k_ex3_newton(Ex3Args A, const double* __re
   double* F = D + 6 * (int64_t)NP;
   double* PH = F + 6 * (int64_t)NP;
   double* DJ = PH + 6 * (int64_t)NP;
-  double* SW = DJ + 36 * (int64_t)NP;
-  double* SWE = SW + 24 * (int64_t)N;
+  double* SWE = DJ + 36 * (int64_t)NP;
   const int rs = A.tx ? 4 : 3;
   const double t0 = A.tx ? rows[b * rs] : 0.0;
   double xbar[3];
@@ -450,7 +466,7 @@ __global__ __launch_bounds__(64) void k_ex3_newton(Ex3Args A, const double* __re
 #pragma unroll
       for (int i = 0; i < 3; ++i) xk[i] = A.K > 0 ? sk * xbar[i] : xbar[i];
       int its = 0;
-      st = ex3_newton(A, alpha, xk, k == 1, Y, Yt, D, F, PH, DJ, SW, SWE, &its);
+      st = ex3_newton<LDSE>(A, alpha, xk, k == 1, Y, Yt, D, F, PH, DJ, SWE, &its);
       it += its;
       if (st != SGCM_BVP_CONVERGED) break;
     }
@@ -544,8 +560,13 @@ int ex3_solve(const sgcm_problem* p, int64_t n_bvps, const double* rows, int tx,
   if (!rows || !lambda0 || !u0 || !status || !iters || !workspace) return SGCM_EINVAL;
   if (((uintptr_t)workspace & 255u) != 0) return SGCM_EINVAL;
   if (ws_bytes < (size_t)a.per_bvp * sizeof(double) * (size_t)n_bvps) return SGCM_EINVAL;
-  hipLaunchKernelGGL(k_ex3_newton, dim3((unsigned)n_bvps), dim3(64), 0, (hipStream_t)stream, a, rows, lambda0, u0,
-                     V, traj, status, iters, (double*)workspace);
+  if (a.N <= kEx3LdsMaxN) {
+    hipLaunchKernelGGL(k_ex3_newton<true>, dim3((unsigned)n_bvps), dim3(64), (size_t)42 * a.N * sizeof(double),
+                       (hipStream_t)stream, a, rows, lambda0, u0, V, traj, status, iters, (double*)workspace);
+  } else {
+    hipLaunchKernelGGL(k_ex3_newton<false>, dim3((unsigned)n_bvps), dim3(64), 0, (hipStream_t)stream, a, rows,
+                       lambda0, u0, V, traj, status, iters, (double*)workspace);
+  }
   return hipGetLastError() == hipSuccess ? SGCM_OK : SGCM_EDEVICE;
 }
 

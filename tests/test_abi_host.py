@@ -238,11 +238,11 @@ def _ex3(**kw):
 
 def test_example3_validation():
     # Example III (Sec. 5.3): its own workspace (Y, trial point, step and
-    # residual, Phi and its Jacobian per mesh point, 24 sweep values per
-    # interval and its 6 x 7 element, rounded up to 32 doubles), validated
-    # before device work
+    # residual, Phi and its Jacobian per mesh point, and per interval a slot
+    # of 42 doubles for its 6 x 7 element, then its sweep values; rounded up
+    # to 32 doubles), validated before device work
     NP = 65
-    per = (NP * 6 * 4 + NP * 6 + NP * 36 + 64 * 24 + 64 * 42 + 31) // 32 * 32
+    per = (NP * 6 * 4 + NP * 6 + NP * 36 + 64 * 42 + 31) // 32 * 32
     assert _ws(_ex3(), 7) == (S.SGCM_OK, 7 * per * 8)
     assert _ws(_ex3(continuation=2), 1) == (S.SGCM_OK, per * 8)
     for kw in (dict(n=6), dict(m=3), dict(T=0.0), dict(N=0), dict(max_iter=-1), dict(continuation=65)):
