@@ -131,6 +131,17 @@ __device__ __forceinline__ void basis_row(const GridArgs& g, double xi, double (
   }
 }
 
+// t += sum over the first N points of the last dimension of bin[e] w[e]
+// (unrolled: static indices into bin, no predicated iterations past N).
+template <int N, int MC>
+__device__ __forceinline__ void last_dim_sum(const double (&bin)[kMaxPoints], const double* __restrict__ wb, int m,
+                                             double (&t)[MC]) {
+#pragma unroll
+  for (int e = 0; e < N; ++e)
+#pragma unroll
+    for (int c = 0; c < MC; ++c) t[c] = fma(bin[e], wb[(int64_t)e * m + c], t[c]);
+}
+
 // Walk the trie below depth K.  bL: excess budget of the storage layout (the
 // full grid), bE: excess budget of the nodes summed (bE <= bL; a smaller bE
 // evaluates a coarser interpolant I^{q'} with the same surplus table).
@@ -145,12 +156,14 @@ __device__ __forceinline__ void walk(const GridArgs& g, const double* __restrict
     double t[MC];
 #pragma unroll
     for (int c = 0; c < MC; ++c) t[c] = 0.0;
-#pragma unroll
-    for (int e = 0; e < kMaxPoints; ++e) {
-      if (e < cE) {
-#pragma unroll
-        for (int c = 0; c < MC; ++c) t[c] = fma(bin[e], wb[(int64_t)e * m + c], t[c]);
-      }
+    static_assert(kMaxPoints == 33, "the point counts of the levels 0..5");
+    switch (cE) {  // upto(bE): 1, 3, 5, 9, 17 or 33 points
+      case 1: last_dim_sum<1, MC>(bin, wb, m, t); break;
+      case 3: last_dim_sum<3, MC>(bin, wb, m, t); break;
+      case 5: last_dim_sum<5, MC>(bin, wb, m, t); break;
+      case 9: last_dim_sum<9, MC>(bin, wb, m, t); break;
+      case 17: last_dim_sum<17, MC>(bin, wb, m, t); break;
+      default: last_dim_sum<33, MC>(bin, wb, m, t); break;
     }
 #pragma unroll
     for (int c = 0; c < MC; ++c) acc[c] = fma(p, t[c], acc[c]);
