@@ -33,6 +33,7 @@
 #include <cmath>
 
 #include "model.h"
+#include "wave_la.h"
 
 namespace sgcm {
 namespace {
@@ -48,52 +49,26 @@ struct LobShared {
 
 // Gauss-Jordan elimination with row partial pivoting (the first row of
 // largest |a| in the pivot column) of the n x ncols system held in LDS
-// (row-major, stride kLd), lane j owning column j (ncols <= 64).  On return
-// columns n..ncols-1 hold A[:, :n]^{-1} A[:, n:].  Returns false on a zero or
-// non-finite pivot.
-__device__ bool wave_gauss_jordan(double* A, const int n, const int ncols) {
+// (row-major, stride kLd, ncols <= 64): lane j takes column j into
+// registers, the elimination runs there (gauss_jordan: the pivot column
+// broadcast by readlane, no LDS traffic per row), and the columns n..ncols-1
+// go back: A[:, :n]^{-1} A[:, n:].  Returns false on a zero or non-finite
+// pivot.  (Row by row in LDS, the elimination waited on LDS once per row and
+// pivot: about four fifths of the four-point solve.)
+template <int n, int ncols>
+__device__ bool wave_gauss_jordan(double* A) {
+  static_assert(ncols <= 64 && n <= ncols, "one column per lane");
   const int lane = threadIdx.x;
-  bool ok = true;
-  for (int p = 0; p < n; ++p) {
-    double v = -1.0;
-    int idx = 64;
-    if (p + lane < n) {
-      v = fabs(A[(p + lane) * kLd + p]);
-      idx = p + lane;
-    }
+  double v[n];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double v2 = __shfl_xor(v, o);
-      const int i2 = __shfl_xor(idx, o);
-      if (v2 > v || (v2 == v && i2 < idx)) {
-        v = v2;
-        idx = i2;
-      }
-    }
-    const int piv = __builtin_amdgcn_readfirstlane(idx);
-    if (!(v > 0.0) || !isfinite(v)) ok = false;
-    if (piv != p && lane >= p && lane < ncols) {
-      const double t = A[p * kLd + lane];
-      A[p * kLd + lane] = A[piv * kLd + lane];
-      A[piv * kLd + lane] = t;
-    }
-    lds_handoff();
-    // every other row minus its multiple of the pivot row, in the columns
-    // right of the pivot (column p keeps the multipliers' numerators)
-    if (lane > p && lane < ncols) {
-      const double rp = 1.0 / A[p * kLd + p];
-      const double apj = A[p * kLd + lane];
-      for (int r = 0; r < n; ++r) {
-        if (r == p) continue;
-        A[r * kLd + lane] = fma(-A[r * kLd + p] * rp, apj, A[r * kLd + lane]);
-      }
-    }
-    lds_handoff();
+  for (int i = 0; i < n; ++i) v[i] = lane < ncols ? A[i * kLd + lane] : 0.0;
+  const bool ok = gauss_jordan<n, 64, true>(v);
+  if (lane >= n && lane < ncols) {
+#pragma unroll
+    for (int i = 0; i < n; ++i) A[i * kLd + lane] = v[i];
   }
-  if (lane >= n && lane < ncols)
-    for (int r = 0; r < n; ++r) A[r * kLd + lane] = A[r * kLd + lane] / A[r * kLd + r];
   lds_handoff();
-  return __builtin_amdgcn_readfirstlane((int)ok) != 0;
+  return ok;
 }
 
 // Entry (r, c) of the 12 x 12 Jacobian of Phi from A and W of point_eval:
@@ -295,25 +270,24 @@ __global__ __launch_bounds__(64) void k_lobatto(BvpArgs P, const double* __restr
       const double* J0 = Jp + 144 * (3 * (int64_t)k);
       const double* Fk = F + 6 + 36 * (int64_t)k;
       // [M | B1 | B4 | -F_{1,2}], 24 x 49: stage rows i = 1, 2
+      // one load and one fma per entry in every lane (no divergent branches,
+      // whose loads would each wait in turn): entry = ident + coef J0[off],
+      // with ident -0 where there is none (so that it adds nothing, sign of
+      // zero included), or -F in the last column
       for (int e = lane; e < 24 * 49; e += 64) {
         const int r = e / 49, c = e - 49 * r;
         const int i = 1 + r / 12, rr = r % 12;
-        double v;
-        if (c < 24) {
-          const int jj = 1 + c / 12, cc = c % 12;
-          v = (r == c ? 1.0 : 0.0) - h * P.lob[i][jj] * J0[144 * jj + rr * 12 + cc];
-        } else if (c < 36) {
-          const int cc = c - 24;
-          v = (rr == cc ? 1.0 : 0.0) + h * P.lob[i][0] * J0[rr * 12 + cc];
-        } else if (c < 48) {
-          v = h * P.lob[i][3] * J0[144 * 3 + rr * 12 + (c - 36)];
-        } else {
-          v = -Fk[12 * (i - 1) + rr];
-        }
-        sh.A[r * kLd + c] = v;
+        const int jj = c < 24 ? 1 + c / 12 : (c < 36 ? 0 : 3);  // stage of the Jacobian block
+        const int cc = c < 24 ? c % 12 : (c < 36 ? c - 24 : (c < 48 ? c - 36 : 0));
+        const double t = h * P.lob[i][jj];
+        const double coef = c < 24 ? -t : t;
+        const double ident = c < 24 ? (r == c ? 1.0 : 0.0) : (c < 36 ? (rr == cc ? 1.0 : 0.0) : -0.0);
+        const double x = fma(coef, J0[144 * jj + rr * 12 + cc], ident);
+        const double f = -Fk[12 * (i - 1) + rr];
+        sh.A[r * kLd + c] = c < 48 ? x : f;
       }
       lds_handoff();
-      regular = wave_gauss_jordan(sh.A, 24, 49);
+      regular = wave_gauss_jordan<24, 49>(sh.A);
       double* Xk = Xg + 600 * (int64_t)k;
       for (int e = lane; e < 600; e += 64) Xk[e] = sh.A[(e / 25) * kLd + 24 + e % 25];
       // T = h [a_31 Phi'_1 | a_32 Phi'_2] (12 x 24);
@@ -324,12 +298,15 @@ __global__ __launch_bounds__(64) void k_lobatto(BvpArgs P, const double* __restr
         double s = 0.0;
         for (int q = 0; q < 24; ++q)
           s = fma(h * P.lob[3][1 + q / 12] * J0[144 * (1 + q / 12) + r * 12 + q % 12], sh.A[q * kLd + 24 + col], s);
-        if (col < 12)
-          Ck[r * 12 + col] = -((r == col ? 1.0 : 0.0) + h * P.lob[3][0] * J0[r * 12 + col] + s);
-        else if (col < 24)
-          Ck[144 + r * 12 + col - 12] = (r == col - 12 ? 1.0 : 0.0) - h * P.lob[3][3] * J0[144 * 3 + r * 12 + col - 12] - s;
-        else
-          Ck[288 + r] = -Fk[24 + r] + s;
+        // the three kinds of entry from one selected load (no divergent branches)
+        const bool cl = col < 12, dl = !cl && col < 24;
+        const int cj = cl ? col : (dl ? col - 12 : 0);
+        const double jv = J0[(cl ? 0 : 144 * 3) + r * 12 + cj];
+        const double id = r == cj ? 1.0 : 0.0;
+        const double cv = -(id + h * P.lob[3][0] * jv + s);
+        const double dv = id - h * P.lob[3][3] * jv - s;
+        const double ev = -Fk[24 + r] + s;
+        Ck[cl ? r * 12 + col : (dl ? 144 + r * 12 + col - 12 : 288 + r)] = cl ? cv : (dl ? dv : ev);
       }
       wave_mem_sync();
       lds_handoff();
@@ -343,24 +320,26 @@ __global__ __launch_bounds__(64) void k_lobatto(BvpArgs P, const double* __restr
       const double* Dk = Ck + 144;
       const double* ek = Ck + 288;
       // [Dx + Dl P | Cl | -Cx | e - Dl c], 12 x 19
+      // one selected load per entry, and one shared sum for the columns
+      // that have one (0..5: + Dl P, 18: - Dl c); no four-way branch, whose
+      // loads would each wait in turn
       for (int e = lane; e < 12 * 19; e += 64) {
         const int r = e / 19, col = e - 19 * r;
-        double v;
-        if (col < 6) {
-          v = Dk[r * 12 + col];
-          for (int m = 0; m < 6; ++m) v = fma(Dk[r * 12 + 6 + m], sh.P[m * 6 + col], v);
-        } else if (col < 12) {
-          v = Ck[r * 12 + col];
-        } else if (col < 18) {
-          v = -Ck[r * 12 + col - 12];
-        } else {
-          v = ek[r];
-          for (int m = 0; m < 6; ++m) v = fma(-Dk[r * 12 + 6 + m], sh.c[m], v);
+        const bool px = col < 6, ce = col >= 18;
+        const int off = px ? 144 + r * 12 + col : (col < 12 ? r * 12 + col : (col < 18 ? r * 12 + col - 12 : 288 + r));
+        const double b0 = Ck[off];
+        double v = (col >= 12 && col < 18) ? -b0 : b0;
+        if (px || ce) {
+#pragma unroll
+          for (int m = 0; m < 6; ++m) {
+            const double dm = Dk[r * 12 + 6 + m];
+            v = px ? fma(dm, sh.P[m * 6 + col], v) : fma(-dm, sh.c[m], v);
+          }
         }
         sh.A[r * kLd + col] = v;
       }
       lds_handoff();
-      regular = wave_gauss_jordan(sh.A, 12, 19);
+      regular = wave_gauss_jordan<12, 19>(sh.A);
       // rows 0..5: [G g] (dx_{k+1} = G dx_k + g); rows 6..11: [P c] at k
       double* Zk = Zs + 84 * (int64_t)k;
       for (int e = lane; e < 84; e += 64) Zk[e] = sh.A[(e / 7) * kLd + 12 + e % 7];

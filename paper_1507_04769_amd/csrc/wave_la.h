@@ -23,8 +23,9 @@ __device__ __forceinline__ double bcast(double x, int from) {
 // W < 64 every group of W consecutive lanes eliminates a matrix of its own
 // (column l in the group's lane l; the pivot column is then read with a lane
 // permute instead of readlane).  Returns false when a pivot was exactly zero
-// (the values are then not finite).
-template <int n, int W = 64>
+// (the values are then not finite), and with FINITE also when a pivot was not
+// finite.
+template <int n, int W = 64, bool FINITE = false>
 __device__ __forceinline__ bool gauss_jordan(double (&v)[n]) {
   bool regular = true;
 #pragma unroll
@@ -53,7 +54,7 @@ __device__ __forceinline__ bool gauss_jordan(double (&v)[n]) {
         col[i] = cc;
         v[i] = vc;
       }
-    regular = regular && cp != 0.0;
+    regular = regular && cp != 0.0 && (!FINITE || isfinite(cp));
     const double nv = vp * (1.0 / cp);
 #pragma unroll
     for (int i = 0; i < n; ++i)
