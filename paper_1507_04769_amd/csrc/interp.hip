@@ -243,6 +243,132 @@ __global__ __launch_bounds__(64) void k_surplus_level(GridArgs g, const double* 
   }
 }
 
+// ---- the generic walk split over the wavefronts of a workgroup -----------------
+//
+// The generic kernels keep (d - 1) * 33 basis values per lane in LDS (50 KB per
+// wavefront at d = 4), so a one-wavefront workgroup leaves a compute unit
+// three wavefronts, each walking its whole trie alone.  Here kGenWaves
+// wavefronts share one copy of the tables of their 64 points and split the
+// walk's outermost loop (the points e0 of dimension 0) into contiguous
+// blocks (gen_bounds); the block sums are added from zero in wavefront order.
+
+constexpr int kGenWaves = 4;
+
+// The rows of dimensions 0..D-2 into the group's LDS (dimension k by
+// wavefront k mod kGenWaves), the last one into bin (every wavefront); ends
+// with a barrier.
+template <int D>
+__device__ __forceinline__ void gen_tables(const GridArgs& g, const double (&xi)[D], int wave, double* lds_lane,
+                                           double (&bin)[kMaxPoints]) {
+  double row[kMaxPoints];
+#pragma unroll
+  for (int k = 0; k < D - 1; ++k) {
+    if (k % kGenWaves == wave) {
+      basis_row(g, xi[k], row);
+#pragma unroll
+      for (int e = 0; e < kMaxPoints; ++e)
+        if (e < g.P) lds_lane[(k * g.P + e) * 64] = row[e];
+    }
+  }
+  basis_row(g, xi[D - 1], bin);
+  __syncthreads();
+}
+
+// walk<0, D, MC> restricted to the points e0 in [e_lo, e_hi) of dimension 0.
+template <int D, int MC>
+__device__ __forceinline__ void walk0_range(const GridArgs& g, const double* __restrict__ w, int m, int col0,
+                                            int bL, int bE, int e_lo, int e_hi, double (&acc)[MC],
+                                            const double (&bin)[kMaxPoints], const double* lds_lane) {
+  static_assert(D >= 2, "the split walks the first of at least two dimensions");
+  const int cE = upto(bE);
+  const int hi = e_hi < cE ? e_hi : cE;
+  const int32_t* offrow = g.off + ((D - 1) * (g.L + 1) + bL) * g.P;
+  for (int e = e_lo; e < hi; ++e) {
+    const int ex = g.excess[e];
+    walk<1, D, MC>(g, w, m, col0, bL - ex, bE - ex, offrow[e], lds_lane[e * 64], acc, bin, lds_lane);
+  }
+}
+
+// The block sums (this wavefront's in acc) added from zero in wavefront order
+// by wavefront 0 (into its acc).
+template <int MC>
+__device__ __forceinline__ void gen_reduce(double* part, int wave, int lane, double (&acc)[MC]) {
+#pragma unroll
+  for (int c = 0; c < MC; ++c) part[(wave * 64 + lane) * MC + c] = acc[c];
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int c = 0; c < MC; ++c) {
+      double t = 0.0;
+#pragma unroll
+      for (int r = 0; r < kGenWaves; ++r) t += part[(r * 64 + lane) * MC + c];
+      acc[c] = t;
+    }
+  }
+}
+
+// Wavefront s walks the points e0 from byte s - 1 of bounds (0 for s = 0) up
+// to byte s (0xff: to the end).
+__device__ __forceinline__ int gen_lo(uint32_t bounds, int s) {
+  return s == 0 ? 0 : (int)((bounds >> (8 * (s - 1))) & 0xffu);
+}
+__device__ __forceinline__ int gen_hi(uint32_t bounds, int s) { return (int)((bounds >> (8 * s)) & 0xffu); }
+
+template <int D, int MC>
+__global__ __launch_bounds__(64 * kGenWaves) void k_eval_gs(GridArgs g, const double* __restrict__ w, int m,
+                                                            int col0, int64_t nq, const double* __restrict__ xq,
+                                                            double* __restrict__ uq, uint32_t bounds) {
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+  const bool active = q < nq;
+  double xi[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) xi[k] = active ? (xq[q * D + k] - g.lo[k]) * g.inv_width[k] : 0.5;
+  double bin[kMaxPoints];
+  double* lds_lane = lds + lane;
+  gen_tables<D>(g, xi, wave, lds_lane, bin);
+  double acc[MC];
+#pragma unroll
+  for (int c = 0; c < MC; ++c) acc[c] = 0.0;
+  walk0_range<D, MC>(g, w, m, col0, g.L, g.L, gen_lo(bounds, wave), gen_hi(bounds, wave), acc, bin, lds_lane);
+  gen_reduce<MC>(lds + (D - 1) * g.P * 64, wave, lane, acc);
+  if (wave == 0 && active) {
+#pragma unroll
+    for (int c = 0; c < MC; ++c) uq[q * m + col0 + c] = acc[c];
+  }
+}
+
+template <int D, int MC>
+__global__ __launch_bounds__(64 * kGenWaves) void k_surplus_level_gs(GridArgs g, const double* __restrict__ f,
+                                                                     double* w, int m, int col0, int lv,
+                                                                     const int32_t* __restrict__ nodes,
+                                                                     int64_t count,
+                                                                     const double* __restrict__ node_xi,
+                                                                     uint32_t bounds) {
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const bool active = i < count;
+  const int64_t node = active ? nodes[i] : 0;
+  double xi[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) xi[k] = node_xi[node * D + k];
+  double bin[kMaxPoints];
+  double* lds_lane = lds + lane;
+  gen_tables<D>(g, xi, wave, lds_lane, bin);
+  double acc[MC];
+#pragma unroll
+  for (int c = 0; c < MC; ++c) acc[c] = 0.0;
+  if (lv > 0)
+    walk0_range<D, MC>(g, w, m, col0, g.L, lv - 1, gen_lo(bounds, wave), gen_hi(bounds, wave), acc, bin, lds_lane);
+  gen_reduce<MC>(lds + (D - 1) * g.P * 64, wave, lane, acc);
+  if (wave == 0 && active) {
+#pragma unroll
+    for (int c = 0; c < MC; ++c) w[node * m + col0 + c] = f[node * m + col0 + c] - acc[c];
+  }
+}
+
 // ---- evaluation with the inner trie unrolled at compile time -----------------
 //
 // For a fixed (d, level, m) the trie below any prefix of the outer dimensions
@@ -781,9 +907,59 @@ GridArgs make_args(const Grid& G, const GridDevice& gd) {
 
 size_t lds_bytes(const Grid& G) { return (size_t)(G.d - 1) * G.P * 64 * sizeof(double); }
 
+// The blocks of the points e0 of dimension 0 for the kGenWaves wavefronts of
+// a split walk of budget bE in d dimensions (packed as gen_lo / gen_hi read
+// them): contiguous, the largest block's subtree nodes as few as possible
+// (the first such partition found), trailing blocks empty when there are
+// fewer points than wavefronts.
+uint32_t gen_bounds(int d, int bE) {
+  const int n = upto(bE < 0 ? 0 : bE);
+  std::vector<int64_t> pre(n + 1, 0);
+  for (int e = 0; e < n; ++e) pre[e + 1] = pre[e] + subgrid(d - 1, bE - excess_of(e));
+  const int S = kGenWaves;
+  // best[k][i]: smallest largest block of points i..n-1 in k non-empty blocks
+  const int64_t inf = INT64_MAX;
+  std::vector<std::vector<int64_t>> best(S + 1, std::vector<int64_t>(n + 1, inf));
+  std::vector<std::vector<int>> cut(S + 1, std::vector<int>(n + 1, n));
+  for (int i = 0; i < n; ++i) best[1][i] = pre[n] - pre[i];
+  for (int k = 2; k <= S; ++k)
+    for (int i = 0; i + k <= n; ++i)
+      for (int j = i + 1; j + k - 1 <= n; ++j) {
+        const int64_t v = std::max(pre[j] - pre[i], best[k - 1][j]);
+        if (v < best[k][i]) {
+          best[k][i] = v;
+          cut[k][i] = j;
+        }
+      }
+  int kb = 1;
+  for (int k = 2; k <= S && k <= n; ++k)
+    if (best[k][0] < best[kb][0]) kb = k;
+  uint32_t packed = 0;
+  int i = 0;
+  for (int s = 0; s < S - 1; ++s) {
+    const int k = kb - s;  // blocks left, this one included
+    const int end = k >= 2 ? cut[k][i] : n;
+    packed |= (uint32_t)(s < kb ? end : n) << (8 * s);
+    if (s < kb) i = end;
+  }
+  return packed | (0xffu << (8 * (S - 1)));
+}
+
 template <int D, int MC>
 hipError_t launch_eval(const GridArgs& a, size_t lds, const double* w, int m, int col0, int64_t nq,
                        const double* xq, double* uq, hipStream_t s) {
+  if constexpr (D >= 2) {
+    auto kern = k_eval_gs<D, MC>;
+    const size_t lds_s = lds + (size_t)kGenWaves * 64 * MC * sizeof(double);
+    if (lds_s > 65536) {
+      hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds_s);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)((nq + 63) / 64)), dim3(64 * kGenWaves), lds_s, s, a, w, m, col0, nq,
+                       xq, uq, gen_bounds(D, a.L));
+    return hipGetLastError();
+  }
   auto kern = k_eval<D, MC>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -799,6 +975,18 @@ template <int D, int MC>
 hipError_t launch_level(const GridArgs& a, size_t lds, const double* f, double* w, int m, int col0,
                         int lv, const int32_t* nodes, int64_t count, const double* node_xi,
                         hipStream_t s) {
+  if constexpr (D >= 2) {
+    auto kern = k_surplus_level_gs<D, MC>;
+    const size_t lds_s = lds + (size_t)kGenWaves * 64 * MC * sizeof(double);
+    if (lds_s > 65536) {
+      hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds_s);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)((count + 63) / 64)), dim3(64 * kGenWaves), lds_s, s, a, f, w, m,
+                       col0, lv, nodes, count, node_xi, gen_bounds(D, lv - 1));
+    return hipGetLastError();
+  }
   auto kern = k_surplus_level<D, MC>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
