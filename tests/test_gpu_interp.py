@@ -132,6 +132,28 @@ def test_eval_deterministic():
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("d,level,m", [(4, 5, 1), (6, 3, 5), (2, 5, 3)])
+def test_generic_eval_independent_of_the_launch(d, level, m):
+    # the generic walk splits each group's walk over four wavefronts and adds
+    # their sums in a fixed order: a point's value has the same bits in any
+    # launch (whole, reversed, a prefix, a window) and matches the oracle
+    torch = _torch()
+    lo, hi = box(d)
+    g = S.Grid(d, level, lo, hi)
+    f = np.random.default_rng(40 + d).standard_normal((len(g), m))
+    w = S.build_interpolant(g, dev(f))
+    xq = np.random.default_rng(41 + d).uniform(lo, hi, size=(3001, d))
+    a = S.eval_feedback(g, w, dev(xq)).cpu().numpy()
+    b = S.eval_feedback(g, w, dev(xq[::-1])).cpu().numpy()[::-1]
+    c = S.eval_feedback(g, w, dev(xq[:70])).cpu().numpy()
+    e = S.eval_feedback(g, w, dev(xq[1000:1129])).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(a, b) and np.array_equal(a[:70], c) and np.array_equal(a[1000:1129], e)
+    w_ref = O.build_surplus(d, level, f)
+    ref = O.eval_hier(d, level, w_ref, xq[:200], lo, hi)
+    assert np.max(np.abs(a[:200] - ref)) <= REL * np.abs(ref).max()
+
+
 def test_build_and_eval_need_uploaded_tables():
     # sgcm_build_interpolant and sgcm_eval_feedback(_f32) allocate nothing:
     # on a grid whose tables are not on the device they refuse the call, and
