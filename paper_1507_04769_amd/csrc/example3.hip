@@ -117,8 +117,8 @@ struct Ex3Args {
 
 // Workspace of one BVP, in doubles: Y, the trial point, the Newton step and
 // the residual ((N + 1) x 6 each), Phi and its Jacobian at the mesh points
-// ((N + 1) x 6 and (N + 1) x 36), the sweep's 24 values per interval and
-// the interval elements (6 x 7 per interval).
+// ((N + 1) x 6 and (N + 1) x 36), and per interval a slot of 42 doubles (its
+// 6 x 7 element, then its sweep values).
 __host__ __device__ inline int64_t ex3_doubles(int N) {
   const int64_t NP = (int64_t)N + 1;
   const int64_t d = NP * 6 * 4 + NP * 6 + NP * 36 + (int64_t)N * 42;
@@ -133,6 +133,57 @@ constexpr double kSigma = 1e-4;  // sufficient-decrease constant (as the main so
 // forward steps then wait on LDS instead of on the memory hierarchy.  Larger
 // meshes keep them in the workspace.
 constexpr int kEx3LdsMaxN = 64;
+
+// Launches of up to this many BVPs run them in decreasing order of |x0|_1
+// (k_ex3_order; the order, n int32, behind the BVP workspaces): a BVP from
+// the zero state converges at once, so the nontrivial ones come first and
+// take the first wavefront slots (on the level-5 grid in (t, x), 552 of 1105
+// BVPs, against 1024 SIMDs), instead of sharing a SIMD with a neighbour in
+// the grid's order.
+constexpr int kEx3OrderMax = 8192;
+
+size_t ex3_order_bytes(int64_t n) { return n <= kEx3OrderMax ? ((size_t)n * 4 + 255) / 256 * 256 : 0; }
+
+// The launch order: a bucket sort of |x0|_1 (largest first; 256 buckets over
+// [0, max]) in one workgroup.  rows: n rows of rs doubles, x0 from column c0.
+__global__ __launch_bounds__(1024) void k_ex3_order(const double* __restrict__ rows, int rs, int c0, int n,
+                                                    int32_t* __restrict__ order) {
+  __shared__ float key[kEx3OrderMax];
+  __shared__ float wmax[16];
+  __shared__ int32_t cnt[256];
+  const int t = threadIdx.x;
+  float m = 0.0f;
+  for (int i = t; i < n; i += 1024) {
+    double a = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) a += fabs(rows[(int64_t)i * rs + c0 + j]);
+    const float f = (float)a;
+    key[i] = isfinite(f) ? f : 0.0f;
+    m = fmaxf(m, key[i]);
+  }
+  if (t < 256) cnt[t] = 0;
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d));
+  if ((t & 63) == 0) wmax[t >> 6] = m;
+  __syncthreads();
+  float kmax = 0.0f;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) kmax = fmaxf(kmax, wmax[w]);
+  const float scale = kmax > 0.0f ? 255.5f / kmax : 0.0f;
+  auto bucket = [&](int i) { return 255 - min(255, (int)(key[i] * scale)); };
+  for (int i = t; i < n; i += 1024) atomicAdd(&cnt[bucket(i)], 1);
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int b = 0; b < 256; ++b) {
+      const int c = cnt[b];
+      cnt[b] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < n; i += 1024) order[atomicAdd(&cnt[bucket(i)], 1)] = i;
+}
 
 // Residual F of point Z (N + 1 points of 6) into F; Phi at Z in PH (and the
 // Jacobian blocks in DJ when jac); returns max|F|, or NaN when a value is not
@@ -426,16 +477,16 @@ __device__ int ex3_newton(const Ex3Args& A, double alpha, const double* xbar, bo
   }
 }
 
-// One BVP per 64-lane workgroup (BVP blockIdx.x); with LDSE, 42 N doubles of
-// dynamic LDS (N <= kEx3LdsMaxN).
+// One BVP per 64-lane workgroup (BVP order[blockIdx.x], or blockIdx.x without
+// an order); with LDSE, 42 N doubles of dynamic LDS (N <= kEx3LdsMaxN).
 template <bool LDSE>
 __global__ __launch_bounds__(64) void k_ex3_newton(Ex3Args A, const double* __restrict__ rows,
                                                    double* __restrict__ lam0, double* __restrict__ u0,
                                                    double* __restrict__ Vout, double* __restrict__ traj,
                                                    int32_t* __restrict__ status, int32_t* __restrict__ iters,
-                                                   double* __restrict__ ws) {
+                                                   double* __restrict__ ws, const int32_t* __restrict__ order) {
   const int lane = threadIdx.x;
-  const int64_t b = blockIdx.x;
+  const int64_t b = order ? order[blockIdx.x] : blockIdx.x;
   const int N = A.N, NP = N + 1;
   double* Y = ws + b * A.per_bvp;
   double* Yt = Y + 6 * (int64_t)NP;
@@ -543,7 +594,7 @@ int ex3_workspace(const sgcm_problem* p, int64_t n_bvps, size_t* bytes) {
   if (!bytes || n_bvps < 0) return SGCM_EINVAL;
   const int rc = ex3_args(p, &a);
   if (rc != SGCM_OK) return rc;
-  *bytes = (size_t)a.per_bvp * sizeof(double) * (size_t)n_bvps;
+  *bytes = (size_t)a.per_bvp * sizeof(double) * (size_t)n_bvps + ex3_order_bytes(n_bvps);
   return SGCM_OK;
 }
 
@@ -559,13 +610,20 @@ int ex3_solve(const sgcm_problem* p, int64_t n_bvps, const double* rows, int tx,
   if (n_bvps > 0x7fffffffLL) return SGCM_EUNSUPPORTED;
   if (!rows || !lambda0 || !u0 || !status || !iters || !workspace) return SGCM_EINVAL;
   if (((uintptr_t)workspace & 255u) != 0) return SGCM_EINVAL;
-  if (ws_bytes < (size_t)a.per_bvp * sizeof(double) * (size_t)n_bvps) return SGCM_EINVAL;
+  const size_t bvp_bytes = (size_t)a.per_bvp * sizeof(double) * (size_t)n_bvps;
+  if (ws_bytes < bvp_bytes + ex3_order_bytes(n_bvps)) return SGCM_EINVAL;
+  int32_t* order = nullptr;
+  if (n_bvps <= kEx3OrderMax) {
+    order = reinterpret_cast<int32_t*>(static_cast<char*>(workspace) + bvp_bytes);
+    hipLaunchKernelGGL(k_ex3_order, dim3(1), dim3(1024), 0, (hipStream_t)stream, rows, tx ? 4 : 3, tx ? 1 : 0,
+                       (int)n_bvps, order);
+  }
   if (a.N <= kEx3LdsMaxN) {
     hipLaunchKernelGGL(k_ex3_newton<true>, dim3((unsigned)n_bvps), dim3(64), (size_t)42 * a.N * sizeof(double),
-                       (hipStream_t)stream, a, rows, lambda0, u0, V, traj, status, iters, (double*)workspace);
+                       (hipStream_t)stream, a, rows, lambda0, u0, V, traj, status, iters, (double*)workspace, order);
   } else {
     hipLaunchKernelGGL(k_ex3_newton<false>, dim3((unsigned)n_bvps), dim3(64), 0, (hipStream_t)stream, a, rows,
-                       lambda0, u0, V, traj, status, iters, (double*)workspace);
+                       lambda0, u0, V, traj, status, iters, (double*)workspace, order);
   }
   return hipGetLastError() == hipSuccess ? SGCM_OK : SGCM_EDEVICE;
 }

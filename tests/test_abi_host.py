@@ -243,8 +243,10 @@ def test_example3_validation():
     # to 32 doubles), validated before device work
     NP = 65
     per = (NP * 6 * 4 + NP * 6 + NP * 36 + 64 * 42 + 31) // 32 * 32
-    assert _ws(_ex3(), 7) == (S.SGCM_OK, 7 * per * 8)
-    assert _ws(_ex3(continuation=2), 1) == (S.SGCM_OK, per * 8)
+    # plus the launch order (int32 per BVP, rounded up to 256 bytes)
+    assert _ws(_ex3(), 7) == (S.SGCM_OK, 7 * per * 8 + 256)
+    assert _ws(_ex3(continuation=2), 1) == (S.SGCM_OK, per * 8 + 256)
+    assert _ws(_ex3(), 8193) == (S.SGCM_OK, 8193 * per * 8)  # above 8192 BVPs: no order
     for kw in (dict(n=6), dict(m=3), dict(T=0.0), dict(N=0), dict(max_iter=-1), dict(continuation=65)):
         assert _ws(_ex3(**kw), 1)[0] == S.SGCM_EINVAL, kw
     for kw in (dict(precision=S.FP32), dict(scheme=S.LOBATTO4)):
