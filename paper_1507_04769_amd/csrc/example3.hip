@@ -253,22 +253,36 @@ __device__ bool ex3_newton_step(const Ex3Args& A, double alpha, const double* DJ
   // k's augmented matrix [Q | R_x | -L_lambda | -r], L = I - alpha J_k,
   // R = I + alpha J_{k-1}: column l in the group's lane l (l < 13).
   const int grp = lane >> 4, l0 = lane & 15;
-  for (int kb = 1; kb <= N; kb += 4) {
+  const int l = l0 < 13 ? l0 : 12;
+  // every lane loads both Jacobians' column and selects (no divergent
+  // branches, whose loads would each wait in turn): with c = l mod 6,
+  // L_k[:, c] = e_c - alpha J_k[:, c] and R_k[:, c] = e_c + alpha J_{k-1}[:, c];
+  // the next round's values are loaded while this round is eliminated
+  const int c = l < 6 ? l : (l < 12 ? l - 6 : 0);
+  auto fetch = [&](int kb, double (&j1)[6], double (&j0)[6], double (&fr)[6]) {
     const int k = kb + grp <= N ? kb + grp : N;  // groups past N repeat interval N
     const double* J1 = DJ + 36 * k;
     const double* J0 = DJ + 36 * (k - 1);
-    const int l = l0 < 13 ? l0 : 12;
-    // every lane loads both Jacobians' column and selects (no divergent
-    // branches, whose loads would each wait in turn): with c = l mod 6,
-    // L_k[:, c] = e_c - alpha J_k[:, c] and R_k[:, c] = e_c + alpha J_{k-1}[:, c]
-    const int c = l < 6 ? l : (l < 12 ? l - 6 : 0);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      j1[i] = J1[i * 6 + c];
+      j0[i] = J0[i * 6 + c];
+      fr[i] = F[3 + 6 * (k - 1) + i];
+    }
+  };
+  double cj1[6], cj0[6], cfr[6];
+  fetch(1, cj1, cj0, cfr);
+  for (int kb = 1; kb <= N; kb += 4) {
+    const int k = kb + grp <= N ? kb + grp : N;
+    double nj1[6], nj0[6], nfr[6];
+    if (kb + 4 <= N) fetch(kb + 4, nj1, nj0, nfr);
     double v[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
       const double e = i == c ? 1.0 : 0.0;
-      const double lk = e - alpha * J1[i * 6 + c];
-      const double rk = e + alpha * J0[i * 6 + c];
-      const double fk = -F[3 + 6 * (k - 1) + i];
+      const double lk = e - alpha * cj1[i];
+      const double rk = e + alpha * cj0[i];
+      const double fk = -cfr[i];
       v[i] = l < 3 ? lk : (l < 6 ? -rk : (l < 9 ? rk : (l < 12 ? -lk : fk)));
     }
     regular = gauss_jordan<6, 16>(v) && regular;
@@ -278,6 +292,14 @@ __device__ bool ex3_newton_step(const Ex3Args& A, double alpha, const double* DJ
       double* E = SWE + 42 * (int64_t)(k - 1);
 #pragma unroll
       for (int i = 0; i < 6; ++i) E[i * 7 + (l0 - 6)] = v[i];
+    }
+    if (kb + 4 <= N) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        cj1[i] = nj1[i];
+        cj0[i] = nj0[i];
+        cfr[i] = nfr[i];
+      }
     }
   }
   wave_mem_sync();
